@@ -1,0 +1,157 @@
+/*
+ * cr.h -- C ABI of libcr: persistent homology over Z/2 of the weighted cubical
+ * complex (V-construction) of 2D images and 3D volumes on one AMD MI355X.
+ *
+ * The problem is the one Kaji, Sudo and Ahara state for Cubical Ripser
+ * (arXiv:2005.12692): an image is a real function on a regular grid (Sec. 2);
+ * its cubical complex has the cells of the grid, each valued by the maximum of
+ * its vertices (Sec. 2); the result is a set of bars [birth, death) of
+ * dimension 0, 1 or 2, with infinite bars marked (Sec. 1).  Connectivity is 4-
+ * (2D) or 6-neighbour (3D) (Sec. 2).  Coefficients are Z/2.
+ *
+ * Conventions for every call:
+ *  - Arrays are C order; x (the last axis) is the fastest ("the cell to the
+ *    right is (1,0,0)", Fig. 1).  A pixel index is a flat index into the input
+ *    buffer passed to the call.
+ *  - Values are float32.  -0.0 is read as +0.0.  NaN is an error
+ *    (CR_ERR_NAN_INPUT).  +inf and -inf are ordinary values; +inf marks pixels
+ *    outside a non-rectangular domain (Sec. 2).
+ *  - Only bars of positive length are reported (zero-length pairs are not).  An
+ *    essential bar has death = +INFINITY and death_pixel = -1; a full grid has
+ *    exactly one, in dimension 0, born at the global minimum.
+ *  - birth == image[birth_pixel] and death == image[death_pixel] bit for bit:
+ *    the pixel of a cell is its vertex of largest value, ties broken towards
+ *    the larger flat index (the paper's "location" of a cycle is "a
+ *    representative", Example 4.6; this fixes one).
+ *  - Rows of one image are in canonical order: ascending (dim, birth_pixel,
+ *    death_pixel), an essential bar after every finite one.  Two runs on the
+ *    same input give identical bytes.
+ *  - Device pointers are HIP device memory of the context's device; "stream"
+ *    is a hipStream_t (NULL = the default stream).  All device work is enqueued
+ *    on that stream.
+ *  - Every entry point returns a cr_status; on failure no output is written or
+ *    allocated and cr_last_error() describes the cause.  No C++ exception
+ *    crosses this boundary.  A context is not thread-safe: use one per host
+ *    thread.
+ */
+#ifndef CR_H
+#define CR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cr_status {
+  CR_OK = 0,
+  CR_ERR_INVALID_ARGUMENT = 1, /* null pointer, bad ndim/shape, maxdim < 0, ... */
+  CR_ERR_NAN_INPUT = 2,        /* a pixel is NaN */
+  CR_ERR_TOO_LARGE = 3,        /* the cell index or key layout would overflow */
+  CR_ERR_CAPACITY = 4,         /* a caller-provided buffer is too small */
+  CR_ERR_OUT_OF_MEMORY = 5,    /* device or host allocation failed */
+  CR_ERR_HIP = 6,              /* a HIP runtime call failed */
+  CR_ERR_INTERNAL = 7          /* an internal consistency check failed */
+} cr_status;
+
+typedef struct cr_context cr_context;
+
+/* Optional allocator for the plain call's output block (e.g. a framework's
+ * caching allocator).  alloc returns device memory of at least `bytes` usable
+ * on `stream`, or NULL on failure; free releases it.  With NULL callbacks the
+ * library uses hipMalloc / hipFree. */
+typedef void* (*cr_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*cr_free_fn)(void* ptr, void* stream, void* user);
+
+/* Creates a context on HIP device `device`.  The context owns its scratch
+ * memory (grown on demand, freed by cr_destroy). */
+cr_status cr_create(cr_context** out, int device, cr_alloc_fn alloc, cr_free_fn free_fn, void* user);
+void cr_destroy(cr_context* ctx);
+
+/* Description of the last failure on the calling thread; valid until the next
+ * call on this thread.  Never NULL. */
+const char* cr_last_error(void);
+
+/* A diagram in structure-of-arrays form.  The five arrays are device pointers
+ * into one block allocated by the plain call (through the context allocator);
+ * the caller owns it and releases it with cr_diagram_free. */
+typedef struct cr_diagram {
+  int64_t n;             /* number of rows (host value) */
+  int32_t* dim;          /* 0 .. ndim-1 */
+  float* birth;          /* == image[birth_pixel] */
+  float* death;          /* == image[death_pixel]; +INFINITY if essential */
+  int64_t* birth_pixel;  /* flat index into the input */
+  int64_t* death_pixel;  /* -1 if essential */
+  void* block;           /* the allocation holding the arrays (NULL if n == 0) */
+} cr_diagram;
+
+/* The persistence diagram of one image or volume (Sec. 2: filtration by the
+ * maximum over each cell's vertices, sort, apparent pairs, degree 0 by
+ * union-find, higher degrees by coboundary reduction with clearing).
+ *   image : device, prod(shape) floats, C order; not modified, not retained.
+ *   ndim  : 2 or 3.  shape : host, ndim extents >= 1, C order.
+ *   maxdim: highest dimension reported; >= 0, clamped to ndim-1.
+ *   flags : must be 0.
+ * Synchronises `stream` once (to learn the number of rows), then allocates
+ * `out` and enqueues the final copy on `stream`.  Errors: INVALID_ARGUMENT,
+ * NAN_INPUT, TOO_LARGE (more than 2^30 cells), OUT_OF_MEMORY, HIP, INTERNAL. */
+cr_status cr_persistence(cr_context* ctx, const float* image, int ndim, const int64_t* shape, int maxdim,
+                         uint32_t flags, void* stream, cr_diagram* out);
+
+/* Releases a diagram returned by cr_persistence; sets out->n = 0. */
+void cr_diagram_free(cr_context* ctx, cr_diagram* d);
+
+/* Diagrams of n_images images of one ndim and possibly different shapes,
+ * packed back to back in one device buffer, computed together in one pass of
+ * every stage (the images share each launch).
+ *   packed        : device floats; image i occupies [pixel_offsets[i], pixel_offsets[i+1]).
+ *   pixel_offsets : host, n_images+1 entries, pixel_offsets[0] = 0, consistent with shapes.
+ *   shapes        : host, n_images*ndim extents, C order per image.
+ *   dim..death_pixel: device arrays of `capacity` rows (caller-provided).
+ *   pair_offsets  : device, n_images+1 int64: rows of image i are
+ *                   [pair_offsets[i], pair_offsets[i+1]) in canonical order;
+ *                   pair_offsets[n_images] is the total (also when it exceeds capacity).
+ *   status        : device, n_images int32: 0, or CR_ERR_NAN_INPUT for an image with NaN.
+ * Pixel indices index `packed`.  Never synchronises; when the device-side row
+ * count exceeds capacity the rows beyond it are dropped and the total in
+ * pair_offsets[n_images] tells the capacity needed.  Host-side argument errors
+ * are returned directly.  Call cr_sync_status after the stream completes to
+ * learn device-side failures (NaN, capacity, internal). */
+cr_status cr_persistence_batched(cr_context* ctx, int n_images, const float* packed, const int64_t* pixel_offsets,
+                                 const int64_t* shapes, int ndim, int maxdim, uint32_t flags, void* stream,
+                                 int32_t* dim, float* birth, float* death, int64_t* birth_pixel,
+                                 int64_t* death_pixel, int64_t capacity, int64_t* pair_offsets, int32_t* status);
+
+/* Synchronises `stream` and returns the device-side status of the last
+ * batched call on this context (CR_OK, CR_ERR_NAN_INPUT, CR_ERR_CAPACITY,
+ * CR_ERR_OUT_OF_MEMORY for scratch exhaustion, or CR_ERR_INTERNAL). */
+cr_status cr_sync_status(cr_context* ctx, void* stream);
+
+/* Gradient of a loss L(birth, death) with respect to the image: since
+ * birth_i = image[birth_pixel_i] and death_i = image[death_pixel_i],
+ *   grad_image[birth_pixel_i] += grad_birth_i,  grad_image[death_pixel_i] += grad_death_i
+ * (rows with death_pixel -1 contribute only their birth).  All arrays are device
+ * arrays of n_pairs rows; grad_birth or grad_death may be NULL (zero).
+ * grad_image (n_pixels floats) is accumulated into, not overwritten.  Pixel
+ * indices outside [0, n_pixels) give CR_ERR_INVALID_ARGUMENT (after the stream
+ * completes: this call synchronises once).  Sums over rows sharing a pixel use
+ * float atomics, so their rounding order is not fixed. */
+cr_status cr_persistence_backward(cr_context* ctx, const int64_t* birth_pixel, const int64_t* death_pixel,
+                                  const float* grad_birth, const float* grad_death, int64_t n_pairs,
+                                  float* grad_image, int64_t n_pixels, void* stream);
+
+/* Sizes seen by the last plain or batched call on this context. */
+typedef struct cr_stats {
+  int64_t n_pixels;
+  int64_t n_cells;
+  int64_t survivors[4]; /* cells of each dimension left after apparent pairs */
+  int64_t n_rows;       /* rows of positive length, essential bars included */
+  int64_t arena_used;   /* 64-bit entries of column storage used by the reduction */
+} cr_stats;
+cr_status cr_get_stats(cr_context* ctx, cr_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CR_H */

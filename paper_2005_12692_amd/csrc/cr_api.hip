@@ -1,0 +1,549 @@
+// Host layer of libcr: argument checks, scratch planning, stage sequencing.
+// Every stage is a HIP kernel enqueued on the caller's stream; the host only
+// validates arguments, lays out scratch memory and reads back counts.
+#include <string>
+#include <vector>
+#include <cstring>
+#include <algorithm>
+
+#include "cr.h"
+#include "cr_emit.h"
+
+namespace cr {
+// launchers defined in the kernel translation units
+void launch_apparent(int ndim, int ntiles, const float* img, const ImgDesc* imgs, const int4* tiles,
+                     Layout L, uint64_t* surv, uint64_t surv_cap, unsigned long long* surv_count,
+                     unsigned long long* dim_count, int32_t* vlink, int32_t* tlink,
+                     uint32_t* img_status, Status* st, hipStream_t stream);
+uint64_t* launch_sort(uint64_t* keys, uint64_t* tmp, const unsigned long long* n_ptr, uint64_t cap, int bits,
+                      uint32_t* hist, hipStream_t stream);
+void launch_h0(int grid, const uint64_t* skeys, const unsigned long long* dim_count, const ImgDesc* imgs,
+               Layout L, int32_t* vlink, uint64_t* T, uint8_t* neg, const EmitCtx& E, Status* st,
+               hipStream_t s);
+void launch_dual(int grid, int top, const uint64_t* skeys, const unsigned long long* dim_count,
+                 const ImgDesc* imgs, Layout L, int32_t* tlink, const uint8_t* neg, const int32_t* owner,
+                 uint64_t* T, const EmitCtx& E, Status* st, hipStream_t s);
+struct RedCtx;
+void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+void launch_gather(int grid, const uint64_t* cand, const unsigned long long* n_ptr, uint64_t cap,
+                   const float* img, const ImgDesc* imgs, Layout L, int32_t* dim, float* birth, float* death,
+                   int64_t* bpix, int64_t* dpix, hipStream_t s);
+void launch_img_offsets(const uint32_t* cnt, const uint32_t* img_status, int nimg, int64_t* offsets,
+                        int32_t* status, hipStream_t s);
+void launch_backward(const int64_t* bpix, const int64_t* dpix, const float* gb, const float* gd, int64_t n,
+                     float* grad, int64_t n_pixels, uint32_t* bad, hipStream_t s);
+void launch_h1_reduce_raw(int grid, const float* img, const ImgDesc* imgs, Layout L, const uint64_t* skeys,
+                          const unsigned long long* dim_count, const uint8_t* neg, int32_t* owner,
+                          uint64_t* piv, uint64_t* col_ptr, uint64_t* arena, uint64_t arena_cap,
+                          unsigned long long* arena_top, Status* st, const EmitCtx& E, hipStream_t s);
+constexpr int SORT_HIST_WORDS = 256 * 1024;
+}  // namespace cr
+
+using namespace cr;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+cr_status fail(cr_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(CR_ERR_HIP, std::string(#expr " failed: ") + hipGetErrorString(e_));       \
+  } while (0)
+
+int bits_for(uint64_t x) {  // smallest b with x < 2^b
+  int b = 0;
+  while (b < 64 && (x >> b) != 0) ++b;
+  return b;
+}
+
+constexpr int TILE2[3] = {1, 8, 32};  // z y x extents of a 2D stencil tile
+constexpr int TILE3[3] = {4, 4, 16};  // of a 3D stencil tile
+constexpr int KGRID = 2048;           // workgroups of the grid-stride kernels
+constexpr int RGRID = 1024;           // workgroups of the reduction
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Problem {
+  int nimg = 0, ndim = 0, maxdim = 0;
+  std::vector<ImgDesc> imgs;
+  std::vector<int4> tiles;
+  uint64_t P = 0, N = 0;  // totals over the batch
+  Layout L{};
+};
+
+struct Plan {
+  size_t status, counters, img_status, img_pairs, imgs, tiles, surv_a, surv_b, hist, vlink, tlink, T, neg,
+      owner, piv, colptr, arena, total;
+  uint64_t surv_cap, e_cap, arena_cap;
+};
+
+}  // namespace
+
+struct cr_context {
+  int device = 0;
+  cr_alloc_fn alloc = nullptr;
+  cr_free_fn free_fn = nullptr;
+  void* user = nullptr;
+  char* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  char* host_stage = nullptr;
+  size_t host_stage_bytes = 0;
+  hipEvent_t stage_done = nullptr;
+  bool stage_pending = false;
+  uint64_t arena_entries = 1ull << 26;
+  Plan plan{};
+  Problem prob{};
+  cr_stats stats{};
+  bool last_batched_valid = false;
+  uint32_t* bwd_flag = nullptr;  // device word for the backward index check
+};
+
+namespace {
+
+// counters block: surv_count, dim_count[4], cand_count, arena_top, spare
+enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_WORDS = 8 };
+
+cr_status build_problem(Problem& pb, int nimg, const int64_t* pixel_offsets, const int64_t* shapes, int ndim,
+                        int maxdim) {
+  if (nimg < 1) return fail(CR_ERR_INVALID_ARGUMENT, "n_images must be >= 1");
+  if (ndim != 2 && ndim != 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
+  if (maxdim < 0) return fail(CR_ERR_INVALID_ARGUMENT, "maxdim must be >= 0");
+  if (!shapes) return fail(CR_ERR_INVALID_ARGUMENT, "shape is NULL");
+  pb.nimg = nimg;
+  pb.ndim = ndim;
+  pb.maxdim = std::min(maxdim, ndim - 1);
+  pb.imgs.resize(nimg);
+  pb.tiles.clear();
+  pb.P = 0;
+  pb.N = 0;
+  uint64_t maxN = 1, maxP = 1;
+  const int* tile = ndim == 2 ? TILE2 : TILE3;
+  for (int i = 0; i < nimg; ++i) {
+    int64_t n[3] = {1, 1, 1};
+    for (int a = 0; a < ndim; ++a) {
+      const int64_t s = shapes[(int64_t)i * ndim + a];
+      if (s < 1) return fail(CR_ERR_INVALID_ARGUMENT, "every extent must be >= 1");
+      if (s > (1 << 29)) return fail(CR_ERR_TOO_LARGE, "extent too large");
+      n[3 - ndim + a] = s;
+    }
+    ImgDesc& d = pb.imgs[i];
+    uint64_t P = 1, N = 1;
+    for (int a = 0; a < 3; ++a) {
+      d.n[a] = (int32_t)n[a];
+      d.K[a] = (int32_t)(2 * n[a] - 1);
+      P *= (uint64_t)n[a];
+      N *= (uint64_t)(2 * n[a] - 1);
+    }
+    if (N > (1ull << 30)) return fail(CR_ERR_TOO_LARGE, "an image has more than 2^30 cells");
+    d.pix_off = (int64_t)pb.P;
+    if (pixel_offsets) {
+      if (pixel_offsets[i] != (int64_t)pb.P || pixel_offsets[i + 1] != (int64_t)(pb.P + P))
+        return fail(CR_ERR_INVALID_ARGUMENT, "pixel_offsets do not match the shapes");
+    }
+    pb.P += P;
+    pb.N += N;
+    maxN = std::max(maxN, N);
+    maxP = std::max(maxP, P);
+    for (int64_t z = 0; z < n[0]; z += tile[0])
+      for (int64_t y = 0; y < n[1]; y += tile[1])
+        for (int64_t x = 0; x < n[2]; x += tile[2]) pb.tiles.push_back(make_int4(i, (int)z, (int)y, (int)x));
+  }
+  if (pb.P >= (1ull << 31) - 2) return fail(CR_ERR_TOO_LARGE, "more than 2^31 pixels in one call");
+  if (pb.N >= (1ull << 32)) return fail(CR_ERR_TOO_LARGE, "more than 2^32 cells in one call");
+  Layout& L = pb.L;
+  L.kb = std::max(1, bits_for(maxN - 1));
+  L.ib = nimg > 1 ? bits_for((uint64_t)nimg - 1) : 0;
+  L.pb = bits_for(maxP);
+  L.nimg = nimg;
+  L.ndim = ndim;
+  if (2 + L.ib + 32 + L.kb > 64 || L.ib + 2 + 2 * L.pb > 64)
+    return fail(CR_ERR_TOO_LARGE, "batch too large for the 64-bit key layout; split it");
+  return CR_OK;
+}
+
+Plan make_plan(const Problem& pb, uint64_t arena_entries) {
+  Plan p{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  p.surv_cap = pb.N;
+  p.e_cap = 3 * pb.P + 64;
+  const bool vol = pb.ndim == 3 && pb.maxdim >= 1;
+  p.arena_cap = vol ? arena_entries : 0;
+  p.status = take(sizeof(Status));
+  p.counters = take(C_WORDS * 8);
+  p.img_status = take(4 * (size_t)pb.nimg);
+  p.img_pairs = take(4 * (size_t)(pb.nimg + 1));
+  p.imgs = take(sizeof(ImgDesc) * pb.nimg);
+  p.tiles = take(sizeof(int4) * pb.tiles.size());
+  p.surv_a = take(8 * p.surv_cap);
+  p.surv_b = take(8 * p.surv_cap);
+  p.hist = take(4 * (size_t)SORT_HIST_WORDS);
+  p.vlink = take(4 * pb.P);
+  p.tlink = take(4 * pb.P);
+  p.T = take(8 * (pb.P + pb.nimg + 64));
+  p.neg = take(p.e_cap);
+  p.owner = take(vol ? 4 * 3 * pb.P : 0);
+  p.piv = take(vol ? 8 * p.e_cap : 0);
+  p.colptr = take(vol ? 8 * p.e_cap : 0);
+  p.arena = take(8 * p.arena_cap);
+  p.total = o;
+  return p;
+}
+
+cr_status ensure_scratch(cr_context* ctx, size_t bytes) {
+  if (ctx->scratch_bytes >= bytes) return CR_OK;
+  if (ctx->scratch) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+  }
+  const size_t want = align_up(bytes + bytes / 8, 1 << 21);
+  if (hipMalloc(&ctx->scratch, want) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->scratch = nullptr;
+    return fail(CR_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(want) + " scratch bytes failed");
+  }
+  ctx->scratch_bytes = want;
+  return CR_OK;
+}
+
+cr_status ensure_stage(cr_context* ctx, size_t bytes) {
+  if (ctx->stage_pending) {
+    HIP_TRY(hipEventSynchronize(ctx->stage_done));
+    ctx->stage_pending = false;
+  }
+  if (ctx->host_stage_bytes >= bytes) return CR_OK;
+  if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+  ctx->host_stage = nullptr;
+  const size_t want = align_up(bytes, 1 << 16);
+  if (hipHostMalloc((void**)&ctx->host_stage, want, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->host_stage_bytes = 0;
+    return fail(CR_ERR_OUT_OF_MEMORY, "pinned staging allocation failed");
+  }
+  ctx->host_stage_bytes = want;
+  return CR_OK;
+}
+
+template <class T>
+T* at(cr_context* ctx, size_t off) {
+  return reinterpret_cast<T*>(ctx->scratch + off);
+}
+
+// Enqueues every stage up to sorted canonical keys.  Returns the buffer holding them.
+cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, uint64_t** cand_out) {
+  const Problem& pb = ctx->prob;
+  const Plan& p = ctx->plan;
+  const Layout L = pb.L;
+  Status* st = at<Status>(ctx, p.status);
+  unsigned long long* cnt = at<unsigned long long>(ctx, p.counters);
+  uint32_t* img_status = at<uint32_t>(ctx, p.img_status);
+  uint32_t* img_pairs = at<uint32_t>(ctx, p.img_pairs);
+  ImgDesc* d_imgs = at<ImgDesc>(ctx, p.imgs);
+  int4* d_tiles = at<int4>(ctx, p.tiles);
+
+  // upload image descriptors and tiles
+  const size_t bi = sizeof(ImgDesc) * pb.nimg, bt = sizeof(int4) * pb.tiles.size();
+  cr_status rc = ensure_stage(ctx, bi + bt);
+  if (rc != CR_OK) return rc;
+  std::memcpy(ctx->host_stage, pb.imgs.data(), bi);
+  std::memcpy(ctx->host_stage + bi, pb.tiles.data(), bt);
+  HIP_TRY(hipMemcpyAsync(d_imgs, ctx->host_stage, bi, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_tiles, ctx->host_stage + bi, bt, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(ctx->stage_done, s));
+  ctx->stage_pending = true;
+
+  // zero the status words, counters and per-image counts (one contiguous range)
+  launch_fill_u32(reinterpret_cast<uint32_t*>(st), 0, (p.img_pairs + 4 * (pb.nimg + 1) - p.status) / 4, s);
+
+  uint64_t* surv = at<uint64_t>(ctx, p.surv_a);
+  uint64_t* surv_tmp = at<uint64_t>(ctx, p.surv_b);
+  int32_t* vlink = at<int32_t>(ctx, p.vlink);
+  int32_t* tlink = at<int32_t>(ctx, p.tlink);
+  launch_apparent(pb.ndim, (int)pb.tiles.size(), image, d_imgs, d_tiles, L, surv, p.surv_cap, &cnt[C_SURV],
+                  &cnt[C_DIM], vlink, tlink, img_status, st, s);
+  uint32_t* hist = at<uint32_t>(ctx, p.hist);
+  uint64_t* skeys = launch_sort(surv, surv_tmp, &cnt[C_SURV], p.surv_cap, 2 + L.ib + 32 + L.kb, hist, s);
+  uint64_t* cand = (skeys == surv) ? surv_tmp : surv;  // the other buffer collects the rows
+
+  EmitCtx E;
+  E.img = image;
+  E.imgs = d_imgs;
+  E.L = L;
+  E.cand = cand;
+  E.cand_cap = p.surv_cap;
+  E.cand_count = &cnt[C_CAND];
+  E.img_pairs = img_pairs;
+  E.st = st;
+
+  uint8_t* neg = at<uint8_t>(ctx, p.neg);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(neg), 0, p.e_cap / 4, s);
+  uint64_t* T = at<uint64_t>(ctx, p.T);
+  launch_h0(KGRID, skeys, &cnt[C_DIM], d_imgs, L, vlink, T, neg, E, st, s);
+
+  int32_t* owner = at<int32_t>(ctx, p.owner);
+  if (pb.maxdim >= 1) {
+    if (pb.ndim == 2) {
+      launch_dual(KGRID, 2, skeys, &cnt[C_DIM], d_imgs, L, tlink, neg, nullptr, T, E, st, s);
+    } else {
+      launch_fill_u32(reinterpret_cast<uint32_t*>(owner), 0xFFFFFFFFu, 3 * pb.P, s);
+      launch_h1_reduce_raw(RGRID, image, d_imgs, L, skeys, &cnt[C_DIM], neg, owner, at<uint64_t>(ctx, p.piv),
+                           at<uint64_t>(ctx, p.colptr), at<uint64_t>(ctx, p.arena), p.arena_cap, &cnt[C_ARENA],
+                           st, E, s);
+      if (pb.maxdim >= 2)
+        launch_dual(KGRID, 3, skeys, &cnt[C_DIM], d_imgs, L, tlink, neg, owner, T, E, st, s);
+    }
+  }
+  // canonical order: sort the row keys.  The survivor keys are dead now, so
+  // their buffer is the scratch of this sort.
+  *cand_out = launch_sort(cand, skeys, &cnt[C_CAND], p.surv_cap, L.ib + 2 + 2 * L.pb, hist, s);
+  return CR_OK;
+}
+
+struct HostCounters {
+  Status st;
+  unsigned long long cnt[C_WORDS];
+};
+
+cr_status read_counters(cr_context* ctx, hipStream_t s, HostCounters* h) {
+  const Plan& p = ctx->plan;
+  cr_status rc = ensure_stage(ctx, sizeof(HostCounters));
+  if (rc != CR_OK) return rc;
+  HIP_TRY(hipMemcpyAsync(ctx->host_stage, ctx->scratch + p.status, sizeof(Status), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(ctx->host_stage + sizeof(Status), ctx->scratch + p.counters, 8 * C_WORDS,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::memcpy(&h->st, ctx->host_stage, sizeof(Status));
+  std::memcpy(h->cnt, ctx->host_stage + sizeof(Status), 8 * C_WORDS);
+  cr_stats& S = ctx->stats;
+  S.n_pixels = (int64_t)ctx->prob.P;
+  S.n_cells = (int64_t)ctx->prob.N;
+  for (int i = 0; i < 4; ++i) S.survivors[i] = (int64_t)h->cnt[C_DIM + i];
+  S.n_rows = (int64_t)h->cnt[C_CAND];
+  S.arena_used = (int64_t)h->cnt[C_ARENA];
+  return CR_OK;
+}
+
+cr_status status_error(const Status& st, bool* arena_overflow) {
+  *arena_overflow = false;
+  if (st.nan_input) return fail(CR_ERR_NAN_INPUT, "input contains NaN");
+  if (st.overflow) {
+    *arena_overflow = true;
+    return fail(CR_ERR_OUT_OF_MEMORY, "scratch capacity exceeded");
+  }
+  if (st.iter_cap) return fail(CR_ERR_INTERNAL, "iteration cap reached");
+  if (st.internal) return fail(CR_ERR_INTERNAL, "internal consistency check failed");
+  return CR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cr_last_error(void) { return g_err.c_str(); }
+
+cr_status cr_create(cr_context** out, int device, cr_alloc_fn alloc, cr_free_fn free_fn, void* user) {
+  if (!out) return fail(CR_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(CR_ERR_INVALID_ARGUMENT, "alloc and free must both be given or both be NULL");
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(CR_ERR_INVALID_ARGUMENT, "no such device");
+  HIP_TRY(hipSetDevice(device));
+  cr_context* c = new (std::nothrow) cr_context();
+  if (!c) return fail(CR_ERR_OUT_OF_MEMORY, "context allocation failed");
+  c->device = device;
+  c->alloc = alloc;
+  c->free_fn = free_fn;
+  c->user = user;
+  if (hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return fail(CR_ERR_HIP, "hipEventCreate failed");
+  }
+  *out = c;
+  return CR_OK;
+}
+
+void cr_destroy(cr_context* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->bwd_flag) (void)hipFree(ctx->bwd_flag);
+  if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+  if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
+  delete ctx;
+}
+
+cr_status cr_persistence(cr_context* ctx, const float* image, int ndim, const int64_t* shape, int maxdim,
+                         uint32_t flags, void* stream, cr_diagram* out) {
+  if (!ctx || !out) return fail(CR_ERR_INVALID_ARGUMENT, "ctx or out is NULL");
+  out->n = 0;
+  out->dim = nullptr; out->birth = nullptr; out->death = nullptr;
+  out->birth_pixel = nullptr; out->death_pixel = nullptr; out->block = nullptr;
+  if (!image) return fail(CR_ERR_INVALID_ARGUMENT, "image is NULL");
+  if (flags != 0) return fail(CR_ERR_INVALID_ARGUMENT, "flags must be 0");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  cr_status rc = build_problem(ctx->prob, 1, nullptr, shape, ndim, maxdim);
+  if (rc != CR_OK) return rc;
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    ctx->plan = make_plan(ctx->prob, ctx->arena_entries);
+    rc = ensure_scratch(ctx, ctx->plan.total);
+    if (rc != CR_OK) return rc;
+    uint64_t* cand = nullptr;
+    rc = enqueue_pipeline(ctx, image, s, &cand);
+    if (rc != CR_OK) return rc;
+    HostCounters h;
+    rc = read_counters(ctx, s, &h);
+    if (rc != CR_OK) return rc;
+    bool arena_over = false;
+    rc = status_error(h.st, &arena_over);
+    if (rc != CR_OK) {
+      if (arena_over && h.cnt[C_ARENA] > ctx->plan.arena_cap && attempt < 3) {
+        ctx->arena_entries = std::max<uint64_t>(ctx->arena_entries * 4, h.cnt[C_ARENA] * 2);
+        continue;  // rerun with a larger column arena
+      }
+      return rc;
+    }
+    const int64_t n = (int64_t)h.cnt[C_CAND];
+    out->n = n;
+    if (n == 0) return CR_OK;
+    const size_t bytes = align_up(4 * n, 256) * 2 + align_up(4 * n, 256) + 2 * align_up(8 * n, 256);
+    void* block = nullptr;
+    if (ctx->alloc) {
+      block = ctx->alloc(bytes, stream, ctx->user);
+    } else if (hipMalloc(&block, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      block = nullptr;
+    }
+    if (!block) {
+      out->n = 0;
+      return fail(CR_ERR_OUT_OF_MEMORY, "output allocation failed");
+    }
+    char* b = (char*)block;
+    out->block = block;
+    out->dim = (int32_t*)b;
+    b += align_up(4 * n, 256);
+    out->birth = (float*)b;
+    b += align_up(4 * n, 256);
+    out->death = (float*)b;
+    b += align_up(4 * n, 256);
+    out->birth_pixel = (int64_t*)b;
+    b += align_up(8 * n, 256);
+    out->death_pixel = (int64_t*)b;
+    launch_gather(KGRID, cand, at<unsigned long long>(ctx, ctx->plan.counters) + C_CAND, (uint64_t)n, image,
+                  at<ImgDesc>(ctx, ctx->plan.imgs), ctx->prob.L, out->dim, out->birth, out->death,
+                  out->birth_pixel, out->death_pixel, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CR_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return CR_OK;
+  }
+  return fail(CR_ERR_OUT_OF_MEMORY, "column arena still too small after retries");
+}
+
+void cr_diagram_free(cr_context* ctx, cr_diagram* d) {
+  if (!d) return;
+  if (d->block) {
+    if (ctx && ctx->free_fn) ctx->free_fn(d->block, nullptr, ctx->user);
+    else (void)hipFree(d->block);
+  }
+  d->n = 0;
+  d->block = nullptr;
+  d->dim = nullptr; d->birth = nullptr; d->death = nullptr;
+  d->birth_pixel = nullptr; d->death_pixel = nullptr;
+}
+
+cr_status cr_persistence_batched(cr_context* ctx, int n_images, const float* packed, const int64_t* pixel_offsets,
+                                 const int64_t* shapes, int ndim, int maxdim, uint32_t flags, void* stream,
+                                 int32_t* dim, float* birth, float* death, int64_t* birth_pixel,
+                                 int64_t* death_pixel, int64_t capacity, int64_t* pair_offsets, int32_t* status) {
+  if (!ctx) return fail(CR_ERR_INVALID_ARGUMENT, "ctx is NULL");
+  if (!packed || !pixel_offsets || !pair_offsets || !status)
+    return fail(CR_ERR_INVALID_ARGUMENT, "a required pointer is NULL");
+  if (capacity < 0 || (capacity > 0 && (!dim || !birth || !death || !birth_pixel || !death_pixel)))
+    return fail(CR_ERR_INVALID_ARGUMENT, "bad output buffers");
+  if (flags != 0) return fail(CR_ERR_INVALID_ARGUMENT, "flags must be 0");
+  if (pixel_offsets[0] != 0) return fail(CR_ERR_INVALID_ARGUMENT, "pixel_offsets[0] must be 0");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  ctx->last_batched_valid = false;
+  cr_status rc = build_problem(ctx->prob, n_images, pixel_offsets, shapes, ndim, maxdim);
+  if (rc != CR_OK) return rc;
+  ctx->plan = make_plan(ctx->prob, ctx->arena_entries);
+  rc = ensure_scratch(ctx, ctx->plan.total);
+  if (rc != CR_OK) return rc;
+  uint64_t* cand = nullptr;
+  rc = enqueue_pipeline(ctx, packed, s, &cand);
+  if (rc != CR_OK) return rc;
+  const Plan& p = ctx->plan;
+  launch_gather(KGRID, cand, at<unsigned long long>(ctx, p.counters) + C_CAND, (uint64_t)capacity, packed,
+                at<ImgDesc>(ctx, p.imgs), ctx->prob.L, dim, birth, death, birth_pixel, death_pixel, s);
+  launch_img_offsets(at<uint32_t>(ctx, p.img_pairs), at<uint32_t>(ctx, p.img_status), n_images, pair_offsets,
+                     status, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(CR_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  ctx->last_batched_valid = true;
+  return CR_OK;
+}
+
+cr_status cr_sync_status(cr_context* ctx, void* stream) {
+  if (!ctx) return fail(CR_ERR_INVALID_ARGUMENT, "ctx is NULL");
+  if (!ctx->last_batched_valid) return fail(CR_ERR_INVALID_ARGUMENT, "no batched call to report on");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HostCounters h;
+  cr_status rc = read_counters(ctx, (hipStream_t)stream, &h);
+  if (rc != CR_OK) return rc;
+  bool arena_over = false;
+  return status_error(h.st, &arena_over);
+}
+
+cr_status cr_persistence_backward(cr_context* ctx, const int64_t* birth_pixel, const int64_t* death_pixel,
+                                  const float* grad_birth, const float* grad_death, int64_t n_pairs,
+                                  float* grad_image, int64_t n_pixels, void* stream) {
+  if (!ctx) return fail(CR_ERR_INVALID_ARGUMENT, "ctx is NULL");
+  if (n_pairs < 0 || n_pixels < 0) return fail(CR_ERR_INVALID_ARGUMENT, "negative size");
+  if (n_pairs == 0) return CR_OK;
+  if (!birth_pixel || !death_pixel || !grad_image)
+    return fail(CR_ERR_INVALID_ARGUMENT, "a required pointer is NULL");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (!ctx->bwd_flag && hipMalloc(&ctx->bwd_flag, 256) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->bwd_flag = nullptr;
+    return fail(CR_ERR_OUT_OF_MEMORY, "hipMalloc failed");
+  }
+  uint32_t* bad = ctx->bwd_flag;
+  launch_fill_u32(bad, 0, 1, s);
+  cr_status rc;
+  launch_backward(birth_pixel, death_pixel, grad_birth, grad_death, n_pairs, grad_image, n_pixels, bad, s);
+  rc = ensure_stage(ctx, 4);
+  if (rc != CR_OK) return rc;
+  HIP_TRY(hipMemcpyAsync(ctx->host_stage, bad, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  uint32_t hb = 0;
+  std::memcpy(&hb, ctx->host_stage, 4);
+  if (hb) return fail(CR_ERR_INVALID_ARGUMENT, "a pixel index is out of range");
+  return CR_OK;
+}
+
+cr_status cr_get_stats(cr_context* ctx, cr_stats* out) {
+  if (!ctx || !out) return fail(CR_ERR_INVALID_ARGUMENT, "NULL argument");
+  *out = ctx->stats;
+  return CR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,261 @@
+// Degree 0 and the top degree by union-find with the elder rule.
+//
+// Degree 0 (Sec. 2, Fig. 2): the surviving edges are visited in filtration
+// order and an edge joining two components kills the younger one.  The top
+// degree (1-cycles of an image, 2-cycles of a volume) is the same computation
+// on the dual graph -- top cells plus one exterior node per image, joined by
+// the (top-1)-cells -- in the reversed order, where the exterior node is the
+// oldest (Alexander duality, Remark 2.1).  Both run here as one kernel.
+//
+// Sequential Kruskal order is replaced by a merge structure whose final state
+// does not depend on the order in which edges are inserted: every node x holds
+// one 64-bit word T[x] = (level s, node v) meaning "x is joined to the older
+// node v by level s".  rep(x, s) follows these words while their level is <= s.
+// Inserting edge (a, b) at level s: take r_a = rep(a, s), r_b = rep(b, s); if
+// they differ, the younger y of the two is relinked to the older o at level s
+// by one 64-bit CAS, and the fact it held before (y joined to v at a higher
+// level s') is re-inserted as (o, v, s').  Levels only decrease in each word,
+// so every loop terminates, and once all edges are in, T[x].s is the level at
+// which x first meets an older node -- exactly the elder-rule death of x.  The
+// edges can therefore be inserted by all threads at once, lock-free.
+#include "cr_emit.h"
+
+namespace cr {
+
+constexpr uint32_t ITER_CAP = 1u << 22;
+
+// ---- the merge structure -------------------------------------------------------
+__device__ inline uint32_t trip_rep(uint64_t* T, uint32_t x, uint32_t s, Status* st) {
+  for (uint32_t it = 0; it < ITER_CAP; ++it) {
+    const uint64_t t = ld_rlx64(&T[x]);
+    if ((uint32_t)(t >> 32) <= s) x = (uint32_t)t;
+    else return x;
+  }
+  raise_flag(st, &st->iter_cap);
+  return x;
+}
+
+__device__ inline void trip_merge(uint64_t* T, uint32_t a, uint32_t b, uint32_t s, Status* st) {
+  for (uint32_t it = 0; it < ITER_CAP; ++it) {
+    a = trip_rep(T, a, s, st);
+    b = trip_rep(T, b, s, st);
+    if (a == b) return;
+    const uint32_t y = a > b ? a : b, o = a > b ? b : a;
+    const uint64_t old = ld_rlx64(&T[y]);
+    const uint32_t os = (uint32_t)(old >> 32);
+    if (os <= s) continue;  // y was relinked meanwhile; walk again
+    if (cas64(&T[y], old, ((uint64_t)s << 32) | o)) {
+      if (os == TRIP_INF) return;
+      a = o;
+      b = (uint32_t)old;
+      s = os;
+    }
+    if (aborted(st)) return;
+  }
+  raise_flag(st, &st->iter_cap);
+}
+
+__global__ void k_trip_init(uint64_t* __restrict__ T, const unsigned long long* __restrict__ cnt,
+                            int cnt_index, uint32_t extra) {
+  const uint64_t n = cnt[cnt_index] + extra;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    T[i] = ((uint64_t)TRIP_INF << 32) | (uint32_t)i;
+}
+
+// Segment [off, off + n) of dimension dm in the sorted survivor array.
+__device__ inline void segment(const unsigned long long* dim_count, int dm, uint64_t* off, uint64_t* n) {
+  uint64_t o = 0;
+  for (int i = 0; i < dm; ++i) o += dim_count[i];
+  *off = o;
+  *n = dim_count[dm];
+}
+
+// Surviving vertices become forest roots: vlink[pixel] = -(rank + 2).
+__global__ void k_vroot_init(const uint64_t* __restrict__ skeys, const unsigned long long* __restrict__ dim_count,
+                             const ImgDesc* __restrict__ imgs, Layout L, int32_t* __restrict__ vlink,
+                             const Status* __restrict__ st) {
+  if (aborted(st)) return;
+  uint64_t off, n;
+  segment(dim_count, 0, &off, &n);
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n;
+       r += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = skeys[off + r];
+    const ImgDesc d = imgs[skey_img(L, k)];
+    int c[3];
+    kidx_coords(d, skey_kidx(L, k), c);
+    vlink[anchor_pixel(d, c)] = -(int32_t)(r + 2);
+  }
+}
+
+// Surviving top cells become dual roots: tlink[anchor] = -(id + 2), where the
+// dual node id of the cell at ascending rank r is nimg + (ntop - 1 - r) (the
+// exterior nodes 0..nimg-1 are the oldest; larger keys are older).
+__global__ void k_troot_init(const uint64_t* __restrict__ skeys, const unsigned long long* __restrict__ dim_count,
+                             int top, const ImgDesc* __restrict__ imgs, Layout L, int32_t* __restrict__ tlink,
+                             const Status* __restrict__ st) {
+  if (aborted(st)) return;
+  uint64_t off, n;
+  segment(dim_count, top, &off, &n);
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n;
+       r += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = skeys[off + r];
+    const ImgDesc d = imgs[skey_img(L, k)];
+    int c[3];
+    kidx_coords(d, skey_kidx(L, k), c);
+    tlink[anchor_pixel(d, c)] = -(int32_t)(L.nimg + (n - 1 - r) + 2);
+  }
+}
+
+__device__ inline uint32_t forest_root(const int32_t* link, int64_t x, Status* st) {
+  for (uint32_t it = 0; it < ITER_CAP; ++it) {
+    const int32_t v = link[x];
+    if (v == -1) break;  // a root that was never numbered: inconsistent state
+    if (v < 0) return (uint32_t)(-(v + 2));
+    x = v;
+  }
+  if (link[x] == -1) {
+    raise_flag(st, &st->internal);
+    return 0;
+  }
+  raise_flag(st, &st->iter_cap);
+  return 0;
+}
+
+// Degree 0: insert every surviving edge (level = its rank among edges).
+__global__ void k_h0_merge(const uint64_t* __restrict__ skeys, const unsigned long long* __restrict__ dim_count,
+                           const ImgDesc* __restrict__ imgs, Layout L, const int32_t* __restrict__ vlink,
+                           uint64_t* __restrict__ T, Status* __restrict__ st) {
+  uint64_t off, n;
+  segment(dim_count, 1, &off, &n);
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    if (aborted(st)) return;
+    const uint64_t k = skeys[off + i];
+    const ImgDesc d = imgs[skey_img(L, k)];
+    int c[3];
+    kidx_coords(d, skey_kidx(L, k), c);
+    const int a = (c[0] & 1) ? 0 : ((c[1] & 1) ? 1 : 2);
+    int p[3] = {c[0], c[1], c[2]}, q[3] = {c[0], c[1], c[2]};
+    p[a] -= 1;
+    q[a] += 1;
+    const uint32_t ra = forest_root(vlink, anchor_pixel(d, p), st);
+    const uint32_t rb = forest_root(vlink, anchor_pixel(d, q), st);
+    trip_merge(T, ra, rb, (uint32_t)i, st);
+  }
+}
+
+// Degree 0 rows; marks edges that kill a component (they are not 1-columns).
+__global__ void k_h0_emit(const uint64_t* __restrict__ skeys, const unsigned long long* __restrict__ dim_count,
+                          const uint64_t* __restrict__ T, uint8_t* __restrict__ neg, EmitCtx E) {
+  if (aborted(E.st)) return;
+  uint64_t off0, n0, off1, n1;
+  segment(dim_count, 0, &off0, &n0);
+  segment(dim_count, 1, &off1, &n1);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t nr = (n0 + 63) & ~63ull;
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < nr; r += stride) {
+    bool active = false;
+    int im = 0;
+    uint64_t ck = 0;
+    if (r < n0) {
+      const uint64_t t = T[r];
+      const uint32_t s = (uint32_t)(t >> 32);
+      const bool ess = s == TRIP_INF;
+      if (!ess) {
+        if (s >= n1) raise_flag(E.st, &E.st->internal);
+        else neg[s] = 1;
+      }
+      active = pair_row(E, skeys[off0 + r], ess ? 0 : skeys[off1 + s], ess, &im, &ck);
+    }
+    emit_rows(E, active, im, ck);
+  }
+}
+
+// Top degree on the dual graph.  Columns are the surviving (top-1)-cells that
+// are not deaths of degree top-2 (clearing): for top = 2 the edges not marked
+// by degree 0, for top = 3 the squares that own no pivot of degree 1.
+// level = n - 1 - i (larger key = earlier in the reversed order).
+__device__ inline bool dual_col_skipped(int top, uint64_t i, const uint8_t* neg, const int32_t* owner,
+                                        const ImgDesc& d, const int c[3]) {
+  if (top == 2) return neg[i] != 0;
+  const int orient = !(c[0] & 1) ? 0 : (!(c[1] & 1) ? 1 : 2);
+  return owner[3 * anchor_pixel(d, c) + orient] >= 0;
+}
+
+__global__ void k_dual_merge(int top, const uint64_t* __restrict__ skeys,
+                             const unsigned long long* __restrict__ dim_count,
+                             const ImgDesc* __restrict__ imgs, Layout L, const int32_t* __restrict__ tlink,
+                             const uint8_t* __restrict__ neg, const int32_t* __restrict__ owner,
+                             uint64_t* __restrict__ T, Status* __restrict__ st) {
+  uint64_t off, n;
+  segment(dim_count, top - 1, &off, &n);
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    if (aborted(st)) return;
+    const uint64_t k = skeys[off + i];
+    const int im = skey_img(L, k);
+    const ImgDesc d = imgs[im];
+    int c[3];
+    kidx_coords(d, skey_kidx(L, k), c);
+    if (dual_col_skipped(top, i, neg, owner, d, c)) continue;
+    // the one even axis of the cell within the image's own dimensions
+    const int a = (top == 2) ? ((c[1] & 1) ? 2 : 1) : (!(c[0] & 1) ? 0 : (!(c[1] & 1) ? 1 : 2));
+    if (d.K[a] == 1) continue;  // no cofacet at all (a flat image): a loop at the exterior node
+    uint32_t ends[2];
+    for (int j = 0; j < 2; ++j) {
+      int t[3] = {c[0], c[1], c[2]};
+      t[a] += j ? 1 : -1;
+      ends[j] = (t[a] < 0 || t[a] >= d.K[a]) ? (uint32_t)im : forest_root(tlink, anchor_pixel(d, t), st);
+    }
+    trip_merge(T, ends[0], ends[1], (uint32_t)(n - 1 - i), st);
+  }
+}
+
+__global__ void k_dual_emit(int top, const uint64_t* __restrict__ skeys,
+                            const unsigned long long* __restrict__ dim_count, const uint64_t* __restrict__ T,
+                            EmitCtx E) {
+  if (aborted(E.st)) return;
+  uint64_t offc, nc, offt, nt;
+  segment(dim_count, top - 1, &offc, &nc);
+  segment(dim_count, top, &offt, &nt);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t nr = (nt + 63) & ~63ull;
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < nr; r += stride) {
+    bool active = false;
+    int im = 0;
+    uint64_t ck = 0;
+    if (r < nt) {
+      const uint64_t id = E.L.nimg + (nt - 1 - r);
+      const uint64_t t = T[id];
+      const uint32_t s = (uint32_t)(t >> 32);
+      if (s == TRIP_INF || s >= nc) {
+        raise_flag(E.st, &E.st->internal);  // a top cell that never dies: impossible in a box
+      } else {
+        active = pair_row(E, skeys[offc + (nc - 1 - s)], skeys[offt + r], false, &im, &ck);
+      }
+    }
+    emit_rows(E, active, im, ck);
+  }
+}
+
+// ---- host launchers ------------------------------------------------------------
+void launch_h0(int grid, const uint64_t* skeys, const unsigned long long* dim_count, const ImgDesc* imgs,
+               Layout L, int32_t* vlink, uint64_t* T, uint8_t* neg, const EmitCtx& E, Status* st,
+               hipStream_t s) {
+  k_vroot_init<<<grid, 256, 0, s>>>(skeys, dim_count, imgs, L, vlink, st);
+  k_trip_init<<<grid, 256, 0, s>>>(T, dim_count, 0, 0);
+  k_h0_merge<<<grid, 256, 0, s>>>(skeys, dim_count, imgs, L, vlink, T, st);
+  k_h0_emit<<<grid, 256, 0, s>>>(skeys, dim_count, T, neg, E);
+}
+
+void launch_dual(int grid, int top, const uint64_t* skeys, const unsigned long long* dim_count,
+                 const ImgDesc* imgs, Layout L, int32_t* tlink, const uint8_t* neg, const int32_t* owner,
+                 uint64_t* T, const EmitCtx& E, Status* st, hipStream_t s) {
+  k_troot_init<<<grid, 256, 0, s>>>(skeys, dim_count, top, imgs, L, tlink, st);
+  k_trip_init<<<grid, 256, 0, s>>>(T, dim_count, top, (uint32_t)L.nimg);
+  k_dual_merge<<<grid, 256, 0, s>>>(top, skeys, dim_count, imgs, L, tlink, neg, owner, T, st);
+  k_dual_emit<<<grid, 256, 0, s>>>(top, skeys, dim_count, T, E);
+}
+
+}  // namespace cr

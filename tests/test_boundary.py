@@ -1,0 +1,85 @@
+"""The C-ABI boundary, checked on the CPU (no GPU compute).
+
+* libcr.so loads and exports every function that include/cr.h declares;
+* the product path refuses to fall back: without a GPU, or without the
+  library, calls raise instead of computing anything on the CPU;
+* the package does not import the oracle.
+"""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cr.h")
+LIB = os.path.join(ROOT, "paper_2005_12692_amd", "libcr.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(cr_[a-z_]+)\s*\(", text)
+    return sorted(set(n for n in names if not n.endswith("_fn")))
+
+
+@pytest.fixture(scope="module")
+def libcr():
+    if not os.path.exists(LIB):
+        from paper_2005_12692_amd import build
+        build.build(verbose=False)
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for required in ("cr_persistence", "cr_persistence_batched", "cr_persistence_backward",
+                     "cr_create", "cr_destroy", "cr_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(libcr):
+    missing = [n for n in declared_functions() if not hasattr(libcr, n)]
+    assert not missing, missing
+
+
+def test_last_error_is_a_string(libcr):
+    libcr.cr_last_error.restype = ctypes.c_char_p
+    assert isinstance(libcr.cr_last_error(), bytes)
+
+
+def test_create_rejects_bad_arguments(libcr):
+    libcr.cr_create.restype = ctypes.c_int
+    # NULL out pointer: rejected before any device call
+    assert libcr.cr_create(None, 0, None, None, None) == 1
+    # only one of alloc/free given
+    h = ctypes.c_void_p()
+    fn = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)(lambda *a: None)
+    assert libcr.cr_create(ctypes.byref(h), 0, fn, None, None) == 1
+
+
+def test_null_context_calls_fail_cleanly(libcr):
+    libcr.cr_persistence.restype = ctypes.c_int
+    assert libcr.cr_persistence(None, None, 2, None, 1, 0, None, None) == 1
+    libcr.cr_persistence_backward.restype = ctypes.c_int
+    assert libcr.cr_persistence_backward(None, None, None, None, None, 0, None, 0, None) == 1
+
+
+def test_package_does_not_import_the_oracle():
+    code = ("import sys; sys.path.insert(0, %r); import paper_2005_12692_amd; "
+            "assert 'oracle' not in sys.modules; print('ok')" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
+    assert out.returncode == 0 and "ok" in out.stdout, out.stderr
+    src = open(os.path.join(ROOT, "paper_2005_12692_amd", "__init__.py")).read()
+    assert "oracle" not in src
+
+
+def test_no_gpu_means_an_error_not_a_fallback():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_2005_12692_amd as cr
+    with pytest.raises(Exception):
+        cr.persistence(torch.rand(8, 8))  # CPU tensor: refused

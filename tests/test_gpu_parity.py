@@ -1,0 +1,161 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU oracle.
+
+Every comparison is byte-for-byte on the five output arrays (dim, birth, death,
+birth_pixel, death_pixel) in canonical order: the bar end points are copies of
+input values and the pixel map is fixed by the written convention, so exact
+equality is the bar.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2005_12692_amd as cr
+import synth
+
+pytestmark = pytest.mark.gpu
+FIELDS = ("dim", "birth", "death", "birth_pixel", "death_pixel")
+
+
+def gpu_diag(img, maxdim=None):
+    d = cr.persistence(torch.from_numpy(np.ascontiguousarray(img)).cuda(), maxdim)
+    return [t.cpu().numpy() for t in d]
+
+
+def oracle_diag(img, maxdim=None):
+    o = oracle.persistence(img, maxdim)
+    return [o.dim, o.birth, o.death, o.birth_pixel, o.death_pixel]
+
+
+def assert_same(got, want, label=""):
+    for name, g, w in zip(FIELDS, got, want):
+        if g.shape != w.shape or not np.array_equal(g.view(np.uint8), w.view(np.uint8)):
+            msg = [f"{label}: field {name} differs: gpu {g.shape} oracle {w.shape}",
+                   f"rows per dim gpu {np.bincount(got[0], minlength=3)} oracle {np.bincount(want[0], minlength=3)}"]
+            n = min(len(g), len(w))
+            bad = np.flatnonzero(g[:n].view(np.uint8).reshape(n, -1).any(1) !=
+                                 w[:n].view(np.uint8).reshape(n, -1).any(1)) if n else []
+            first = next((i for i in range(n) if g[i].tobytes() != w[i].tobytes()), None)
+            if first is not None:
+                msg.append(f"first differing row {first}: gpu {[x[first] for x in got]} "
+                           f"oracle {[x[first] for x in want]}")
+            raise AssertionError("\n".join(msg))
+
+
+def check(img, maxdim=None, label=""):
+    assert_same(gpu_diag(img, maxdim), oracle_diag(img, maxdim), label or str(img.shape))
+
+
+TINY_2D = [(1, 1), (1, 2), (2, 1), (2, 2), (1, 9), (9, 1), (3, 3), (2, 5), (4, 5), (7, 3)]
+
+
+@pytest.mark.parametrize("shape", TINY_2D)
+def test_tiny_2d(shape):
+    rng = np.random.default_rng(sum(shape))
+    for levels in (2, 3, 1000):
+        for _ in range(4):
+            img = rng.integers(0, levels, size=shape).astype(np.float32)
+            check(img, label=f"{shape} levels={levels}")
+
+
+@pytest.mark.parametrize("name", ["ttk", "fig2", "void"])
+def test_worked_examples(name):
+    if name == "ttk":
+        img = np.array([[0, 0, 0], [0, 9, 0], [0, 0, 0]], np.float32)
+    elif name == "fig2":
+        img = np.array([[-1, 1, -2], [3, 3, 2], [3, 3, -1]], np.float32)
+    else:
+        img = np.zeros((3, 3, 3), np.float32)
+        img[1, 1, 1] = 9
+    check(img, label=name)
+
+
+def test_uniform_64x64_seeds():
+    """64x64 i.i.d. uniform images, seeds 0..199."""
+    for seed in range(200):
+        check(synth.uniform2d((64, 64), seed), label=f"seed {seed}")
+
+
+@pytest.mark.parametrize("shape", [(33, 17), (100, 37), (5, 200), (257, 129), (31, 1000)])
+def test_ragged_2d(shape):
+    rng = np.random.default_rng(shape[0] * 7 + shape[1])
+    check(synth.uniform2d(shape, shape[0]), label=f"uniform {shape}")
+    check(synth.grf_seeded(shape, 2.0, shape[1]), label=f"grf {shape}")
+    check(rng.integers(0, 4, size=shape).astype(np.float32), label=f"ties {shape}")
+
+
+def test_special_values_2d():
+    check(np.full((17, 23), 1.5, np.float32), label="constant")
+    check((np.indices((20, 21)).sum(0) % 2).astype(np.float32), label="checkerboard")
+    img = synth.uniform2d((40, 40), 3)
+    img[10:20, 5:30] = np.inf
+    img[0, :] = -np.inf
+    check(img, label="infinities")
+    img = np.zeros((12, 12), np.float32)
+    img[::3, ::2] = -0.0
+    img[5, 5] = 1.0
+    check(img, label="negative zero")
+
+
+def test_grf_1024():
+    """The 2D workload: 1024x1024 Gaussian random field, sigma 4."""
+    check(synth.config("C2"), label="C2")
+
+
+TINY_3D = [(2, 2, 2), (1, 4, 5), (3, 1, 4), (2, 3, 1), (3, 4, 5), (5, 3, 2)]
+
+
+@pytest.mark.parametrize("shape", TINY_3D)
+def test_tiny_3d(shape):
+    rng = np.random.default_rng(sum(shape) + 100)
+    for levels in (2, 3, 1000):
+        for _ in range(4):
+            img = rng.integers(0, levels, size=shape).astype(np.float32)
+            check(img, label=f"{shape} levels={levels}")
+
+
+@pytest.mark.parametrize("shape", [(9, 8, 10), (17, 16, 15), (6, 33, 5), (20, 20, 20)])
+def test_ragged_3d(shape):
+    rng = np.random.default_rng(sum(shape))
+    check(synth.grf_seeded(shape, 1.5, 1), label=f"grf {shape}")
+    check(rng.random(shape, dtype=np.float32), label=f"uniform {shape}")
+    check(rng.integers(0, 3, size=shape).astype(np.float32), label=f"ties {shape}")
+
+
+@pytest.mark.parametrize("n", [24, 48, 64])
+def test_blobs_3d(n):
+    """The 3D workload's recipe at sizes the oracle finishes in seconds."""
+    check(synth.blobs3d(n, 2), label=f"blobs {n}")
+
+
+def test_maxdim():
+    vol = synth.grf_seeded((14, 13, 12), 1.5, 5)
+    for md in (0, 1, 2, 7):
+        check(vol, maxdim=md, label=f"maxdim {md}")
+    img = synth.uniform2d((30, 30), 4)
+    for md in (0, 1, 3):
+        check(img, maxdim=md, label=f"2d maxdim {md}")
+
+
+def test_nan_and_bad_arguments():
+    img = synth.uniform2d((16, 16), 1)
+    img[3, 4] = np.nan
+    with pytest.raises(cr.CRError) as e:
+        cr.persistence(torch.from_numpy(img).cuda())
+    assert e.value.code == cr.CR_ERR_NAN_INPUT
+    with pytest.raises(cr.CRError) as e:
+        cr.persistence(torch.rand(8, 8, device="cuda"), maxdim=-1)
+    assert e.value.code == cr.CR_ERR_INVALID_ARGUMENT
+    with pytest.raises((TypeError, ValueError)):
+        cr.persistence(torch.rand(8, device="cuda"))
+    # the context is still usable after errors
+    check(synth.uniform2d((16, 16), 2), label="after errors")
+
+
+def test_deterministic_repeat():
+    vol = synth.blobs3d(40, 7)
+    x = torch.from_numpy(vol).cuda()
+    a = [t.cpu().numpy() for t in cr.persistence(x)]
+    for _ in range(5):
+        b = [t.cpu().numpy() for t in cr.persistence(x)]
+        assert_same(b, a, "repeat")
