@@ -73,6 +73,9 @@ void cr_destroy(cr_context* ctx);
  * call on this thread.  Never NULL. */
 const char* cr_last_error(void);
 
+/* flags bits */
+#define CR_FLAG_STAGE_TIMES 1u /* record HIP events between stages (see cr_get_stage_times) */
+
 /* A diagram in structure-of-arrays form.  The five arrays are device pointers
  * into one block allocated by the plain call (through the context allocator);
  * the caller owns it and releases it with cr_diagram_free. */
@@ -92,7 +95,7 @@ typedef struct cr_diagram {
  *   image : device, prod(shape) floats, C order; not modified, not retained.
  *   ndim  : 2 or 3.  shape : host, ndim extents >= 1, C order.
  *   maxdim: highest dimension reported; >= 0, clamped to ndim-1.
- *   flags : must be 0.
+ *   flags : 0 or CR_FLAG_STAGE_TIMES.
  * Synchronises `stream` once (to learn the number of rows), then allocates
  * `out` and enqueues the final copy on `stream`.  Errors: INVALID_ARGUMENT,
  * NAN_INPUT, TOO_LARGE (more than 2^30 cells), OUT_OF_MEMORY, HIP, INTERNAL. */
@@ -148,8 +151,22 @@ typedef struct cr_stats {
   int64_t survivors[4]; /* cells of each dimension left after apparent pairs */
   int64_t n_rows;       /* rows of positive length, essential bars included */
   int64_t arena_used;   /* 64-bit entries of column storage used by the reduction */
+  int64_t red_adds;     /* column additions performed by the reduction */
+  int64_t red_merged;   /* list entries read by those additions */
+  int64_t red_max_col;  /* longest working column of the reduction */
+  int64_t red_rounds;   /* rounds of the degree-1 reduction (plain call) */
 } cr_stats;
 cr_status cr_get_stats(cr_context* ctx, cr_stats* out);
+
+/* Stage durations in milliseconds of the last plain call made with
+ * CR_FLAG_STAGE_TIMES, measured with HIP events on the call's stream, in this
+ * order: 0 stencil (filtration, apparent pairs, survivor compaction), 1 sort of
+ * the surviving cells, 2 degree 0 (forest roots and union-find), 3 degree 1
+ * (dual union-find of an image, or the coboundary reduction of a volume),
+ * 4 degree 2 of a volume (dual union-find), 5 sort of the output rows.  A stage
+ * that did not run reports 0.  Writes min(capacity, 6) values and sets
+ * *n_stages = 6. */
+cr_status cr_get_stage_times(cr_context* ctx, float* ms, int capacity, int* n_stages);
 
 #ifdef __cplusplus
 }

@@ -43,7 +43,9 @@ class _Diagram(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("n_pixels", ctypes.c_int64), ("n_cells", ctypes.c_int64),
                 ("survivors", ctypes.c_int64 * 4), ("n_rows", ctypes.c_int64),
-                ("arena_used", ctypes.c_int64)]
+                ("arena_used", ctypes.c_int64), ("red_adds", ctypes.c_int64),
+                ("red_merged", ctypes.c_int64), ("red_max_col", ctypes.c_int64),
+                ("red_rounds", ctypes.c_int64)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -94,8 +96,9 @@ def lib():
         L.cr_sync_status.argtypes = [vp, vp]
         L.cr_persistence_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, i64, vp]
         L.cr_get_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
+        L.cr_get_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
         for f in ("cr_create", "cr_persistence", "cr_persistence_batched", "cr_sync_status",
-                  "cr_persistence_backward", "cr_get_stats"):
+                  "cr_persistence_backward", "cr_get_stats", "cr_get_stage_times"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -142,8 +145,15 @@ def _view(block: torch.Tensor, base: int, ptr: int, n: int, dtype, itemsize: int
     return block[off:off + n * itemsize].view(dtype)
 
 
-def persistence(image: torch.Tensor, maxdim: int | None = None) -> Diagram:
-    """Persistence diagram of a 2D image or 3D volume (float32, on the GPU)."""
+CR_FLAG_STAGE_TIMES = 1
+STAGES = ("stencil", "sort_cells", "degree0", "degree1", "degree2", "sort_rows")
+
+
+def persistence(image: torch.Tensor, maxdim: int | None = None, stage_times: bool = False) -> Diagram:
+    """Persistence diagram of a 2D image or 3D volume (float32, on the GPU).
+
+    With ``stage_times`` the library records HIP events between its stages;
+    read them with ``stage_times()``."""
     image = _check_image(image)
     h, dev = _context(image.device)
     if maxdim is None:
@@ -151,7 +161,8 @@ def persistence(image: torch.Tensor, maxdim: int | None = None) -> Diagram:
     shape = (ctypes.c_int64 * image.dim())(*image.shape)
     out = _Diagram()
     _alloc_dev[0] = dev
-    _check(lib().cr_persistence(h, ctypes.c_void_p(image.data_ptr()), image.dim(), shape, int(maxdim), 0,
+    _check(lib().cr_persistence(h, ctypes.c_void_p(image.data_ptr()), image.dim(), shape, int(maxdim),
+                                CR_FLAG_STAGE_TIMES if stage_times else 0,
                                 _stream(image.device), ctypes.byref(out)))
     n = int(out.n)
     if n == 0:
@@ -305,10 +316,21 @@ class PersistenceBatchedFn(torch.autograd.Function):
         return grad, None, None
 
 
+def stage_times(device=None) -> dict:
+    """Stage durations (ms) of the last ``persistence(..., stage_times=True)`` call."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    h, _ = _context(dev)
+    ms = (ctypes.c_float * 6)()
+    n = ctypes.c_int()
+    _check(lib().cr_get_stage_times(h, ms, 6, ctypes.byref(n)))
+    return {name: float(ms[i]) for i, name in enumerate(STAGES)}
+
+
 def stats(device=None) -> dict:
     dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
     h, _ = _context(dev)
     s = _Stats()
     _check(lib().cr_get_stats(h, ctypes.byref(s)))
     return {"n_pixels": s.n_pixels, "n_cells": s.n_cells, "survivors": list(s.survivors),
-            "n_rows": s.n_rows, "arena_used": s.arena_used}
+            "n_rows": s.n_rows, "arena_used": s.arena_used, "red_adds": s.red_adds,
+            "red_merged": s.red_merged, "red_max_col": s.red_max_col, "red_rounds": s.red_rounds}

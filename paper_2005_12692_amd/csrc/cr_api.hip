@@ -7,7 +7,7 @@
 #include <algorithm>
 
 #include "cr.h"
-#include "cr_emit.h"
+#include "cr_reduce.h"
 
 namespace cr {
 // launchers defined in the kernel translation units
@@ -21,7 +21,7 @@ void launch_h0(int grid, const uint64_t* skeys, const unsigned long long* dim_co
                Layout L, int32_t* vlink, uint64_t* T, uint8_t* neg, const EmitCtx& E, Status* st,
                hipStream_t s);
 void launch_dual(int grid, int top, const uint64_t* skeys, const unsigned long long* dim_count,
-                 const ImgDesc* imgs, Layout L, int32_t* tlink, const uint8_t* neg, const int32_t* owner,
+                 const ImgDesc* imgs, Layout L, int32_t* tlink, const uint8_t* neg, uint8_t* mark, int emit,
                  uint64_t* T, const EmitCtx& E, Status* st, hipStream_t s);
 struct RedCtx;
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
@@ -32,11 +32,9 @@ void launch_img_offsets(const uint32_t* cnt, const uint32_t* img_status, int nim
                         int32_t* status, hipStream_t s);
 void launch_backward(const int64_t* bpix, const int64_t* dpix, const float* gb, const float* gd, int64_t n,
                      float* grad, int64_t n_pixels, uint32_t* bad, hipStream_t s);
-void launch_h1_reduce_raw(int grid, const float* img, const ImgDesc* imgs, Layout L, const uint64_t* skeys,
-                          const unsigned long long* dim_count, const uint8_t* neg, int32_t* owner,
-                          uint64_t* piv, uint64_t* col_ptr, uint64_t* arena, uint64_t arena_cap,
-                          unsigned long long* arena_top, Status* st, const EmitCtx& E, hipStream_t s);
+void launch_check_empty(const unsigned long long* count, Status* st, hipStream_t s);
 constexpr int SORT_HIST_WORDS = 256 * 1024;
+
 }  // namespace cr
 
 using namespace cr;
@@ -66,7 +64,7 @@ int bits_for(uint64_t x) {  // smallest b with x < 2^b
 constexpr int TILE2[3] = {1, 8, 32};  // z y x extents of a 2D stencil tile
 constexpr int TILE3[3] = {4, 4, 16};  // of a 3D stencil tile
 constexpr int KGRID = 2048;           // workgroups of the grid-stride kernels
-constexpr int RGRID = 1024;           // workgroups of the reduction
+constexpr int RGRID = 512;            // workgroups of the reduction (256 threads each)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -80,7 +78,7 @@ struct Problem {
 
 struct Plan {
   size_t status, counters, img_status, img_pairs, imgs, tiles, surv_a, surv_b, hist, vlink, tlink, T, neg,
-      owner, piv, colptr, arena, total;
+      owner, claim, piv, colptr, arena, pbuf, cleared, list0, list1, total;
   uint64_t surv_cap, e_cap, arena_cap;
 };
 
@@ -97,18 +95,25 @@ struct cr_context {
   size_t host_stage_bytes = 0;
   hipEvent_t stage_done = nullptr;
   bool stage_pending = false;
-  uint64_t arena_entries = 1ull << 26;
+  uint64_t arena_entries = 1ull << 28;
   Plan plan{};
   Problem prob{};
   cr_stats stats{};
   bool last_batched_valid = false;
   uint32_t* bwd_flag = nullptr;  // device word for the backward index check
+  bool sync_allowed = false;     // the plain call may synchronise between reduction rounds
+  int rounds = 0;
+  // stage timing (CR_FLAG_STAGE_TIMES)
+  hipEvent_t ev[8] = {};
+  bool ev_ready = false;
+  bool timing = false;
+  float stage_ms[6] = {};
 };
 
 namespace {
 
 // counters block: surv_count, dim_count[4], cand_count, arena_top, spare
-enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_WORDS = 8 };
+enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* two words */, C_WORDS = 10 };
 
 cr_status build_problem(Problem& pb, int nimg, const int64_t* pixel_offsets, const int64_t* shapes, int ndim,
                         int maxdim) {
@@ -197,6 +202,11 @@ Plan make_plan(const Problem& pb, uint64_t arena_entries) {
   p.piv = take(vol ? 8 * p.e_cap : 0);
   p.colptr = take(vol ? 8 * p.e_cap : 0);
   p.arena = take(8 * p.arena_cap);
+  p.pbuf = take(vol ? 8 * PBUF_PER_THREAD * RGRID * 256 : 0);
+  p.cleared = take(vol ? p.e_cap : 0);
+  p.claim = take(vol ? 4 * 3 * pb.P : 0);
+  p.list0 = take(vol ? 4 * p.e_cap : 0);
+  p.list1 = take(vol ? 4 * p.e_cap : 0);
   p.total = o;
   return p;
 }
@@ -242,6 +252,50 @@ T* at(cr_context* ctx, size_t off) {
   return reinterpret_cast<T*>(ctx->scratch + off);
 }
 
+// stage boundaries; A and B close the two higher-degree stages (2D: degree 1
+// then nothing; 3D: degree 2 then degree 1)
+enum { EV_START = 0, EV_STENCIL, EV_SORT, EV_H0, EV_A, EV_B, EV_ROWS, EV_N };
+
+// Records stage boundary `i` when stage timing is on.
+void mark(cr_context* ctx, int i, hipStream_t s) {
+  if (ctx->timing) (void)hipEventRecord(ctx->ev[i], s);
+}
+
+// Rounds of the degree-1 reduction.  With host synchronisation allowed (plain
+// call) the host checks the active count every ROUND_BATCH rounds; otherwise a
+// fixed budget of rounds is enqueued (rounds with an empty list return at once)
+// and a leftover list raises the iteration flag.
+constexpr int ROUND_BATCH = 4;
+constexpr int ROUND_BUDGET = 96;
+constexpr int ROUND_LIMIT = 4096;
+
+cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[2], unsigned long long* counts,
+                     hipStream_t s) {
+  ctx->rounds = 0;
+  if (!ctx->sync_allowed) {
+    launch_h1_rounds(RGRID, R, lists, counts, 0, ROUND_BUDGET, s);
+    launch_check_empty(counts + (ROUND_BUDGET & 1), R.st, s);
+    return CR_OK;
+  }
+  for (int r = 0; r < ROUND_LIMIT; r += ROUND_BATCH) {
+    launch_h1_rounds(RGRID, R, lists, counts, r, ROUND_BATCH, s);
+    const int cur = (r + ROUND_BATCH) & 1;
+    cr_status rc = ensure_stage(ctx, 64);
+    if (rc != CR_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(ctx->host_stage, counts + cur, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ctx->host_stage + 8, &R.st->abort, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    unsigned long long left = 0;
+    uint32_t ab = 0;
+    std::memcpy(&left, ctx->host_stage, 8);
+    std::memcpy(&ab, ctx->host_stage + 8, 4);
+    ctx->rounds = r + ROUND_BATCH;
+    if (left == 0 || ab) return CR_OK;
+  }
+  launch_check_empty(counts + (ROUND_LIMIT & 1), R.st, s);
+  return CR_OK;
+}
+
 // Enqueues every stage up to sorted canonical keys.  Returns the buffer holding them.
 cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, uint64_t** cand_out) {
   const Problem& pb = ctx->prob;
@@ -272,10 +326,13 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
   uint64_t* surv_tmp = at<uint64_t>(ctx, p.surv_b);
   int32_t* vlink = at<int32_t>(ctx, p.vlink);
   int32_t* tlink = at<int32_t>(ctx, p.tlink);
+  mark(ctx, EV_START, s);
   launch_apparent(pb.ndim, (int)pb.tiles.size(), image, d_imgs, d_tiles, L, surv, p.surv_cap, &cnt[C_SURV],
                   &cnt[C_DIM], vlink, tlink, img_status, st, s);
+  mark(ctx, EV_STENCIL, s);
   uint32_t* hist = at<uint32_t>(ctx, p.hist);
   uint64_t* skeys = launch_sort(surv, surv_tmp, &cnt[C_SURV], p.surv_cap, 2 + L.ib + 32 + L.kb, hist, s);
+  mark(ctx, EV_SORT, s);
   uint64_t* cand = (skeys == surv) ? surv_tmp : surv;  // the other buffer collects the rows
 
   EmitCtx E;
@@ -292,23 +349,38 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
   launch_fill_u32(reinterpret_cast<uint32_t*>(neg), 0, p.e_cap / 4, s);
   uint64_t* T = at<uint64_t>(ctx, p.T);
   launch_h0(KGRID, skeys, &cnt[C_DIM], d_imgs, L, vlink, T, neg, E, st, s);
+  mark(ctx, EV_H0, s);
 
   int32_t* owner = at<int32_t>(ctx, p.owner);
-  if (pb.maxdim >= 1) {
-    if (pb.ndim == 2) {
-      launch_dual(KGRID, 2, skeys, &cnt[C_DIM], d_imgs, L, tlink, neg, nullptr, T, E, st, s);
-    } else {
-      launch_fill_u32(reinterpret_cast<uint32_t*>(owner), 0xFFFFFFFFu, 3 * pb.P, s);
-      launch_h1_reduce_raw(RGRID, image, d_imgs, L, skeys, &cnt[C_DIM], neg, owner, at<uint64_t>(ctx, p.piv),
-                           at<uint64_t>(ctx, p.colptr), at<uint64_t>(ctx, p.arena), p.arena_cap, &cnt[C_ARENA],
-                           st, E, s);
-      if (pb.maxdim >= 2)
-        launch_dual(KGRID, 3, skeys, &cnt[C_DIM], d_imgs, L, tlink, neg, owner, T, E, st, s);
-    }
+  if (pb.ndim == 2) {
+    if (pb.maxdim >= 1) launch_dual(KGRID, 2, skeys, &cnt[C_DIM], d_imgs, L, tlink, neg, nullptr, 1, T, E, st, s);
+    mark(ctx, EV_A, s);
+    mark(ctx, EV_B, s);
+  } else if (pb.maxdim >= 1) {
+    // degree 2 first (dual union-find over every surviving square); it marks the
+    // squares that give birth to a void, whose degree-1 columns are zero
+    uint8_t* cleared = at<uint8_t>(ctx, p.cleared);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(cleared), 0, p.e_cap / 4, s);
+    launch_dual(KGRID, 3, skeys, &cnt[C_DIM], d_imgs, L, tlink, nullptr, cleared, pb.maxdim >= 2, T, E, st, s);
+    mark(ctx, EV_A, s);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(owner), 0xFFFFFFFFu, 3 * pb.P, s);
+    launch_fill_u32(at<uint32_t>(ctx, p.claim), 0x7FFFFFFFu, 3 * pb.P, s);
+    const RedCtx R = make_redctx(image, d_imgs, L, skeys, &cnt[C_DIM], cleared, owner, at<int32_t>(ctx, p.claim),
+                                 at<uint64_t>(ctx, p.piv), at<uint64_t>(ctx, p.colptr), at<uint64_t>(ctx, p.arena),
+                                 p.arena_cap, &cnt[C_ARENA], at<uint64_t>(ctx, p.pbuf), st);
+    uint32_t* lists[2] = {at<uint32_t>(ctx, p.list0), at<uint32_t>(ctx, p.list1)};
+    cr_status rrc = run_rounds(ctx, R, lists, &cnt[C_LIST], s);
+    if (rrc != CR_OK) return rrc;
+    launch_h1_emit(KGRID, R, E, s);
+    mark(ctx, EV_B, s);
+  } else {
+    mark(ctx, EV_A, s);
+    mark(ctx, EV_B, s);
   }
   // canonical order: sort the row keys.  The survivor keys are dead now, so
   // their buffer is the scratch of this sort.
   *cand_out = launch_sort(cand, skeys, &cnt[C_CAND], p.surv_cap, L.ib + 2 + 2 * L.pb, hist, s);
+  mark(ctx, EV_ROWS, s);
   return CR_OK;
 }
 
@@ -325,6 +397,17 @@ cr_status read_counters(cr_context* ctx, hipStream_t s, HostCounters* h) {
   HIP_TRY(hipMemcpyAsync(ctx->host_stage + sizeof(Status), ctx->scratch + p.counters, 8 * C_WORDS,
                          hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (ctx->timing) {
+    float ms[6] = {};
+    for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&ms[i], ctx->ev[i], ctx->ev[i + 1]);
+    const bool vol = ctx->prob.ndim == 3;
+    ctx->stage_ms[0] = ms[0];
+    ctx->stage_ms[1] = ms[1];
+    ctx->stage_ms[2] = ms[2];
+    ctx->stage_ms[3] = vol ? ms[4] : ms[3];  // degree 1
+    ctx->stage_ms[4] = vol ? ms[3] : 0.0f;   // degree 2
+    ctx->stage_ms[5] = ms[5];
+  }
   std::memcpy(&h->st, ctx->host_stage, sizeof(Status));
   std::memcpy(h->cnt, ctx->host_stage + sizeof(Status), 8 * C_WORDS);
   cr_stats& S = ctx->stats;
@@ -333,6 +416,10 @@ cr_status read_counters(cr_context* ctx, hipStream_t s, HostCounters* h) {
   for (int i = 0; i < 4; ++i) S.survivors[i] = (int64_t)h->cnt[C_DIM + i];
   S.n_rows = (int64_t)h->cnt[C_CAND];
   S.arena_used = (int64_t)h->cnt[C_ARENA];
+  S.red_adds = (int64_t)h->st.adds;
+  S.red_merged = (int64_t)h->st.merged;
+  S.red_max_col = (int64_t)h->st.max_col;
+  S.red_rounds = ctx->rounds;
   return CR_OK;
 }
 
@@ -340,8 +427,13 @@ cr_status status_error(const Status& st, bool* arena_overflow) {
   *arena_overflow = false;
   if (st.nan_input) return fail(CR_ERR_NAN_INPUT, "input contains NaN");
   if (st.overflow) {
-    *arena_overflow = true;
-    return fail(CR_ERR_OUT_OF_MEMORY, "scratch capacity exceeded");
+    *arena_overflow = (st.overflow & OVF_ARENA) != 0;
+    std::string what;
+    if (st.overflow & OVF_SURVIVORS) what += " survivors";
+    if (st.overflow & OVF_ARENA) what += " column-arena";
+    if (st.overflow & OVF_ROWS) what += " rows";
+    if (st.overflow & OVF_COLUMN) what += " column-length";
+    return fail(CR_ERR_OUT_OF_MEMORY, "scratch capacity exceeded:" + what);
   }
   if (st.iter_cap) return fail(CR_ERR_INTERNAL, "iteration cap reached");
   if (st.internal) return fail(CR_ERR_INTERNAL, "internal consistency check failed");
@@ -385,6 +477,8 @@ void cr_destroy(cr_context* ctx) {
   if (ctx->bwd_flag) (void)hipFree(ctx->bwd_flag);
   if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
   if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
+  if (ctx->ev_ready)
+    for (int i = 0; i < EV_N; ++i) (void)hipEventDestroy(ctx->ev[i]);
   delete ctx;
 }
 
@@ -395,8 +489,14 @@ cr_status cr_persistence(cr_context* ctx, const float* image, int ndim, const in
   out->dim = nullptr; out->birth = nullptr; out->death = nullptr;
   out->birth_pixel = nullptr; out->death_pixel = nullptr; out->block = nullptr;
   if (!image) return fail(CR_ERR_INVALID_ARGUMENT, "image is NULL");
-  if (flags != 0) return fail(CR_ERR_INVALID_ARGUMENT, "flags must be 0");
+  if (flags & ~CR_FLAG_STAGE_TIMES) return fail(CR_ERR_INVALID_ARGUMENT, "unknown flags");
   HIP_TRY(hipSetDevice(ctx->device));
+  if ((flags & CR_FLAG_STAGE_TIMES) && !ctx->ev_ready) {
+    for (int i = 0; i < EV_N; ++i) HIP_TRY(hipEventCreate(&ctx->ev[i]));
+    ctx->ev_ready = true;
+  }
+  ctx->timing = (flags & CR_FLAG_STAGE_TIMES) != 0;
+  ctx->sync_allowed = true;
   hipStream_t s = (hipStream_t)stream;
   cr_status rc = build_problem(ctx->prob, 1, nullptr, shape, ndim, maxdim);
   if (rc != CR_OK) return rc;
@@ -413,7 +513,7 @@ cr_status cr_persistence(cr_context* ctx, const float* image, int ndim, const in
     bool arena_over = false;
     rc = status_error(h.st, &arena_over);
     if (rc != CR_OK) {
-      if (arena_over && h.cnt[C_ARENA] > ctx->plan.arena_cap && attempt < 3) {
+      if (arena_over && attempt < 3) {
         ctx->arena_entries = std::max<uint64_t>(ctx->arena_entries * 4, h.cnt[C_ARENA] * 2);
         continue;  // rerun with a larger column arena
       }
@@ -480,6 +580,8 @@ cr_status cr_persistence_batched(cr_context* ctx, int n_images, const float* pac
   if (pixel_offsets[0] != 0) return fail(CR_ERR_INVALID_ARGUMENT, "pixel_offsets[0] must be 0");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
+  ctx->timing = false;
+  ctx->sync_allowed = false;
   ctx->last_batched_valid = false;
   cr_status rc = build_problem(ctx->prob, n_images, pixel_offsets, shapes, ndim, maxdim);
   if (rc != CR_OK) return rc;
@@ -537,6 +639,13 @@ cr_status cr_persistence_backward(cr_context* ctx, const int64_t* birth_pixel, c
   uint32_t hb = 0;
   std::memcpy(&hb, ctx->host_stage, 4);
   if (hb) return fail(CR_ERR_INVALID_ARGUMENT, "a pixel index is out of range");
+  return CR_OK;
+}
+
+cr_status cr_get_stage_times(cr_context* ctx, float* ms, int capacity, int* n_stages) {
+  if (!ctx || (capacity > 0 && !ms)) return fail(CR_ERR_INVALID_ARGUMENT, "NULL argument");
+  for (int i = 0; i < 6 && i < capacity; ++i) ms[i] = ctx->stage_ms[i];
+  if (n_stages) *n_stages = 6;
   return CR_OK;
 }
 

@@ -39,7 +39,7 @@ __device__ inline void emit_rows(const EmitCtx& E, bool active, int img, uint64_
       E.cand[pos] = ckey;
       atomicAdd(&E.img_pairs[img], 1u);
     } else {
-      raise_flag(E.st, &E.st->overflow);
+      raise_flag(E.st, &E.st->overflow, OVF_ROWS);
     }
   }
 }

@@ -36,12 +36,15 @@ struct Layout {
 // Device-side status words (all zero on success).
 struct Status {
   uint32_t nan_input;      // some input pixel was NaN
-  uint32_t overflow;       // a capacity was exceeded (survivors, arena, candidates)
+  uint32_t overflow;       // a capacity was exceeded: OVF_* bits
   uint32_t internal;       // an invariant of the algorithm failed (bug guard)
   uint32_t iter_cap;       // a bounded loop hit its iteration cap
   uint32_t abort;          // set together with any of the above: stop early
-  uint32_t pad[3];
+  uint32_t max_col;        // longest column seen by the reduction
+  unsigned long long adds; // column additions performed by the reduction
+  unsigned long long merged;  // list entries read by those additions
 };
+enum : uint32_t { OVF_SURVIVORS = 1, OVF_ARENA = 2, OVF_ROWS = 4, OVF_COLUMN = 8 };
 
 __host__ __device__ inline uint32_t ord32_bits(uint32_t u) {
   return (u >> 31) ? ~u : (u | 0x80000000u);
@@ -142,8 +145,8 @@ __device__ inline bool cas32_rel(int32_t* p, int32_t expected, int32_t desired) 
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline void raise_flag(Status* st, uint32_t* word) {
-  atomicOr(word, 1u);
+__device__ inline void raise_flag(Status* st, uint32_t* word, uint32_t bits = 1u) {
+  atomicOr(word, bits);
   atomicOr(&st->abort, 1u);
 }
 __device__ inline bool aborted(const Status* st) {

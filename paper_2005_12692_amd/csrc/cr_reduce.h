@@ -1,0 +1,43 @@
+// Shared between the degree-1 reduction kernels and the host layer.
+#pragma once
+#include "cr_emit.h"
+
+namespace cr {
+
+constexpr uint32_t RED_ITER_CAP = 1u << 24;
+constexpr uint32_t FCAP = 64;              // front list capacity
+constexpr uint32_t FBUF = 2 * FCAP + 8;    // front buffer entries (F plus an addend)
+constexpr uint32_t PCAP = 1024;            // private tail buffer entries
+
+struct RedCtx {
+  const float* img;
+  const ImgDesc* imgs;
+  Layout L;
+  const uint64_t* skeys;
+  const unsigned long long* dim_count;
+  const uint8_t* cleared;  // per square rank: 1 = birth of degree 2 (zero column)
+  int32_t* owner;          // per edge (3 * anchor pixel + axis of the edge): owning column, or -1
+  int32_t* claim;          // per edge: leftmost proposer of the current round, INT32_MAX if none
+  uint64_t* piv;           // per column: key of its pivot edge (the proposed one while active)
+  uint64_t* col_ptr;       // per column: (arena offset << 24) | length of its stored column
+  uint64_t* arena;
+  uint64_t arena_cap;
+  unsigned long long* arena_top;
+  uint64_t* pbuf;          // private buffers, PBUF_PER_THREAD entries per thread
+  Status* st;
+};
+constexpr uint64_t PBUF_PER_THREAD = 2 * FBUF + 2 * PCAP;
+
+RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64_t* skeys,
+                   const unsigned long long* dim_count, const uint8_t* cleared, int32_t* owner, int32_t* claim,
+                   uint64_t* piv, uint64_t* col_ptr, uint64_t* arena, uint64_t arena_cap,
+                   unsigned long long* arena_top, uint64_t* pbuf, Status* st);
+
+// Enqueues rounds [round0, round0 + nrounds) of the reduction.  lists/counts:
+// two ping-pong lists of column ids with their device counts; round r reads
+// the list r & 1 (round 0 reads every column) and builds the list (r + 1) & 1.
+void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[2], unsigned long long* counts, int round0,
+                      int nrounds, hipStream_t s);
+void launch_h1_emit(int grid, const RedCtx& R, const EmitCtx& E, hipStream_t s);
+
+}  // namespace cr

@@ -240,7 +240,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_apparent(
   for (int cs = 0; cs < NCELL; ++cs) {
     if (surv_mask & (1u << cs)) {
       if (pos < surv_cap) surv[pos] = keys[cs];
-      else raise_flag(st, &st->overflow);
+      else raise_flag(st, &st->overflow, OVF_SURVIVORS);
       ++pos;
     }
   }

@@ -172,22 +172,20 @@ __global__ void k_h0_emit(const uint64_t* __restrict__ skeys, const unsigned lon
   }
 }
 
-// Top degree on the dual graph.  Columns are the surviving (top-1)-cells that
-// are not deaths of degree top-2 (clearing): for top = 2 the edges not marked
-// by degree 0, for top = 3 the squares that own no pivot of degree 1.
+// Top degree on the dual graph.  For an image (top = 2) the columns are the
+// surviving edges that kill no component (clearing).  For a volume (top = 3)
+// every surviving square is a column: a square whose column would reduce to
+// zero closes a cycle of the dual graph and merges nothing, so no clearing is
+// needed, and degree 2 can run before degree 1.
 // level = n - 1 - i (larger key = earlier in the reversed order).
-__device__ inline bool dual_col_skipped(int top, uint64_t i, const uint8_t* neg, const int32_t* owner,
-                                        const ImgDesc& d, const int c[3]) {
-  if (top == 2) return neg[i] != 0;
-  const int orient = !(c[0] & 1) ? 0 : (!(c[1] & 1) ? 1 : 2);
-  return owner[3 * anchor_pixel(d, c) + orient] >= 0;
+__device__ inline bool dual_col_skipped(int top, uint64_t i, const uint8_t* neg) {
+  return top == 2 && neg[i] != 0;
 }
 
 __global__ void k_dual_merge(int top, const uint64_t* __restrict__ skeys,
                              const unsigned long long* __restrict__ dim_count,
                              const ImgDesc* __restrict__ imgs, Layout L, const int32_t* __restrict__ tlink,
-                             const uint8_t* __restrict__ neg, const int32_t* __restrict__ owner,
-                             uint64_t* __restrict__ T, Status* __restrict__ st) {
+                             const uint8_t* __restrict__ neg, uint64_t* __restrict__ T, Status* __restrict__ st) {
   uint64_t off, n;
   segment(dim_count, top - 1, &off, &n);
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
@@ -198,7 +196,7 @@ __global__ void k_dual_merge(int top, const uint64_t* __restrict__ skeys,
     const ImgDesc d = imgs[im];
     int c[3];
     kidx_coords(d, skey_kidx(L, k), c);
-    if (dual_col_skipped(top, i, neg, owner, d, c)) continue;
+    if (dual_col_skipped(top, i, neg)) continue;
     // the one even axis of the cell within the image's own dimensions
     const int a = (top == 2) ? ((c[1] & 1) ? 2 : 1) : (!(c[0] & 1) ? 0 : (!(c[1] & 1) ? 1 : 2));
     if (d.K[a] == 1) continue;  // no cofacet at all (a flat image): a loop at the exterior node
@@ -212,9 +210,11 @@ __global__ void k_dual_merge(int top, const uint64_t* __restrict__ skeys,
   }
 }
 
+// Rows of the top degree; with `mark`, also flags each column that gives birth
+// to a class (mark[column position] = 1), the clearing set of degree top-1.
 __global__ void k_dual_emit(int top, const uint64_t* __restrict__ skeys,
                             const unsigned long long* __restrict__ dim_count, const uint64_t* __restrict__ T,
-                            EmitCtx E) {
+                            uint8_t* __restrict__ mark, int emit, EmitCtx E) {
   if (aborted(E.st)) return;
   uint64_t offc, nc, offt, nt;
   segment(dim_count, top - 1, &offc, &nc);
@@ -232,7 +232,8 @@ __global__ void k_dual_emit(int top, const uint64_t* __restrict__ skeys,
       if (s == TRIP_INF || s >= nc) {
         raise_flag(E.st, &E.st->internal);  // a top cell that never dies: impossible in a box
       } else {
-        active = pair_row(E, skeys[offc + (nc - 1 - s)], skeys[offt + r], false, &im, &ck);
+        if (mark) mark[nc - 1 - s] = 1;
+        if (emit) active = pair_row(E, skeys[offc + (nc - 1 - s)], skeys[offt + r], false, &im, &ck);
       }
     }
     emit_rows(E, active, im, ck);
@@ -250,12 +251,12 @@ void launch_h0(int grid, const uint64_t* skeys, const unsigned long long* dim_co
 }
 
 void launch_dual(int grid, int top, const uint64_t* skeys, const unsigned long long* dim_count,
-                 const ImgDesc* imgs, Layout L, int32_t* tlink, const uint8_t* neg, const int32_t* owner,
+                 const ImgDesc* imgs, Layout L, int32_t* tlink, const uint8_t* neg, uint8_t* mark, int emit,
                  uint64_t* T, const EmitCtx& E, Status* st, hipStream_t s) {
   k_troot_init<<<grid, 256, 0, s>>>(skeys, dim_count, top, imgs, L, tlink, st);
   k_trip_init<<<grid, 256, 0, s>>>(T, dim_count, top, (uint32_t)L.nimg);
-  k_dual_merge<<<grid, 256, 0, s>>>(top, skeys, dim_count, imgs, L, tlink, neg, owner, T, st);
-  k_dual_emit<<<grid, 256, 0, s>>>(top, skeys, dim_count, T, E);
+  k_dual_merge<<<grid, 256, 0, s>>>(top, skeys, dim_count, imgs, L, tlink, neg, T, st);
+  k_dual_emit<<<grid, 256, 0, s>>>(top, skeys, dim_count, T, mark, emit, E);
 }
 
 }  // namespace cr

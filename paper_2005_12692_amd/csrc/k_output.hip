@@ -88,6 +88,15 @@ __global__ void k_backward(const int64_t* __restrict__ bpix, const int64_t* __re
   }
 }
 
+// Raises the iteration flag if a reduction list is still non-empty.
+__global__ void k_check_empty(const unsigned long long* count, Status* st) {
+  if (*count) raise_flag(st, &st->iter_cap);
+}
+
+void launch_check_empty(const unsigned long long* count, Status* st, hipStream_t s) {
+  k_check_empty<<<1, 1, 0, s>>>(count, st);
+}
+
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   if (!n) return;
   uint64_t blocks = (n + 255) / 256;
