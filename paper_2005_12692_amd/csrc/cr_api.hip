@@ -5,6 +5,7 @@
 #include <vector>
 #include <cstring>
 #include <algorithm>
+#include <cstdlib>
 
 #include "cr.h"
 #include "cr_reduce.h"
@@ -78,7 +79,7 @@ struct Problem {
 
 struct Plan {
   size_t status, counters, img_status, img_pairs, imgs, tiles, surv_a, surv_b, hist, vlink, tlink, T, neg,
-      owner, claim, piv, colptr, arena, pbuf, cleared, list0, list1, total;
+      owner, claim, piv, colptr, arena, pbuf, cleared, list[4], total;
   uint64_t surv_cap, e_cap, arena_cap;
 };
 
@@ -113,7 +114,7 @@ struct cr_context {
 namespace {
 
 // counters block: surv_count, dim_count[4], cand_count, arena_top, spare
-enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* two words */, C_WORDS = 10 };
+enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* four words */, C_WORDS = 12 };
 
 cr_status build_problem(Problem& pb, int nimg, const int64_t* pixel_offsets, const int64_t* shapes, int ndim,
                         int maxdim) {
@@ -205,8 +206,7 @@ Plan make_plan(const Problem& pb, uint64_t arena_entries) {
   p.pbuf = take(vol ? 8 * PBUF_PER_THREAD * RGRID * 256 : 0);
   p.cleared = take(vol ? p.e_cap : 0);
   p.claim = take(vol ? 4 * 3 * pb.P : 0);
-  p.list0 = take(vol ? 4 * p.e_cap : 0);
-  p.list1 = take(vol ? 4 * p.e_cap : 0);
+  for (int i = 0; i < 4; ++i) p.list[i] = take(vol ? 4 * p.e_cap : 0);
   p.total = o;
   return p;
 }
@@ -269,12 +269,12 @@ constexpr int ROUND_BATCH = 4;
 constexpr int ROUND_BUDGET = 96;
 constexpr int ROUND_LIMIT = 4096;
 
-cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[2], unsigned long long* counts,
+cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts,
                      hipStream_t s) {
   ctx->rounds = 0;
   if (!ctx->sync_allowed) {
     launch_h1_rounds(RGRID, R, lists, counts, 0, ROUND_BUDGET, s);
-    launch_check_empty(counts + (ROUND_BUDGET & 1), R.st, s);
+    launch_check_empty(counts + 2 * (ROUND_BUDGET & 1), R.st, s);
     return CR_OK;
   }
   for (int r = 0; r < ROUND_LIMIT; r += ROUND_BATCH) {
@@ -282,17 +282,17 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[2], unsig
     const int cur = (r + ROUND_BATCH) & 1;
     cr_status rc = ensure_stage(ctx, 64);
     if (rc != CR_OK) return rc;
-    HIP_TRY(hipMemcpyAsync(ctx->host_stage, counts + cur, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(ctx->host_stage + 8, &R.st->abort, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ctx->host_stage, counts + 2 * cur, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ctx->host_stage + 16, &R.st->abort, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    unsigned long long left = 0;
+    unsigned long long left[2] = {0, 0};
     uint32_t ab = 0;
-    std::memcpy(&left, ctx->host_stage, 8);
-    std::memcpy(&ab, ctx->host_stage + 8, 4);
+    std::memcpy(left, ctx->host_stage, 16);
+    std::memcpy(&ab, ctx->host_stage + 16, 4);
     ctx->rounds = r + ROUND_BATCH;
-    if (left == 0 || ab) return CR_OK;
+    if ((left[0] == 0 && left[1] == 0) || ab) return CR_OK;
   }
-  launch_check_empty(counts + (ROUND_LIMIT & 1), R.st, s);
+  launch_check_empty(counts + 2 * (ROUND_LIMIT & 1), R.st, s);
   return CR_OK;
 }
 
@@ -365,10 +365,15 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     mark(ctx, EV_A, s);
     launch_fill_u32(reinterpret_cast<uint32_t*>(owner), 0xFFFFFFFFu, 3 * pb.P, s);
     launch_fill_u32(at<uint32_t>(ctx, p.claim), 0x7FFFFFFFu, 3 * pb.P, s);
-    const RedCtx R = make_redctx(image, d_imgs, L, skeys, &cnt[C_DIM], cleared, owner, at<int32_t>(ctx, p.claim),
-                                 at<uint64_t>(ctx, p.piv), at<uint64_t>(ctx, p.colptr), at<uint64_t>(ctx, p.arena),
-                                 p.arena_cap, &cnt[C_ARENA], at<uint64_t>(ctx, p.pbuf), st);
-    uint32_t* lists[2] = {at<uint32_t>(ctx, p.list0), at<uint32_t>(ctx, p.list1)};
+    RedCtx R = make_redctx(image, d_imgs, L, skeys, &cnt[C_DIM], cleared, owner, at<int32_t>(ctx, p.claim),
+                           at<uint64_t>(ctx, p.piv), at<uint64_t>(ctx, p.colptr), at<uint64_t>(ctx, p.arena),
+                           p.arena_cap, &cnt[C_ARENA], at<uint64_t>(ctx, p.pbuf), st);
+    // thresholds between thread and block mode (CR_LONG_LEN / CR_YIELD_ITERS
+    // override them, e.g. to exercise block mode on small inputs)
+    if (const char* v = getenv("CR_LONG_LEN")) R.long_len = (uint32_t)strtoul(v, nullptr, 10);
+    if (const char* v = getenv("CR_YIELD_ITERS")) R.yield_iters = (uint32_t)strtoul(v, nullptr, 10);
+    uint32_t* lists[4] = {at<uint32_t>(ctx, p.list[0]), at<uint32_t>(ctx, p.list[1]), at<uint32_t>(ctx, p.list[2]),
+                          at<uint32_t>(ctx, p.list[3])};
     cr_status rrc = run_rounds(ctx, R, lists, &cnt[C_LIST], s);
     if (rrc != CR_OK) return rrc;
     launch_h1_emit(KGRID, R, E, s);

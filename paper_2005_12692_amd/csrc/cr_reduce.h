@@ -25,6 +25,8 @@ struct RedCtx {
   unsigned long long* arena_top;
   uint64_t* pbuf;          // private buffers, PBUF_PER_THREAD entries per thread
   Status* st;
+  uint32_t long_len;       // stored columns longer than this continue in block mode
+  uint32_t yield_iters;    // thread mode hands a column to block mode after this many additions
 };
 constexpr uint64_t PBUF_PER_THREAD = 2 * FBUF + 2 * PCAP;
 
@@ -34,9 +36,10 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
                    unsigned long long* arena_top, uint64_t* pbuf, Status* st);
 
 // Enqueues rounds [round0, round0 + nrounds) of the reduction.  lists/counts:
-// two ping-pong lists of column ids with their device counts; round r reads
-// the list r & 1 (round 0 reads every column) and builds the list (r + 1) & 1.
-void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[2], unsigned long long* counts, int round0,
+// two ping-pong pairs of column lists (short columns for thread mode, long ones
+// for block mode) with their device counts: round r reads pair r & 1 (round 0
+// reads every column) and builds pair (r + 1) & 1; list 2k is short, 2k+1 long.
+void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round0,
                       int nrounds, hipStream_t s);
 void launch_h1_emit(int grid, const RedCtx& R, const EmitCtx& E, hipStream_t s);
 

@@ -88,9 +88,9 @@ __global__ void k_backward(const int64_t* __restrict__ bpix, const int64_t* __re
   }
 }
 
-// Raises the iteration flag if a reduction list is still non-empty.
+// Raises the iteration flag if a pair of reduction lists is still non-empty.
 __global__ void k_check_empty(const unsigned long long* count, Status* st) {
-  if (*count) raise_flag(st, &st->iter_cap);
+  if (count[0] || count[1]) raise_flag(st, &st->iter_cap);
 }
 
 void launch_check_empty(const unsigned long long* count, Status* st, hipStream_t s) {

@@ -159,3 +159,24 @@ def test_deterministic_repeat():
     for _ in range(5):
         b = [t.cpu().numpy() for t in cr.persistence(x)]
         assert_same(b, a, "repeat")
+
+
+def test_block_mode_forced():
+    """Volumes whose columns are handed to the workgroup-per-column mode after a
+    few additions (thresholds lowered through the environment, which the
+    library reads at every call)."""
+    import os
+    rng = np.random.default_rng(5)
+    cases = [(synth.blobs3d(16, 1), "blobs 16"), (synth.blobs3d(24, 2), "blobs 24"),
+             (synth.blobs3d(40, 3), "blobs 40"),
+             (rng.integers(0, 3, size=(9, 10, 11)).astype(np.float32), "ties"),
+             (synth.grf_seeded((20, 18, 22), 1.5, 4), "grf")]
+    try:
+        for long_len, yield_iters in [("0", "2"), ("8", "8")]:
+            os.environ["CR_LONG_LEN"] = long_len
+            os.environ["CR_YIELD_ITERS"] = yield_iters
+            for img, label in cases:
+                check(img, label=f"{label} long_len={long_len}")
+    finally:
+        os.environ.pop("CR_LONG_LEN", None)
+        os.environ.pop("CR_YIELD_ITERS", None)
