@@ -14,8 +14,10 @@ namespace cr {
 // launchers defined in the kernel translation units
 void launch_apparent(int ndim, int ntiles, const float* img, const ImgDesc* imgs, const int4* tiles,
                      Layout L, uint64_t* surv, uint64_t surv_cap, unsigned long long* surv_count,
-                     unsigned long long* dim_count, int32_t* vlink, int32_t* tlink,
-                     uint32_t* img_status, Status* st, hipStream_t stream);
+                     int32_t* vlink, int32_t* tlink, uint8_t* eapp, uint32_t* img_status, Status* st,
+                     hipStream_t stream);
+void launch_dim_bounds(const uint64_t* keys, const unsigned long long* n_ptr, uint64_t cap, Layout L,
+                       unsigned long long* dim_count, hipStream_t s);
 uint64_t* launch_sort(uint64_t* keys, uint64_t* tmp, const unsigned long long* n_ptr, uint64_t cap, int bits,
                       uint32_t* hist, hipStream_t stream);
 void launch_h0(int grid, const uint64_t* skeys, const unsigned long long* dim_count, const ImgDesc* imgs,
@@ -79,7 +81,7 @@ struct Problem {
 
 struct Plan {
   size_t status, counters, img_status, img_pairs, imgs, tiles, surv_a, surv_b, hist, vlink, tlink, T, neg,
-      owner, claim, piv, colptr, arena, pbuf, cleared, list[4], total;
+      owner, claim, piv, colptr, arena, pbuf, cleared, list[4], eapp, total;
   uint64_t surv_cap, e_cap, arena_cap;
 };
 
@@ -207,6 +209,7 @@ Plan make_plan(const Problem& pb, uint64_t arena_entries) {
   p.cleared = take(vol ? p.e_cap : 0);
   p.claim = take(vol ? 4 * 3 * pb.P : 0);
   for (int i = 0; i < 4; ++i) p.list[i] = take(vol ? 4 * p.e_cap : 0);
+  p.eapp = take(vol ? 3 * pb.P : 0);
   p.total = o;
   return p;
 }
@@ -327,11 +330,13 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
   int32_t* vlink = at<int32_t>(ctx, p.vlink);
   int32_t* tlink = at<int32_t>(ctx, p.tlink);
   mark(ctx, EV_START, s);
+  uint8_t* eapp = (pb.ndim == 3 && pb.maxdim >= 1) ? at<uint8_t>(ctx, p.eapp) : nullptr;
   launch_apparent(pb.ndim, (int)pb.tiles.size(), image, d_imgs, d_tiles, L, surv, p.surv_cap, &cnt[C_SURV],
-                  &cnt[C_DIM], vlink, tlink, img_status, st, s);
+                  vlink, tlink, eapp, img_status, st, s);
   mark(ctx, EV_STENCIL, s);
   uint32_t* hist = at<uint32_t>(ctx, p.hist);
   uint64_t* skeys = launch_sort(surv, surv_tmp, &cnt[C_SURV], p.surv_cap, 2 + L.ib + 32 + L.kb, hist, s);
+  launch_dim_bounds(skeys, &cnt[C_SURV], p.surv_cap, L, &cnt[C_DIM], s);
   mark(ctx, EV_SORT, s);
   uint64_t* cand = (skeys == surv) ? surv_tmp : surv;  // the other buffer collects the rows
 
@@ -365,7 +370,7 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     mark(ctx, EV_A, s);
     launch_fill_u32(reinterpret_cast<uint32_t*>(owner), 0xFFFFFFFFu, 3 * pb.P, s);
     launch_fill_u32(at<uint32_t>(ctx, p.claim), 0x7FFFFFFFu, 3 * pb.P, s);
-    RedCtx R = make_redctx(image, d_imgs, L, skeys, &cnt[C_DIM], cleared, owner, at<int32_t>(ctx, p.claim),
+    RedCtx R = make_redctx(image, d_imgs, L, skeys, &cnt[C_DIM], cleared, eapp, owner, at<int32_t>(ctx, p.claim),
                            at<uint64_t>(ctx, p.piv), at<uint64_t>(ctx, p.colptr), at<uint64_t>(ctx, p.arena),
                            p.arena_cap, &cnt[C_ARENA], at<uint64_t>(ctx, p.pbuf), st);
     // thresholds between thread and block mode (CR_LONG_LEN / CR_YIELD_ITERS

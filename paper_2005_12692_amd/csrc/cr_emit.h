@@ -23,6 +23,19 @@ __device__ inline uint64_t canon_key(const Layout& L, int img, int dim, uint64_t
   return ((uint64_t)img << (2 + 2 * L.pb)) | ((uint64_t)dim << (2 * L.pb)) | (bl << L.pb) | dl;
 }
 
+// Adds one to cnt[key] for every active lane with one atomic per distinct key
+// in the wavefront; every lane of the wavefront must call it.
+__device__ inline void wave_count(uint32_t* cnt, bool active, int key) {
+  uint64_t mask = __ballot(active);
+  while (mask) {
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    const int lk = __shfl(key, leader, 64);
+    const uint64_t peers = __ballot(active && key == lk);
+    if (__lane_id() == leader) atomicAdd(&cnt[lk], (uint32_t)__popcll(peers));
+    mask &= ~peers;
+  }
+}
+
 // Appends one row per active lane; every lane of the wavefront must call it.
 __device__ inline void emit_rows(const EmitCtx& E, bool active, int img, uint64_t ckey) {
   const uint64_t mask = __ballot(active);
@@ -32,16 +45,18 @@ __device__ inline void emit_rows(const EmitCtx& E, bool active, int img, uint64_
   unsigned long long base = 0;
   if (lane == leader) base = atomicAdd(E.cand_count, (unsigned long long)__popcll(mask));
   base = __shfl(base, leader, 64);
+  bool stored = false;
   if (active) {
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
     const unsigned long long pos = base + __popcll(mask & lt);
     if (pos < E.cand_cap) {
       E.cand[pos] = ckey;
-      atomicAdd(&E.img_pairs[img], 1u);
+      stored = true;
     } else {
       raise_flag(E.st, &E.st->overflow, OVF_ROWS);
     }
   }
+  wave_count(E.img_pairs, stored, img);
 }
 
 // Row for the pair (birth cell, death cell) given by their sort keys; returns

@@ -16,6 +16,7 @@ struct RedCtx {
   const uint64_t* skeys;
   const unsigned long long* dim_count;
   const uint8_t* cleared;  // per square rank: 1 = birth of degree 2 (zero column)
+  const uint8_t* eapp;     // per edge slot: apparent partner square (2 * axis + dir), 0xFF if none
   int32_t* owner;          // per edge (3 * anchor pixel + axis of the edge): owning column, or -1
   int32_t* claim;          // per edge: leftmost proposer of the current round, INT32_MAX if none
   uint64_t* piv;           // per column: key of its pivot edge (the proposed one while active)
@@ -31,7 +32,8 @@ struct RedCtx {
 constexpr uint64_t PBUF_PER_THREAD = 2 * FBUF + 2 * PCAP;
 
 RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64_t* skeys,
-                   const unsigned long long* dim_count, const uint8_t* cleared, int32_t* owner, int32_t* claim,
+                   const unsigned long long* dim_count, const uint8_t* cleared, const uint8_t* eapp,
+                   int32_t* owner, int32_t* claim,
                    uint64_t* piv, uint64_t* col_ptr, uint64_t* arena, uint64_t arena_cap,
                    unsigned long long* arena_top, uint64_t* pbuf, Status* st);
 

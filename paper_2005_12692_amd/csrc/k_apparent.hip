@@ -41,13 +41,13 @@ template <int NDIM, int TX, int TY, int TZ>
 __global__ __launch_bounds__(TX* TY* TZ) void k_apparent(
     const float* __restrict__ img, const ImgDesc* __restrict__ imgs, const int4* __restrict__ tiles,
     Layout L, uint64_t* __restrict__ surv, uint64_t surv_cap,
-    unsigned long long* __restrict__ surv_count, unsigned long long* __restrict__ dim_count,
-    int32_t* __restrict__ vlink, int32_t* __restrict__ tlink, uint32_t* __restrict__ img_status,
-    Status* __restrict__ st) {
+    unsigned long long* __restrict__ surv_count, int32_t* __restrict__ vlink, int32_t* __restrict__ tlink,
+    uint8_t* __restrict__ eapp, uint32_t* __restrict__ img_status, Status* __restrict__ st) {
   using T = ApparentTile<NDIM, TX, TY, TZ>;
   __shared__ float pix[T::PZ * T::PY * T::PX];
   __shared__ float kv[T::RZ * T::RY * T::RX];
-  __shared__ unsigned int dcnt[4];
+  __shared__ unsigned int wtot[T::NT / 64];
+  __shared__ unsigned long long bbase;
   __shared__ unsigned int nan_seen;
 
   const int tid = threadIdx.x;
@@ -55,7 +55,6 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_apparent(
   const int im = tile.x;
   const ImgDesc d = imgs[im];
   const int z0 = (NDIM == 3) ? tile.y : 0, y0 = tile.z, x0 = tile.w;
-  if (tid < 4) dcnt[tid] = 0;
   if (tid == 0) nan_seen = 0;
 
   // ---- stage pixels (tile origin minus one, plus a halo of two after) ----
@@ -140,10 +139,11 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_apparent(
           }
         }
       }
+      bool latest = false;
       if (ta >= 0) {
         int t[3] = {k[0], k[1], k[2]};
         t[ta] += ts;
-        bool latest = true;
+        latest = true;
         for (int b = 0; b < 3 && latest; ++b) {
           if (!(t[b] & 1)) continue;
           for (int s = -1; s <= 1; s += 2) {
@@ -156,14 +156,21 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_apparent(
             }
           }
         }
-        if (latest) {
-          paired = true;
-          if (dim == 0) {  // vertex: link to the other endpoint of its edge
-            int o[3] = {k[0], k[1], k[2]};
-            o[ta] += 2 * ts;
-            vlink[pixel_index(d, k[0] >> 1, k[1] >> 1, k[2] >> 1)] =
-                (int32_t)pixel_index(d, o[0] >> 1, o[1] >> 1, o[2] >> 1);
-          }
+      }
+      if (NDIM == 3 && dim == 1 && eapp) {
+        // apparent-partner code of an edge for the degree-1 reduction:
+        // 2 * axis + (direction > 0) of its partner square, 0xFF if none
+        const int oa = (k[0] & 1) ? 0 : ((k[1] & 1) ? 1 : 2);
+        eapp[3 * pixel_index(d, k[0] >> 1, k[1] >> 1, k[2] >> 1) + oa] =
+            latest ? (uint8_t)(2 * ta + (ts > 0 ? 1 : 0)) : (uint8_t)0xFF;
+      }
+      if (latest) {
+        paired = true;
+        if (dim == 0) {  // vertex: link to the other endpoint of its edge
+          int o[3] = {k[0], k[1], k[2]};
+          o[ta] += 2 * ts;
+          vlink[pixel_index(d, k[0] >> 1, k[1] >> 1, k[2] >> 1)] =
+              (int32_t)pixel_index(d, o[0] >> 1, o[1] >> 1, o[2] >> 1);
         }
       }
     }
@@ -217,25 +224,32 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_apparent(
       uint32_t bits;
       __builtin_memcpy(&bits, &vc, 4);
       keys[cs] = make_skey(L, dim, im, ord32_bits(bits), kc);
-      atomicAdd(&dcnt[dim], 1u);
       if (dim == 0) vlink[pixel_index(d, k[0] >> 1, k[1] >> 1, k[2] >> 1)] = -1;
       if (dim == NDIM) tlink[pixel_index(d, k[0] >> 1, k[1] >> 1, k[2] >> 1)] = -1;
     }
   }
 
-  // ---- wave-aggregated append of this thread's survivors ----
+  // ---- append this workgroup's survivors with one atomic ----
   const uint32_t mine = __popc(surv_mask);
-  const int lane = __lane_id();
+  const int lane = __lane_id(), wave = tid >> 6;
   uint32_t incl = mine;
   for (int off = 1; off < 64; off <<= 1) {
-    uint32_t up = __shfl_up(incl, off, 64);
+    const uint32_t up = __shfl_up(incl, off, 64);
     if (lane >= off) incl += up;
   }
-  const uint32_t total = __shfl(incl, 63, 64);
-  unsigned long long wbase = 0;
-  if (lane == 63 && total) wbase = atomicAdd(surv_count, (unsigned long long)total);
-  wbase = __shfl(wbase, 63, 64);
-  unsigned long long pos = wbase + incl - mine;
+  if (lane == 63) wtot[wave] = incl;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < T::NT / 64; ++w) {
+      const uint32_t t = wtot[w];
+      wtot[w] = run;
+      run += t;
+    }
+    bbase = run ? atomicAdd(surv_count, (unsigned long long)run) : 0ull;
+  }
+  __syncthreads();
+  unsigned long long pos = bbase + wtot[wave] + incl - mine;
 #pragma unroll
   for (int cs = 0; cs < NCELL; ++cs) {
     if (surv_mask & (1u << cs)) {
@@ -244,25 +258,48 @@ __global__ __launch_bounds__(TX* TY* TZ) void k_apparent(
       ++pos;
     }
   }
+}
+
+// Segment sizes of the sorted survivors: dim_count[d] = number of keys whose
+// top field (the dimension) is d, by binary search for each boundary.
+__global__ void k_dim_bounds(const uint64_t* __restrict__ keys, const unsigned long long* __restrict__ n_ptr,
+                             uint64_t cap, Layout L, unsigned long long* __restrict__ dim_count) {
+  __shared__ uint64_t first[5];
+  const int t = threadIdx.x;
+  const uint64_t n = *n_ptr < cap ? *n_ptr : cap;
+  const int shift = L.ib + 32 + L.kb;
+  if (t < 5) {
+    // first index whose dimension is >= t
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+      const uint64_t m = (lo + hi) >> 1;
+      if ((int)(keys[m] >> shift) < t) lo = m + 1;
+      else hi = m;
+    }
+    first[t] = t == 4 ? n : lo;
+  }
   __syncthreads();
-  if (tid < NDIM + 1 && dcnt[tid]) atomicAdd(&dim_count[tid], (unsigned long long)dcnt[tid]);
+  if (t < 4) dim_count[t] = first[t + 1] - first[t];
 }
 
 // ---- host launcher ----------------------------------------------------------
 void launch_apparent(int ndim, int ntiles, const float* img, const ImgDesc* imgs, const int4* tiles,
                      Layout L, uint64_t* surv, uint64_t surv_cap, unsigned long long* surv_count,
-                     unsigned long long* dim_count, int32_t* vlink, int32_t* tlink,
-                     uint32_t* img_status, Status* st, hipStream_t stream) {
+                     int32_t* vlink, int32_t* tlink, uint8_t* eapp, uint32_t* img_status, Status* st,
+                     hipStream_t stream) {
   if (ntiles <= 0) return;
   if (ndim == 2) {
-    k_apparent<2, 32, 8, 1><<<ntiles, 256, 0, stream>>>(img, imgs, tiles, L, surv, surv_cap,
-                                                        surv_count, dim_count, vlink, tlink,
-                                                        img_status, st);
+    k_apparent<2, 32, 8, 1><<<ntiles, 256, 0, stream>>>(img, imgs, tiles, L, surv, surv_cap, surv_count,
+                                                        vlink, tlink, eapp, img_status, st);
   } else {
-    k_apparent<3, 16, 4, 4><<<ntiles, 256, 0, stream>>>(img, imgs, tiles, L, surv, surv_cap,
-                                                        surv_count, dim_count, vlink, tlink,
-                                                        img_status, st);
+    k_apparent<3, 16, 4, 4><<<ntiles, 256, 0, stream>>>(img, imgs, tiles, L, surv, surv_cap, surv_count,
+                                                        vlink, tlink, eapp, img_status, st);
   }
+}
+
+void launch_dim_bounds(const uint64_t* keys, const unsigned long long* n_ptr, uint64_t cap, Layout L,
+                       unsigned long long* dim_count, hipStream_t s) {
+  k_dim_bounds<<<1, 64, 0, s>>>(keys, n_ptr, cap, L, dim_count);
 }
 
 }  // namespace cr

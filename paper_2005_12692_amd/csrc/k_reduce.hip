@@ -77,29 +77,16 @@ __device__ inline int sq_boundary(const RedCtx& R, int im, const ImgDesc& d, con
 }
 
 // If edge e is in an apparent pair (e, s) -- s its earliest cofacet and e the
-// latest facet of s -- writes the boundary of s into bnd and returns its length.
+// latest facet of s, as recorded by the stencil pass -- writes the boundary of
+// s into bnd and returns its length; returns 0 otherwise.
 __device__ inline int apparent_bnd(const RedCtx& R, int im, const ImgDesc& d, const int ec[3], uint64_t ekey,
                                    uint64_t bnd[4]) {
-  int best[3] = {0, 0, 0};
-  uint64_t bk = 0;
-  bool have = false;
-  for (int a = 0; a < 3; ++a) {
-    if (ec[a] & 1) continue;
-    for (int s = -1; s <= 1; s += 2) {
-      int t[3] = {ec[0], ec[1], ec[2]};
-      t[a] += s;
-      if (t[a] < 0 || t[a] >= d.K[a]) continue;
-      const uint64_t k = cell_key(R, 2, im, d, t);
-      if (!have || k < bk) {
-        have = true;
-        bk = k;
-        best[0] = t[0]; best[1] = t[1]; best[2] = t[2];
-      }
-    }
-  }
-  if (!have) return 0;
-  const int n = sq_boundary(R, im, d, best, bnd);
-  return bnd[n - 1] == ekey ? n : 0;
+  (void)ekey;
+  const uint8_t code = R.eapp[edge_slot(d, ec)];
+  if (code == 0xFF) return 0;
+  int t[3] = {ec[0], ec[1], ec[2]};
+  t[code >> 1] += (code & 1) ? 1 : -1;
+  return sq_boundary(R, im, d, t, bnd);
 }
 
 __device__ inline uint64_t arena_alloc(const RedCtx& R, uint32_t len) {
@@ -219,6 +206,21 @@ __device__ inline void push_list(uint32_t* list, unsigned long long* n, uint32_t
   list[at] = c;
 }
 
+// Wave-aggregated append of c for every active lane (all lanes must call it).
+__device__ inline void wave_push(uint32_t* list, unsigned long long* n, bool active, uint32_t c) {
+  const uint64_t mask = __ballot(active);
+  if (!mask) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(n, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader, 64);
+  if (active) {
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    list[base + __popcll(mask & lt)] = c;
+  }
+}
+
 // Stores W as column c and proposes c as the owner of e (or yields if e == YIELDED).
 __device__ inline bool store_and_propose(const RedCtx& R, Work& W, uint32_t c, uint64_t e, int64_t slot) {
   uint32_t len = 0;
@@ -236,8 +238,9 @@ __device__ inline bool store_and_propose(const RedCtx& R, Work& W, uint32_t c, u
 
 // One round of column c in thread mode: reduce it against the columns done
 // before this round, then store it and propose it as the owner of its pivot.
-// A column whose tail outgrows the private buffer, or that needs more than
-// R.yield_iters additions, stores its state and moves to the block-mode list.
+// A column whose tail grows past R.long_len keys, or that needs more than
+// R.yield_iters additions, stores its state and moves to the block-mode list
+// (a single thread merges long lists at one memory latency per key).
 __device__ void reduce_round(const RedCtx& R, uint32_t c, bool first, uint64_t off2, Work& W,
                              uint32_t* long_next, unsigned long long* n_long_next) {
   if (first) {  // initial column: the boundary of the square
@@ -257,7 +260,7 @@ __device__ void reduce_round(const RedCtx& R, uint32_t c, bool first, uint64_t o
   }
   for (uint32_t it = 0; it < RED_ITER_CAP; ++it) {
     if ((it & 63) == 63 && aborted(R.st)) return;
-    if (it >= R.yield_iters || (W.tsel < 0 && W.nt > PCAP)) {
+    if (it >= R.yield_iters || W.nt > R.long_len) {
       if (store_and_propose(R, W, c, YIELDED, 0)) push_list(long_next, n_long_next, c);
       return;
     }
@@ -365,32 +368,42 @@ struct BlockLds {
   unsigned long long adds, merged;
 };
 
-// Exclusive scan of flags[0..n) (n <= (BT) * per) into out[0..n]; returns the total.
+// Exclusive scan of one value per thread across the workgroup (wave shuffles,
+// then the four wave totals); returns the prefix and writes the total.
+__device__ inline uint32_t blk_excl(uint32_t v, uint32_t* part, uint32_t* total) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t up = __shfl_up(incl, off, 64);
+    if (lane >= (uint32_t)off) incl += up;
+  }
+  if (lane == 63) part[wave] = incl;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+  for (uint32_t w = 0; w < BT / 64; ++w) {
+    const uint32_t x = part[w];
+    if (w < wave) base += x;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + incl - v;
+}
+
+// Exclusive scan of flags[0..n) into out[0..n] (out[n] = total); returns the total.
 __device__ inline uint32_t blk_scan(const uint32_t* flags, uint32_t n, uint32_t* out, uint32_t* part) {
   const uint32_t tid = threadIdx.x;
   const uint32_t per = (n + BT - 1) / BT;
-  const uint32_t lo = tid * per, hi = lo + per < n ? lo + per : n;
+  const uint32_t lo = tid * per < n ? tid * per : n, hi = lo + per < n ? lo + per : n;
   uint32_t s = 0;
   for (uint32_t i = lo; i < hi; ++i) s += flags[i];
-  part[tid] = s;
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t run = 0;
-    for (int i = 0; i < BT; ++i) {
-      const uint32_t v = part[i];
-      part[i] = run;
-      run += v;
-    }
-    part[BT] = run;
-  }
-  __syncthreads();
-  uint32_t run = part[tid];
+  uint32_t total;
+  uint32_t run = blk_excl(s, part, &total);
   for (uint32_t i = lo; i < hi; ++i) {
     const uint32_t v = flags[i];
     out[i] = run;
     run += v;
   }
-  const uint32_t total = part[BT];
   if (tid == 0) out[n] = total;
   __syncthreads();
   return total;
@@ -429,28 +442,17 @@ __device__ uint32_t blk_xor_lds(BlockLds& S, const uint64_t* A, uint32_t na, con
   // exclusive prefix of the cancel flags, in place (pref[j] = # cancels in B[0:j])
   {
     const uint32_t per = (nb + BT - 1) / BT;
-    const uint32_t lo = tid * per, hi = lo + per < nb ? lo + per : nb;
+    const uint32_t lo = tid * per < nb ? tid * per : nb, hi = lo + per < nb ? lo + per : nb;
     uint32_t s = 0;
     for (uint32_t i = lo; i < hi; ++i) s += S.pref[i];
-    S.part[tid] = s;
-    __syncthreads();
-    if (tid == 0) {
-      uint32_t run = 0;
-      for (int i = 0; i < BT; ++i) {
-        const uint32_t v = S.part[i];
-        S.part[i] = run;
-        run += v;
-      }
-      S.part[BT] = run;
-    }
-    __syncthreads();
-    uint32_t run = S.part[tid];
+    uint32_t total;
+    uint32_t run = blk_excl(s, S.part, &total);
     for (uint32_t i = lo; i < hi; ++i) {
       const uint32_t v = S.pref[i];
       S.pref[i] = run;
       run += v;
     }
-    if (tid == 0) S.pref[nb] = S.part[BT];
+    if (tid == 0) S.pref[nb] = total;
     __syncthreads();
   }
   const uint32_t ncancel = S.pref[nb];
@@ -712,41 +714,47 @@ __device__ inline int64_t pivot_slot(const RedCtx& R, uint64_t e) {
 // Commit: the leftmost proposer of each pivot becomes its owner; losers and
 // displaced owners go to the next round's lists (long stored columns to the
 // block-mode list).  Yielded columns were already listed.
-__device__ inline void commit_one(const RedCtx& R, uint32_t c, uint32_t* const next[2],
-                                  unsigned long long* n_next) {
-  const uint64_t e = R.piv[c];
-  if (e == YIELDED) return;
-  const int64_t slot = pivot_slot(R, e);
-  uint32_t again;
-  if (R.claim[slot] == (int32_t)c) {
-    const int32_t old = R.owner[slot];
-    R.owner[slot] = (int32_t)c;
-    if (old < 0) return;
-    again = (uint32_t)old;
-  } else {
-    again = c;
-  }
-  const int which = (uint32_t)(R.col_ptr[again] & ((1u << 24) - 1)) > R.long_len ? 1 : 0;
-  push_list(next[which], n_next + which, again);
-}
-
 __global__ void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t, const unsigned long long* __restrict__ n_t,
                              const uint32_t* __restrict__ list_b, const unsigned long long* __restrict__ n_b,
                              int first, uint32_t* next_t, uint32_t* next_b, unsigned long long* __restrict__ n_next) {
   if (aborted(R.st)) return;
-  uint32_t* const next[2] = {next_t, next_b};
   const uint64_t nt = first ? R.dim_count[2] : *n_t;
   const uint64_t nb = first ? 0 : *n_b;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nt + nb; i += stride) {
-    uint32_t c;
-    if (i < nt) {
-      c = first ? (uint32_t)i : list_t[i];
-      if (first && R.cleared[c]) continue;
-    } else {
-      c = list_b[i - nt];
+  const uint64_t nr = (nt + nb + 63) & ~63ull;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nr; i += stride) {
+    bool again_short = false, again_long = false;
+    uint32_t again = 0;
+    if (i < nt + nb) {
+      uint32_t c;
+      bool skip = false;
+      if (i < nt) {
+        c = first ? (uint32_t)i : list_t[i];
+        skip = first && R.cleared[c];
+      } else {
+        c = list_b[i - nt];
+      }
+      const uint64_t e = skip ? YIELDED : R.piv[c];
+      if (e != YIELDED) {
+        const int64_t slot = pivot_slot(R, e);
+        bool push = true;
+        if (R.claim[slot] == (int32_t)c) {
+          const int32_t old = R.owner[slot];
+          R.owner[slot] = (int32_t)c;
+          push = old >= 0;
+          again = (uint32_t)old;
+        } else {
+          again = c;
+        }
+        if (push) {
+          const bool lng = (uint32_t)(R.col_ptr[again] & ((1u << 24) - 1)) > R.long_len;
+          again_long = lng;
+          again_short = !lng;
+        }
+      }
     }
-    commit_one(R, c, next, n_next);
+    wave_push(next_t, n_next, again_short, again);
+    wave_push(next_b, n_next + 1, again_long, again);
   }
 }
 
@@ -796,7 +804,8 @@ __global__ void k_h1_emit(RedCtx R, EmitCtx E) {
 }
 
 RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64_t* skeys,
-                   const unsigned long long* dim_count, const uint8_t* cleared, int32_t* owner, int32_t* claim,
+                   const unsigned long long* dim_count, const uint8_t* cleared, const uint8_t* eapp,
+                   int32_t* owner, int32_t* claim,
                    uint64_t* piv, uint64_t* col_ptr, uint64_t* arena, uint64_t arena_cap,
                    unsigned long long* arena_top, uint64_t* pbuf, Status* st) {
   RedCtx R;
@@ -806,6 +815,7 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.skeys = skeys;
   R.dim_count = dim_count;
   R.cleared = cleared;
+  R.eapp = eapp;
   R.owner = owner;
   R.claim = claim;
   R.piv = piv;
@@ -815,8 +825,8 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.arena_top = arena_top;
   R.pbuf = pbuf;
   R.st = st;
-  R.long_len = 256;
-  R.yield_iters = 256;
+  R.long_len = 128;
+  R.yield_iters = 32;
   return R;
 }
 
