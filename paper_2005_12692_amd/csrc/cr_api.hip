@@ -115,8 +115,8 @@ struct cr_context {
 
 namespace {
 
-// counters block: surv_count, dim_count[4], cand_count, arena_top, spare
-enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* four words */, C_WORDS = 12 };
+// counters block: surv_count, dim_count[4], cand_count, arena_top, lists[4], wave work counter
+enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* four words */, C_WORK = 11, C_WORDS = 12 };
 
 cr_status build_problem(Problem& pb, int nimg, const int64_t* pixel_offsets, const int64_t* shapes, int ndim,
                         int maxdim) {
@@ -187,7 +187,7 @@ Plan make_plan(const Problem& pb, uint64_t arena_entries) {
   p.surv_cap = pb.N;
   p.e_cap = 3 * pb.P + 64;
   const bool vol = pb.ndim == 3 && pb.maxdim >= 1;
-  p.arena_cap = vol ? arena_entries : 0;
+  p.arena_cap = vol ? std::min<uint64_t>(arena_entries, ARENA_MAX) : 0;
   p.status = take(sizeof(Status));
   p.counters = take(C_WORDS * 8);
   p.img_status = take(4 * (size_t)pb.nimg);
@@ -201,10 +201,10 @@ Plan make_plan(const Problem& pb, uint64_t arena_entries) {
   p.tlink = take(4 * pb.P);
   p.T = take(8 * (pb.P + pb.nimg + 64));
   p.neg = take(p.e_cap);
-  p.owner = take(vol ? 4 * 3 * pb.P : 0);
+  p.owner = take(vol ? 8 * 3 * pb.P : 0);
   p.piv = take(vol ? 8 * p.e_cap : 0);
   p.colptr = take(vol ? 8 * p.e_cap : 0);
-  p.arena = take(8 * p.arena_cap);
+  p.arena = take(vol ? 8 * (p.arena_cap + ARENA_SLACK) : 0);
   p.pbuf = take(vol ? 8 * PBUF_PER_THREAD * RGRID * 256 : 0);
   p.cleared = take(vol ? p.e_cap : 0);
   p.claim = take(vol ? 4 * 3 * pb.P : 0);
@@ -356,7 +356,7 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
   launch_h0(KGRID, skeys, &cnt[C_DIM], d_imgs, L, vlink, T, neg, E, st, s);
   mark(ctx, EV_H0, s);
 
-  int32_t* owner = at<int32_t>(ctx, p.owner);
+  uint64_t* owner = at<uint64_t>(ctx, p.owner);
   if (pb.ndim == 2) {
     if (pb.maxdim >= 1) launch_dual(KGRID, 2, skeys, &cnt[C_DIM], d_imgs, L, tlink, neg, nullptr, 1, T, E, st, s);
     mark(ctx, EV_A, s);
@@ -368,15 +368,21 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     launch_fill_u32(reinterpret_cast<uint32_t*>(cleared), 0, p.e_cap / 4, s);
     launch_dual(KGRID, 3, skeys, &cnt[C_DIM], d_imgs, L, tlink, nullptr, cleared, pb.maxdim >= 2, T, E, st, s);
     mark(ctx, EV_A, s);
-    launch_fill_u32(reinterpret_cast<uint32_t*>(owner), 0xFFFFFFFFu, 3 * pb.P, s);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(owner), 0xFFFFFFFFu, 2 * 3 * pb.P, s);
     launch_fill_u32(at<uint32_t>(ctx, p.claim), 0x7FFFFFFFu, 3 * pb.P, s);
     RedCtx R = make_redctx(image, d_imgs, L, skeys, &cnt[C_DIM], cleared, eapp, owner, at<int32_t>(ctx, p.claim),
                            at<uint64_t>(ctx, p.piv), at<uint64_t>(ctx, p.colptr), at<uint64_t>(ctx, p.arena),
-                           p.arena_cap, &cnt[C_ARENA], at<uint64_t>(ctx, p.pbuf), st);
-    // thresholds between thread and block mode (CR_LONG_LEN / CR_YIELD_ITERS
-    // override them, e.g. to exercise block mode on small inputs)
+                           p.arena_cap, &cnt[C_ARENA], &cnt[C_WORK], at<uint64_t>(ctx, p.pbuf), st);
+    // thresholds between thread and wave mode and the wave-mode front capacity
+    // (CR_LONG_LEN / CR_YIELD_ITERS / CR_WAVE_SHORT / CR_FRONT_CAP override them,
+    // e.g. to exercise wave mode and its tail merges on small inputs)
     if (const char* v = getenv("CR_LONG_LEN")) R.long_len = (uint32_t)strtoul(v, nullptr, 10);
     if (const char* v = getenv("CR_YIELD_ITERS")) R.yield_iters = (uint32_t)strtoul(v, nullptr, 10);
+    if (const char* v = getenv("CR_WAVE_SHORT")) R.wave_short = (uint32_t)strtoul(v, nullptr, 10);
+    if (const char* v = getenv("CR_FRONT_CAP")) {
+      const unsigned long f = strtoul(v, nullptr, 10);
+      R.front_cap = (uint32_t)(f < FRONT_CAP_MIN ? FRONT_CAP_MIN : (f > FRONT_CAP_MAX ? FRONT_CAP_MAX : f));
+    }
     uint32_t* lists[4] = {at<uint32_t>(ctx, p.list[0]), at<uint32_t>(ctx, p.list[1]), at<uint32_t>(ctx, p.list[2]),
                           at<uint32_t>(ctx, p.list[3])};
     cr_status rrc = run_rounds(ctx, R, lists, &cnt[C_LIST], s);
@@ -523,7 +529,7 @@ cr_status cr_persistence(cr_context* ctx, const float* image, int ndim, const in
     bool arena_over = false;
     rc = status_error(h.st, &arena_over);
     if (rc != CR_OK) {
-      if (arena_over && attempt < 3) {
+      if (arena_over && attempt < 3 && ctx->plan.arena_cap < ARENA_MAX) {
         ctx->arena_entries = std::max<uint64_t>(ctx->arena_entries * 4, h.cnt[C_ARENA] * 2);
         continue;  // rerun with a larger column arena
       }

@@ -17,29 +17,38 @@ struct RedCtx {
   const unsigned long long* dim_count;
   const uint8_t* cleared;  // per square rank: 1 = birth of degree 2 (zero column)
   const uint8_t* eapp;     // per edge slot: apparent partner square (2 * axis + dir), 0xFF if none
-  int32_t* owner;          // per edge (3 * anchor pixel + axis of the edge): owning column, or -1
+  uint64_t* owner;         // per edge (3 * anchor pixel + axis of the edge): (owning column << 32) |
+                           // arena offset of that column's stored list; NO_OWNER if none
   int32_t* claim;          // per edge: leftmost proposer of the current round, INT32_MAX if none
   uint64_t* piv;           // per column: key of its pivot edge (the proposed one while active)
-  uint64_t* col_ptr;       // per column: (arena offset << 24) | length of its stored column
-  uint64_t* arena;
+  uint64_t* col_ptr;       // per column: arena offset of its stored list (length word, then keys)
+  uint64_t* arena;         // stored lists: a length word followed by that many ascending keys
   uint64_t arena_cap;
   unsigned long long* arena_top;
   uint64_t* pbuf;          // private buffers, PBUF_PER_THREAD entries per thread
   Status* st;
-  uint32_t long_len;       // stored columns longer than this continue in block mode
-  uint32_t yield_iters;    // thread mode hands a column to block mode after this many additions
+  unsigned long long* work;  // column counter of the wave-mode round
+  uint32_t long_len;       // stored columns longer than this continue in wave mode
+  uint32_t yield_iters;    // thread mode hands a column to wave mode after this many additions
+  uint32_t wave_short;     // a short list of at most this many columns is run in wave mode too
+  uint32_t front_cap;      // keys of the wave-mode LDS front list
 };
+constexpr uint64_t NO_OWNER = ~0ull;
 constexpr uint64_t PBUF_PER_THREAD = 2 * FBUF + 2 * PCAP;
+constexpr uint64_t ARENA_SLACK = 64;       // readable entries past the arena end (wave loads of 64 words)
+constexpr uint64_t ARENA_MAX = (1ull << 32) - ARENA_SLACK;  // offsets fit the low half of an owner word
+constexpr uint32_t FRONT_CAP_MIN = 128;    // wave-mode LDS front list capacity bounds
+constexpr uint32_t FRONT_CAP_MAX = 4096;
 
 RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64_t* skeys,
                    const unsigned long long* dim_count, const uint8_t* cleared, const uint8_t* eapp,
-                   int32_t* owner, int32_t* claim,
+                   uint64_t* owner, int32_t* claim,
                    uint64_t* piv, uint64_t* col_ptr, uint64_t* arena, uint64_t arena_cap,
-                   unsigned long long* arena_top, uint64_t* pbuf, Status* st);
+                   unsigned long long* arena_top, unsigned long long* work, uint64_t* pbuf, Status* st);
 
 // Enqueues rounds [round0, round0 + nrounds) of the reduction.  lists/counts:
 // two ping-pong pairs of column lists (short columns for thread mode, long ones
-// for block mode) with their device counts: round r reads pair r & 1 (round 0
+// for wave mode) with their device counts: round r reads pair r & 1 (round 0
 // reads every column) and builds pair (r + 1) & 1; list 2k is short, 2k+1 long.
 void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round0,
                       int nrounds, hipStream_t s);

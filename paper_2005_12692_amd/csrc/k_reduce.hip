@@ -27,16 +27,12 @@
 // the rounds end in a reduced matrix with the unique pivots of the sequential
 // reduction.
 //
-// A working column is kept in two sorted parts: a short front list F (at most
-// FCAP entries plus one addend) that absorbs small additions, and a tail T.
-// The pivot is the larger of the two last entries after cancelling equal ones,
-// so adding a 4-entry boundary to a long column costs O(FCAP), not O(length);
-// F is merged into T only when it overflows.  Stored columns live in an
-// append-only arena.
+// Short columns are reduced one per thread; a column that grows long, or needs
+// many additions, continues in wave mode (one wavefront per column).  Stored
+// columns live in an append-only arena as a length word followed by the keys.
 #include "cr_reduce.h"
 
 namespace cr {
-
 
 __device__ inline uint64_t cell_key(const RedCtx& R, int dim, int im, const ImgDesc& d, const int c[3]) {
   const float v = cell_value(R.img, d, c);
@@ -79,9 +75,7 @@ __device__ inline int sq_boundary(const RedCtx& R, int im, const ImgDesc& d, con
 // If edge e is in an apparent pair (e, s) -- s its earliest cofacet and e the
 // latest facet of s, as recorded by the stencil pass -- writes the boundary of
 // s into bnd and returns its length; returns 0 otherwise.
-__device__ inline int apparent_bnd(const RedCtx& R, int im, const ImgDesc& d, const int ec[3], uint64_t ekey,
-                                   uint64_t bnd[4]) {
-  (void)ekey;
+__device__ inline int apparent_bnd(const RedCtx& R, int im, const ImgDesc& d, const int ec[3], uint64_t bnd[4]) {
   const uint8_t code = R.eapp[edge_slot(d, ec)];
   if (code == 0xFF) return 0;
   int t[3] = {ec[0], ec[1], ec[2]};
@@ -89,7 +83,7 @@ __device__ inline int apparent_bnd(const RedCtx& R, int im, const ImgDesc& d, co
   return sq_boundary(R, im, d, t, bnd);
 }
 
-__device__ inline uint64_t arena_alloc(const RedCtx& R, uint32_t len) {
+__device__ inline uint64_t arena_alloc(const RedCtx& R, uint64_t len) {
   const unsigned long long off = atomicAdd(R.arena_top, (unsigned long long)len);
   if (off + len > R.arena_cap) {
     raise_flag(R.st, &R.st->overflow, OVF_ARENA);
@@ -113,8 +107,13 @@ __device__ inline uint32_t xor_lists(const uint64_t* a, uint32_t na, const uint6
   return m;
 }
 
-__device__ inline uint64_t pack_col(uint64_t off, uint32_t len) { return (off << 24) | len; }
-
+// ---- thread mode -----------------------------------------------------------------
+//
+// A working column is kept in two sorted parts: a short front list F (at most
+// FCAP entries plus one addend) that absorbs small additions, and a tail T.
+// The pivot is the larger of the two last entries after cancelling equal ones,
+// so adding a 4-entry boundary to a long column costs O(FCAP), not O(length);
+// F is merged into T only when it overflows.
 struct Work {
   uint64_t* fbuf[2];
   uint64_t* tbuf[2];
@@ -179,22 +178,22 @@ __device__ inline bool work_pivot(Work& W, uint64_t* piv) {
   return true;
 }
 
-// Writes F XOR T to the arena; afterwards the working column is that list.
-__device__ inline uint64_t work_publish(const RedCtx& R, Work& W, uint32_t* len) {
-  const uint32_t need = W.nf + W.nt;
-  const uint64_t off = arena_alloc(R, need ? need : 1);
+// Writes F XOR T to the arena as a stored list; afterwards the working column is that list.
+__device__ inline uint64_t work_publish(const RedCtx& R, Work& W) {
+  const uint64_t off = arena_alloc(R, (uint64_t)W.nf + W.nt + 1);
   if (off == ~0ull) return ~0ull;
-  *len = xor_lists(W.F, W.nf, W.T, W.nt, R.arena + off);
-  W.T = R.arena + off;
-  W.nt = *len;
+  const uint32_t len = xor_lists(W.F, W.nf, W.T, W.nt, R.arena + off + 1);
+  R.arena[off] = len;
+  W.T = R.arena + off + 1;
+  W.nt = len;
   W.tsel = -1;
   W.nf = 0;
   return off;
 }
 
-__device__ inline void work_load(Work& W, const RedCtx& R, uint64_t p) {
-  W.T = R.arena + (p >> 24);
-  W.nt = (uint32_t)(p & ((1u << 24) - 1));
+__device__ inline void work_load(Work& W, const RedCtx& R, uint64_t off) {
+  W.T = R.arena + off + 1;
+  W.nt = (uint32_t)R.arena[off];
   W.tsel = -1;
   W.nf = 0;
 }
@@ -223,14 +222,9 @@ __device__ inline void wave_push(uint32_t* list, unsigned long long* n, bool act
 
 // Stores W as column c and proposes c as the owner of e (or yields if e == YIELDED).
 __device__ inline bool store_and_propose(const RedCtx& R, Work& W, uint32_t c, uint64_t e, int64_t slot) {
-  uint32_t len = 0;
-  const uint64_t off = work_publish(R, W, &len);
+  const uint64_t off = work_publish(R, W);
   if (off == ~0ull) return false;
-  if (len >= (1u << 24)) {
-    raise_flag(R.st, &R.st->overflow, OVF_COLUMN);
-    return false;
-  }
-  R.col_ptr[c] = pack_col(off, len);
+  R.col_ptr[c] = off;
   R.piv[c] = e;
   if (e != YIELDED) atomicMin(&R.claim[slot], (int32_t)c);
   return true;
@@ -239,7 +233,7 @@ __device__ inline bool store_and_propose(const RedCtx& R, Work& W, uint32_t c, u
 // One round of column c in thread mode: reduce it against the columns done
 // before this round, then store it and propose it as the owner of its pivot.
 // A column whose tail grows past R.long_len keys, or that needs more than
-// R.yield_iters additions, stores its state and moves to the block-mode list
+// R.yield_iters additions, stores its state and moves to the wave-mode list
 // (a single thread merges long lists at one memory latency per key).
 __device__ void reduce_round(const RedCtx& R, uint32_t c, bool first, uint64_t off2, Work& W,
                              uint32_t* long_next, unsigned long long* n_long_next) {
@@ -274,16 +268,17 @@ __device__ void reduce_round(const RedCtx& R, uint32_t c, bool first, uint64_t o
     int ec[3];
     kidx_coords(d, skey_kidx(R.L, e), ec);
     uint64_t bnd[4];
-    const int na = apparent_bnd(R, im, d, ec, e, bnd);
+    const int na = apparent_bnd(R, im, d, ec, bnd);
     if (na > 0) {  // owner: the apparent partner, whose column is its raw boundary
       if (!work_add(R, W, bnd, (uint32_t)na)) return;
       continue;
     }
     const int64_t slot = edge_slot(d, ec);
-    const int32_t o = R.owner[slot];
+    const uint64_t ow = R.owner[slot];
+    const int32_t o = ow == NO_OWNER ? -1 : (int32_t)(ow >> 32);
     if (o >= 0 && (uint32_t)o < c) {  // add the column of o
-      const uint64_t p = R.col_ptr[o];
-      if (!work_add(R, W, R.arena + (p >> 24), (uint32_t)(p & ((1u << 24) - 1)))) return;
+      const uint64_t* q = R.arena + (uint32_t)ow;
+      if (!work_add(R, W, q + 1, (uint32_t)q[0])) return;
       continue;
     }
     if ((uint32_t)o == c) {  // cannot happen: an active column owns nothing
@@ -296,13 +291,14 @@ __device__ void reduce_round(const RedCtx& R, uint32_t c, bool first, uint64_t o
   raise_flag(R.st, &R.st->iter_cap);
 }
 
-__global__ void k_fill_count(unsigned long long* c) {
+__global__ void k_fill_count(unsigned long long* c, unsigned long long* work) {
   c[0] = 0;
   c[1] = 0;
+  work[0] = 0;
 }
 
 // Thread-mode round.  Round 0 runs every column that is not cleared; later
-// rounds run the short-column list.
+// rounds run the short-column list unless it is short enough for wave mode.
 __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __restrict__ list,
                                                    const unsigned long long* __restrict__ n_list, int first,
                                                    uint32_t* __restrict__ long_next,
@@ -310,7 +306,7 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
   if (aborted(R.st)) return;
   const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
   const uint64_t n = first ? R.dim_count[2] : *n_list;
-  if (n == 0) return;
+  if (n == 0 || (!first && n <= R.wave_short)) return;
   const uint64_t gtid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   Work W;
   uint64_t* base = R.pbuf + gtid * PBUF_PER_THREAD;
@@ -334,373 +330,506 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
   }
 }
 
-// ---- block mode: one workgroup per long column ---------------------------------
+// ---- wave mode: one wavefront per column -----------------------------------------
 //
-// The front list F lives in LDS (two buffers of FB_CAP keys); the tail T is a
-// sorted list in global memory.  Small additions are merged into F by rank
-// computations in LDS (every thread places some elements); F is merged into T
-// when it passes FB_LIM, and long addends are merged into T directly, by a
-// tiled merge: tiles of both inputs are staged in LDS with coalesced loads,
-// merged by ranks, equal pairs cancelled, and the survivors written out with a
-// block-wide scan.
-constexpr int BT = 256;
-constexpr uint32_t FB_CAP = 7168;
-constexpr uint32_t FB_LIM = FB_CAP - 2048;  // room for an addend of up to STAGE keys
-constexpr uint32_t STAGE = 2048;            // longest addend merged in LDS
-constexpr int TILE = 256;
-constexpr int BLOCK_GRID = 512;          // workgroups of the block-mode round
+// The working column is the XOR of three sorted lists:
+//   P -- at most 64 keys in registers, lane i holding the i-th smallest; the
+//        three new edges of an apparent addition and short owner columns go here;
+//   F -- the front list in this wavefront's LDS (at most front_cap keys), which
+//        absorbs P when it fills and owner columns of up to XN keys;
+//   T -- the tail in the arena (immutable: a merge into it writes a new list);
+//        its top 64 keys are kept in a register window.
+// The pivot is the largest key present an odd number of times among the tops
+// of the three lists.  An iteration issues its loads together: the apparent
+// code of the pivot edge, its owner word, and the ten pixels that the four
+// squares around the edge can have as vertices, so an apparent addition costs
+// one memory latency and an owner addition two.  Merges are merge-path XOR
+// merges: PER positions per lane, equal pairs dropped, never split between
+// lanes.  Every step is wave-synchronous: no workgroup barriers.
+constexpr int WPB = 2;                 // wavefronts per workgroup
+constexpr uint32_t XN = 1024;          // addend stage / two merge tiles
+constexpr int PER = 8;                 // merge positions per lane per chunk
+constexpr uint32_t CHUNK = 64 * PER;   // merge positions per chunk (= one tile)
+constexpr uint64_t KEY_INF = ~0ull;    // above every key
+static_assert(2 * CHUNK <= XN, "two merge tiles must fit the stage");
 
-struct BlockLds {
-  uint64_t F[2][FB_CAP];
-  uint64_t stage[STAGE];
-  uint32_t pref[STAGE + 1];
-  uint64_t tA[TILE + 1], tB[TILE + 1];
-  uint64_t tM[2 * TILE + 2];
-  uint32_t keep[2 * TILE + 2];
-  uint32_t part[BT + 1];
-  uint64_t bnd[4];
-  uint64_t e, tlast;
-  unsigned long long off;
-  int64_t slot;
-  int32_t o;
-  uint32_t nf, cur, nt, n_out, ka, kb, act, na;
+__host__ __device__ __forceinline__ size_t wave_lds_words(uint32_t front_cap) { return 2 * (size_t)front_cap + XN + 64; }
+
+struct WaveBufs {
+  uint64_t* F0;      // the two front buffers (the front list and its merge target)
+  uint64_t* F1;
+  uint64_t* X;
+  uint64_t* ps;
+  uint32_t cap;
+};
+
+__device__ __forceinline__ uint64_t* fbuf(const WaveBufs& S, uint32_t i) { return i ? S.F1 : S.F0; }
+
+struct WState {
+  uint64_t p;        // this lane's pending key (lane < np)
+  uint64_t tw;       // tail window: lane i holds T[tb + i] for tb + i < nt
   const uint64_t* T;
+  uint32_t np, nf, nt, tb, cur;
   unsigned long long adds, merged;
 };
 
-// Exclusive scan of one value per thread across the workgroup (wave shuffles,
-// then the four wave totals); returns the prefix and writes the total.
-__device__ inline uint32_t blk_excl(uint32_t v, uint32_t* part, uint32_t* total) {
-  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// After global stores that other lanes of the wave read back.
+__device__ __forceinline__ void wsync_global() {
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+}
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ uint64_t rdlane64(uint64_t v, uint32_t i) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)i);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)i);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Wave exclusive scan of one value per lane; returns the prefix, sets *total.
+__device__ __forceinline__ uint32_t w_excl(uint32_t v, int lane, uint32_t* total) {
   uint32_t incl = v;
   for (int off = 1; off < 64; off <<= 1) {
     const uint32_t up = __shfl_up(incl, off, 64);
-    if (lane >= (uint32_t)off) incl += up;
+    if (lane >= off) incl += up;
   }
-  if (lane == 63) part[wave] = incl;
-  __syncthreads();
-  uint32_t base = 0, tot = 0;
-  for (uint32_t w = 0; w < BT / 64; ++w) {
-    const uint32_t x = part[w];
-    if (w < wave) base += x;
-    tot += x;
-  }
-  __syncthreads();
-  *total = tot;
-  return base + incl - v;
+  *total = uni(__shfl(incl, 63, 64));
+  return incl - v;
 }
 
-// Exclusive scan of flags[0..n) into out[0..n] (out[n] = total); returns the total.
-__device__ inline uint32_t blk_scan(const uint32_t* flags, uint32_t n, uint32_t* out, uint32_t* part) {
-  const uint32_t tid = threadIdx.x;
-  const uint32_t per = (n + BT - 1) / BT;
-  const uint32_t lo = tid * per < n ? tid * per : n, hi = lo + per < n ? lo + per : n;
-  uint32_t s = 0;
-  for (uint32_t i = lo; i < hi; ++i) s += flags[i];
-  uint32_t total;
-  uint32_t run = blk_excl(s, part, &total);
-  for (uint32_t i = lo; i < hi; ++i) {
-    const uint32_t v = flags[i];
-    out[i] = run;
-    run += v;
+// Number of A elements among the first d positions of the merge of A and B,
+// ties taken from A first.
+__device__ __forceinline__ uint32_t mp_split(const uint64_t* A, uint32_t na, const uint64_t* B, uint32_t nb, uint32_t d) {
+  uint32_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const uint32_t m = (lo + hi) >> 1;
+    if (A[m] <= B[d - m - 1]) lo = m + 1;
+    else hi = m;
   }
-  if (tid == 0) out[n] = total;
-  __syncthreads();
+  return lo;
+}
+
+// Writes the XOR of the first d merge positions of A and B (LDS, ascending;
+// equal pairs dropped) ascending to out, d <= CHUNK.  An equal pair is never
+// split: if position d falls between its two copies the second is consumed
+// too.  A or B may be a tile of a longer list as long as it holds at least d
+// keys or all that remain.  Sets *ka, *kb to the keys consumed; returns the
+// number written.
+__device__ __forceinline__ uint32_t w_merge_seg(const uint64_t* A, uint32_t na, const uint64_t* B, uint32_t nb, uint32_t d,
+                                uint64_t* out, int lane, uint32_t* ka, uint32_t* kb) {
+  const uint32_t dend = (uint32_t)(lane + 1) * PER < d ? (uint32_t)(lane + 1) * PER : d;
+  const uint32_t ie = mp_split(A, na, B, nb, dend);
+  uint32_t je = dend - ie;
+  if (ie > 0 && je < nb && A[ie - 1] == B[je]) ++je;
+  uint32_t is = __shfl_up(ie, 1, 64), js = __shfl_up(je, 1, 64);
+  if (lane == 0) {
+    is = 0;
+    js = 0;
+  }
+  uint32_t i = is, j = js;
+  uint64_t a = i < ie ? A[i] : KEY_INF;
+  uint64_t b = j < je ? B[j] : KEY_INF;
+  uint64_t buf[PER + 1];
+  uint32_t keep = 0;
+#pragma unroll
+  for (int t = 0; t <= PER; ++t) {
+    buf[t] = 0;
+    if (a < b) {
+      buf[t] = a;
+      keep |= 1u << t;
+      ++i;
+      a = i < ie ? A[i] : KEY_INF;
+    } else if (b < a) {
+      buf[t] = b;
+      keep |= 1u << t;
+      ++j;
+      b = j < je ? B[j] : KEY_INF;
+    } else if (a != KEY_INF) {  // an equal pair: both dropped
+      ++i;
+      ++j;
+      a = i < ie ? A[i] : KEY_INF;
+      b = j < je ? B[j] : KEY_INF;
+    }
+  }
+  uint32_t total;
+  uint32_t pos = w_excl((uint32_t)__popc(keep), lane, &total);
+#pragma unroll
+  for (int t = 0; t <= PER; ++t)
+    if (keep & (1u << t)) out[pos++] = buf[t];
+  *ka = uni(__shfl(ie, 63, 64));
+  *kb = uni(__shfl(je, 63, 64));
   return total;
 }
 
-__device__ inline uint32_t lower_bound_lds(const uint64_t* a, uint32_t n, uint64_t v) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const uint32_t m = (lo + hi) >> 1;
-    if (a[m] < v) lo = m + 1;
-    else hi = m;
-  }
-  return lo;
-}
-__device__ inline uint32_t upper_bound_lds(const uint64_t* a, uint32_t n, uint64_t v) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const uint32_t m = (lo + hi) >> 1;
-    if (a[m] <= v) lo = m + 1;
-    else hi = m;
-  }
-  return lo;
-}
-
-// out = A XOR B, with A and B sorted lists in LDS (|B| <= STAGE); out in LDS.
-// Returns the length.  Uses S.pref for the cancellation prefix over B.
-__device__ uint32_t blk_xor_lds(BlockLds& S, const uint64_t* A, uint32_t na, const uint64_t* B, uint32_t nb,
-                                uint64_t* out) {
-  const uint32_t tid = threadIdx.x;
-  // flags over B: B[j] also in A (these values cancel)
-  for (uint32_t j = tid; j < nb; j += BT) {
-    const uint32_t q = lower_bound_lds(A, na, B[j]);
-    S.pref[j] = (q < na && A[q] == B[j]) ? 1u : 0u;
-  }
-  __syncthreads();
-  // exclusive prefix of the cancel flags, in place (pref[j] = # cancels in B[0:j])
-  {
-    const uint32_t per = (nb + BT - 1) / BT;
-    const uint32_t lo = tid * per < nb ? tid * per : nb, hi = lo + per < nb ? lo + per : nb;
-    uint32_t s = 0;
-    for (uint32_t i = lo; i < hi; ++i) s += S.pref[i];
-    uint32_t total;
-    uint32_t run = blk_excl(s, S.part, &total);
-    for (uint32_t i = lo; i < hi; ++i) {
-      const uint32_t v = S.pref[i];
-      S.pref[i] = run;
-      run += v;
-    }
-    if (tid == 0) S.pref[nb] = total;
-    __syncthreads();
-  }
-  const uint32_t ncancel = S.pref[nb];
-  for (uint32_t i = tid; i < na; i += BT) {
-    const uint64_t v = A[i];
-    const uint32_t r = lower_bound_lds(B, nb, v);
-    if (r < nb && B[r] == v) continue;  // cancelled
-    out[i + r - 2 * S.pref[r]] = v;
-  }
-  for (uint32_t j = tid; j < nb; j += BT) {
-    const uint64_t v = B[j];
-    const uint32_t q = lower_bound_lds(A, na, v);
-    if (q < na && A[q] == v) continue;
-    out[j + q - 2 * S.pref[j]] = v;
-  }
-  __syncthreads();
-  return na + nb - 2 * ncancel;
-}
-
-// out = A XOR B for sorted lists anywhere (global or LDS); out in global
-// memory.  Tiled merge in key order; returns the length.
-__device__ uint32_t blk_xor_tiled(BlockLds& S, const uint64_t* A, uint32_t na, const uint64_t* B, uint32_t nb,
-                                  uint64_t* out) {
-  const uint32_t tid = threadIdx.x;
-  const uint64_t INF = ~0ull;
+// out = A XOR B for sorted lists in LDS; out (LDS) distinct from both.
+__device__ __forceinline__ uint32_t w_xor_lds(const uint64_t* A, uint32_t na, const uint64_t* B, uint32_t nb, uint64_t* out,
+                              int lane) {
   uint32_t ia = 0, ib = 0, o = 0;
   while (ia < na || ib < nb) {
-    const uint32_t la = na - ia < (uint32_t)TILE ? na - ia : TILE;
-    const uint32_t lb = nb - ib < (uint32_t)TILE ? nb - ib : TILE;
-    S.tA[tid] = tid < la ? A[ia + tid] : INF;
-    S.tB[tid] = tid < lb ? B[ib + tid] : INF;
-    if (tid == 0) {
-      S.tA[TILE] = INF;
-      S.tB[TILE] = INF;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      // the next d outputs of the merge come from tA[0:ka] and tB[0:kb]
-      uint32_t d = la + lb < (uint32_t)TILE ? la + lb : TILE;
-      uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
-      while (lo < hi) {  // smallest ka with tA[ka] >= tB[d - ka - 1]
-        const uint32_t ka = (lo + hi) >> 1;
-        if (S.tA[ka] < S.tB[d - ka - 1]) lo = ka + 1;
-        else hi = ka;
-      }
-      uint32_t ka = lo, kb = d - lo;
-      // keep an equal pair in one tile
-      if (ka < la && kb > 0 && S.tA[ka] == S.tB[kb - 1]) ++ka;
-      else if (kb < lb && ka > 0 && S.tB[kb] == S.tA[ka - 1]) ++kb;
-      S.ka = ka;
-      S.kb = kb;
-    }
-    __syncthreads();
-    const uint32_t ka = S.ka, kb = S.kb, m = ka + kb;
-    if (tid < ka) S.tM[tid + lower_bound_lds(S.tB, kb, S.tA[tid])] = S.tA[tid];
-    if (tid < kb) S.tM[tid + upper_bound_lds(S.tA, ka, S.tB[tid])] = S.tB[tid];
-    if (tid + BT < ka) S.tM[tid + BT + lower_bound_lds(S.tB, kb, S.tA[tid + BT])] = S.tA[tid + BT];
-    if (tid + BT < kb) S.tM[tid + BT + upper_bound_lds(S.tA, ka, S.tB[tid + BT])] = S.tB[tid + BT];
-    __syncthreads();
-    for (uint32_t p = tid; p < m; p += BT) {
-      const uint64_t v = S.tM[p];
-      const bool dup = (p > 0 && S.tM[p - 1] == v) || (p + 1 < m && S.tM[p + 1] == v);
-      S.keep[p] = dup ? 0u : 1u;
-    }
-    __syncthreads();
-    uint32_t* pos = S.pref;  // reuse as scan output (m + 1 <= STAGE)
-    const uint32_t kept = blk_scan(S.keep, m, pos, S.part);
-    for (uint32_t p = tid; p < m; p += BT)
-      if (S.keep[p]) out[o + pos[p]] = S.tM[p];
-    o += kept;
+    const uint32_t rem = (na - ia) + (nb - ib);
+    uint32_t ka, kb;
+    o += w_merge_seg(A + ia, na - ia, B + ib, nb - ib, rem < CHUNK ? rem : CHUNK, out + o, lane, &ka, &kb);
     ia += ka;
     ib += kb;
-    __syncthreads();
   }
+  wsync();
   return o;
 }
 
-// Allocates n arena entries for the block (thread 0) and broadcasts the offset.
-__device__ inline uint64_t blk_alloc(const RedCtx& R, BlockLds& S, uint32_t n) {
-  if (threadIdx.x == 0) {
-    const unsigned long long off = atomicAdd(R.arena_top, (unsigned long long)(n ? n : 1));
-    if (off + n > R.arena_cap) {
-      raise_flag(R.st, &R.st->overflow, OVF_ARENA);
-      S.off = ~0ull;
-    } else {
-      S.off = off;
+// out (arena) = A XOR B; each of A and B is in LDS (a_lds / b_lds) or in global
+// memory, in which case it is read through a tile in the stage.
+__device__ __forceinline__ uint32_t w_xor_glob(const WaveBufs& S, const uint64_t* A, uint32_t na, bool a_lds, const uint64_t* B,
+                               uint32_t nb, bool b_lds, uint64_t* out, int lane) {
+  uint32_t ia = 0, ib = 0, o = 0;
+  while (ia < na || ib < nb) {
+    const uint32_t la = na - ia < CHUNK ? na - ia : CHUNK;
+    const uint32_t lb = nb - ib < CHUNK ? nb - ib : CHUNK;
+    const uint64_t* tA = A + ia;
+    const uint64_t* tB = B + ib;
+    if (!a_lds) {
+      for (uint32_t t = lane; t < la; t += 64) S.X[t] = A[ia + t];
+      tA = S.X;
     }
+    if (!b_lds) {
+      for (uint32_t t = lane; t < lb; t += 64) S.X[CHUNK + t] = B[ib + t];
+      tB = S.X + CHUNK;
+    }
+    wsync();
+    uint32_t ka, kb;
+    o += w_merge_seg(tA, la, tB, lb, la + lb < CHUNK ? la + lb : CHUNK, out + o, lane, &ka, &kb);
+    ia += ka;
+    ib += kb;
+    wsync();
   }
-  __syncthreads();
-  return S.off;
+  wsync_global();
+  return o;
 }
 
-// T = T XOR src (any memory), into the arena.  Returns false on exhaustion.
-__device__ inline bool blk_tail_add(const RedCtx& R, BlockLds& S, const uint64_t* src, uint32_t n) {
-  const uint64_t off = blk_alloc(R, S, S.nt + n);
+// Allocates n arena entries (lane 0) and broadcasts the offset (~0 on overflow).
+__device__ __forceinline__ uint64_t w_alloc(const RedCtx& R, uint64_t n, int lane) {
+  unsigned long long off = 0;
+  if (lane == 0) off = arena_alloc(R, n ? n : 1);
+  return __shfl(off, 0, 64);
+}
+
+__device__ __forceinline__ void w_twin_load(WState& W, int lane) {
+  W.tb = W.nt > 64 ? W.nt - 64 : 0;
+  W.tw = (W.tb + (uint32_t)lane < W.nt) ? W.T[W.tb + lane] : 0;
+}
+__device__ __forceinline__ void w_set_tail(WState& W, const uint64_t* T, uint32_t nt, int lane) {
+  W.T = T;
+  W.nt = nt;
+  w_twin_load(W, lane);
+}
+__device__ __forceinline__ void w_tpop(WState& W, int lane) {
+  --W.nt;
+  if (W.nt > 0 && W.nt == W.tb) w_twin_load(W, lane);
+}
+
+// T ^= F (F becomes empty).
+__device__ __forceinline__ bool w_push_front(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
+  if (W.nf == 0) return true;
+  const uint64_t off = w_alloc(R, (uint64_t)W.nt + W.nf, lane);
   if (off == ~0ull) return false;
-  const uint32_t len = blk_xor_tiled(S, S.T, S.nt, src, n, R.arena + off);
-  if (threadIdx.x == 0) {
-    S.T = R.arena + off;
-    S.nt = len;
-    S.merged += len + n;
-  }
-  __syncthreads();
+  const uint32_t len = w_xor_glob(S, W.T, W.nt, false, fbuf(S, W.cur), W.nf, true, R.arena + off, lane);
+  W.merged += W.nt + W.nf;
+  W.nf = 0;
+  w_set_tail(W, R.arena + off, len, lane);
   return true;
 }
 
-// F = F XOR B (B in LDS, |B| <= STAGE); flushes F into T past FB_LIM.
-__device__ inline bool blk_front_add(const RedCtx& R, BlockLds& S, const uint64_t* B, uint32_t nb) {
-  const uint32_t cur = S.cur;
-  const uint32_t n = blk_xor_lds(S, S.F[cur], S.nf, B, nb, S.F[cur ^ 1]);
-  if (threadIdx.x == 0) {
-    S.cur = cur ^ 1;
-    S.nf = n;
-    S.merged += n + nb;
-  }
-  __syncthreads();
-  if (S.nf > FB_LIM) {
-    if (!blk_tail_add(R, S, S.F[S.cur], S.nf)) return false;
-    if (threadIdx.x == 0) S.nf = 0;
-    __syncthreads();
-  }
+// T ^= B for a list B in global memory.
+__device__ __forceinline__ bool w_tail_add(const RedCtx& R, const WaveBufs& S, WState& W, const uint64_t* b, uint32_t nb,
+                           int lane) {
+  const uint64_t off = w_alloc(R, (uint64_t)W.nt + nb, lane);
+  if (off == ~0ull) return false;
+  const uint32_t len = w_xor_glob(S, W.T, W.nt, false, b, nb, false, R.arena + off, lane);
+  W.merged += W.nt + nb;
+  w_set_tail(W, R.arena + off, len, lane);
   return true;
 }
 
-static_assert(sizeof(BlockLds) <= 160 * 1024, "block-mode LDS exceeds the workgroup limit");
+// F ^= X[0..m) (X in LDS), pushing F into T first if the result might not fit.
+__device__ __forceinline__ bool w_front_add(const RedCtx& R, const WaveBufs& S, WState& W, const uint64_t* X, uint32_t m,
+                            int lane) {
+  if (W.nf + m > S.cap && !w_push_front(R, S, W, lane)) return false;
+  W.merged += W.nf + m;
+  W.nf = w_xor_lds(fbuf(S, W.cur), W.nf, X, m, fbuf(S, W.cur ^ 1), lane);
+  W.cur ^= 1;
+  return true;
+}
 
-enum { ACT_APP = 1, ACT_OWNER = 2, ACT_PROPOSE = 3, ACT_STOP = 4 };
+// F ^= P (P becomes empty).
+__device__ __forceinline__ bool w_flush_p(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
+  if (W.np == 0) return true;
+  if ((uint32_t)lane < W.np) S.ps[lane] = W.p;
+  wsync();
+  const uint32_t np = W.np;
+  W.np = 0;
+  return w_front_add(R, S, W, S.ps, np, lane);
+}
 
-__global__ __launch_bounds__(BT) void k_red_round_block(RedCtx R, const uint32_t* __restrict__ list,
-                                                        const unsigned long long* __restrict__ n_list) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  BlockLds& S = *reinterpret_cast<BlockLds*>(lds_raw);
-  const uint32_t tid = threadIdx.x;
-  // every exit decision is taken by thread 0 and broadcast, so all threads of
-  // the workgroup reach the same barriers
-  if (tid == 0) {
-    S.adds = 0;
-    S.merged = 0;
-    S.act = aborted(R.st) ? ACT_STOP : 0;
+// XOR-inserts one wave-uniform key into P (flushing P first if it is full).
+__device__ __forceinline__ bool w_insert(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t b, int lane) {
+  const uint64_t hit = __ballot((uint32_t)lane < W.np && W.p == b);
+  if (hit) {
+    const int pos = __ffsll((unsigned long long)hit) - 1;
+    const uint64_t q = __shfl_down(W.p, 1, 64);
+    if (lane >= pos) W.p = q;
+    --W.np;
+    return true;
   }
-  __syncthreads();
-  if (S.act == ACT_STOP) return;
-  const uint64_t n = *n_list;
-  for (uint64_t li = blockIdx.x; li < n; li += gridDim.x) {
-    const uint32_t c = list[li];
-    // load the stored column: into F if it fits, else as the tail
-    const uint64_t p = R.col_ptr[c];
-    const uint32_t len = (uint32_t)(p & ((1u << 24) - 1));
-    const uint64_t* src = R.arena + (p >> 24);
-    if (len <= FB_LIM) {
-      for (uint32_t i = tid; i < len; i += BT) S.F[0][i] = src[i];
-      if (tid == 0) {
-        S.nf = len;
-        S.nt = 0;
-        S.T = src;
-      }
-    } else if (tid == 0) {
-      S.nf = 0;
-      S.T = src;
-      S.nt = len;
+  if (W.np == 64 && !w_flush_p(R, S, W, lane)) return false;
+  const int pos = __popcll(__ballot((uint32_t)lane < W.np && W.p < b));
+  const uint64_t q = __shfl_up(W.p, 1, 64);
+  if (lane > pos) W.p = q;
+  if (lane == pos) W.p = b;
+  ++W.np;
+  return true;
+}
+
+// P ^= X[0..m) for a staged list with np + m <= 64; F's spare buffer is the output.
+__device__ __forceinline__ void w_p_add(const WaveBufs& S, WState& W, const uint64_t* X, uint32_t m, int lane) {
+  if ((uint32_t)lane < W.np) S.ps[lane] = W.p;
+  wsync();
+  uint64_t* out = fbuf(S, W.cur ^ 1);
+  const uint32_t n = w_xor_lds(S.ps, W.np, X, m, out, lane);
+  W.merged += W.np + m;
+  W.p = (uint32_t)lane < n ? out[lane] : 0;
+  W.np = n;
+  wsync();
+}
+
+// Largest key present an odd number of times among the tops of P, F and T,
+// after dropping equal pairs (0 if the column is empty); *where names the list
+// that holds it afterwards (0 = P, 1 = F, 2 = T).
+__device__ __forceinline__ uint64_t w_pivot(const WaveBufs& S, WState& W, int lane, int* where) {
+  for (;;) {
+    const uint64_t a = W.np ? rdlane64(W.p, W.np - 1) : 0;
+    const uint64_t b = W.nf ? fbuf(S, W.cur)[W.nf - 1] : 0;
+    const uint64_t c = W.nt ? rdlane64(W.tw, W.nt - 1 - W.tb) : 0;
+    uint64_t m = a > b ? a : b;
+    m = m > c ? m : c;
+    if (m == 0) return 0;
+    const int k = (a == m) + (b == m) + (c == m);
+    if (k == 1) {
+      *where = a == m ? 0 : (b == m ? 1 : 2);
+      return m;
     }
-    if (tid == 0) S.cur = 0;
-    __syncthreads();
-    bool ok = true;
-    for (uint32_t it = 0; ok; ++it) {
-      if (tid == 0) {
-        uint32_t act = ACT_STOP;
-        if (it >= RED_ITER_CAP) {
-          raise_flag(R.st, &R.st->iter_cap);
-        } else if (!aborted(R.st)) {
-          // pivot: cancel equal last entries of F and T
-          const uint64_t* F = S.F[S.cur];
-          uint32_t nf = S.nf, nt = S.nt;
-          while (nf && nt && F[nf - 1] == S.T[nt - 1]) {
-            --nf;
-            --nt;
-          }
-          S.nf = nf;
-          S.nt = nt;
-          if (!nf && !nt) {
-            raise_flag(R.st, &R.st->internal);
-          } else {
-            uint64_t e;
-            if (!nf) e = S.T[nt - 1];
-            else if (!nt) e = F[nf - 1];
-            else e = F[nf - 1] > S.T[nt - 1] ? F[nf - 1] : S.T[nt - 1];
-            S.e = e;
-            const int im = skey_img(R.L, e);
-            const ImgDesc d = R.imgs[im];
-            int ec[3];
-            kidx_coords(d, skey_kidx(R.L, e), ec);
-            const int na = apparent_bnd(R, im, d, ec, e, S.bnd);
-            if (na > 0) {
-              S.na = (uint32_t)na;
-              act = ACT_APP;
-            } else {
-              const int64_t slot = edge_slot(d, ec);
-              const int32_t o = R.owner[slot];
-              S.slot = slot;
-              S.o = o;
-              if (o >= 0 && (uint32_t)o < c) act = ACT_OWNER;
-              else if ((uint32_t)o == c) raise_flag(R.st, &R.st->internal);
-              else act = ACT_PROPOSE;
-            }
-          }
-        }
-        S.act = act;
-        if (act == ACT_APP || act == ACT_OWNER) S.adds += 1;
-      }
-      __syncthreads();
-      const uint32_t act = S.act;
-      if (act == ACT_STOP) {
-        ok = false;
-      } else if (act == ACT_APP) {
-        ok = blk_front_add(R, S, S.bnd, S.na);
-      } else if (act == ACT_OWNER) {
-        const uint64_t q = R.col_ptr[S.o];
-        const uint32_t ql = (uint32_t)(q & ((1u << 24) - 1));
-        const uint64_t* qs = R.arena + (q >> 24);
-        if (ql <= STAGE) {
-          for (uint32_t i = tid; i < ql; i += BT) S.stage[i] = qs[i];
-          __syncthreads();
-          ok = blk_front_add(R, S, S.stage, ql);
-        } else {
-          ok = blk_tail_add(R, S, qs, ql);
-        }
-      } else {  // ACT_PROPOSE: store F XOR T and propose c for e
-        const uint64_t off = blk_alloc(R, S, S.nf + S.nt);
-        if (off != ~0ull) {
-          const uint32_t l = blk_xor_tiled(S, S.F[S.cur], S.nf, S.T, S.nt, R.arena + off);
-          if (tid == 0) {
-            if (l >= (1u << 24)) {
-              raise_flag(R.st, &R.st->overflow, OVF_COLUMN);
-            } else {
-              R.col_ptr[c] = pack_col(off, l);
-              R.piv[c] = S.e;
-              atomicMin(&R.claim[S.slot], (int32_t)c);
-            }
-          }
-        }
-        ok = false;
-      }
-      __syncthreads();
+    // two copies cancel; with three, the one in T remains
+    if (a == m) --W.np;
+    if (b == m) --W.nf;
+    if (k == 2 && c == m) w_tpop(W, lane);
+    if (k == 3) {
+      *where = 2;
+      return m;
     }
   }
-  if (tid == 0 && S.adds) {
-    atomicAdd(&R.st->adds, S.adds);
-    atomicAdd(&R.st->merged, S.merged);
+}
+
+__device__ __forceinline__ void w_pop(WState& W, int where, int lane) {
+  if (where == 0) --W.np;
+  else if (where == 1) --W.nf;
+  else w_tpop(W, lane);
+}
+
+template <typename T>
+__device__ __forceinline__ T sel3(int i, T a, T b, T c) { return i == 0 ? a : (i == 1 ? b : c); }
+__device__ __forceinline__ float pix_val(const float* img, int64_t p) {
+  const float v = img[p];
+  return (v != v) ? INFINITY : canon(v);
+}
+__device__ __forceinline__ uint32_t ord_of(float v) {
+  uint32_t bits;
+  __builtin_memcpy(&bits, &v, 4);
+  return ord32_bits(bits);
+}
+
+// Reduces column c for one round in wave mode: until its pivot has no owner to
+// its left, then stores it and proposes it for its pivot.
+__device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c, uint64_t off2,
+                                   int lane) {
+  const int im = skey_img(R.L, R.skeys[off2 + c]);  // every edge of the column lies in this image
+  const ImgDesc d = R.imgs[im];
+  const uint32_t K1 = (uint32_t)d.K[1], K2 = (uint32_t)d.K[2];
+  const int64_t ps0 = (int64_t)d.n[1] * d.n[2], ps1 = d.n[2];
+  const uint32_t ks0 = K1 * K2, ks1 = K2;
+  {
+    const uint64_t off = R.col_ptr[c];
+    const uint32_t len = (uint32_t)R.arena[off];
+    const uint64_t* src = R.arena + off + 1;
+    W.np = 0;
+    W.cur = 0;
+    if (len <= S.cap) {
+      for (uint32_t i = lane; i < len; i += 64) S.F0[i] = src[i];
+      W.nf = len;
+      w_set_tail(W, src, 0, lane);
+    } else {
+      W.nf = 0;
+      w_set_tail(W, src, len, lane);
+    }
+    wsync();
+  }
+  for (uint32_t it = 0;; ++it) {
+    if (it >= RED_ITER_CAP) {
+      if (lane == 0) raise_flag(R.st, &R.st->iter_cap);
+      return;
+    }
+    if ((it & 63) == 63 && aborted(R.st)) return;
+    int where = 0;
+    const uint64_t e = w_pivot(S, W, lane, &where);
+    if (e == 0) {  // a zero column: impossible after clearing
+      if (lane == 0) raise_flag(R.st, &R.st->internal);
+      return;
+    }
+    // the pivot edge: Khalimsky coordinates, axis, anchor pixel
+    const uint32_t kidx = skey_kidx(R.L, e);
+    const uint32_t kx = kidx % K2, t1 = kidx / K2;
+    const uint32_t ky = t1 % K1, kz = t1 / K1;
+    if ((e >> (R.L.ib + 32 + R.L.kb)) != 1 || skey_img(R.L, e) != im || kz >= (uint32_t)d.K[0] ||
+        ((kz & 1) + (ky & 1) + (kx & 1)) != 1) {  // not an edge of this image: a broken invariant
+      if (lane == 0) raise_flag(R.st, &R.st->internal);
+      return;
+    }
+    const int ax = (kz & 1) ? 0 : ((ky & 1) ? 1 : 2);
+    const int b0 = ax == 0 ? 1 : 0, b1 = ax == 2 ? 1 : 2;  // the two other axes
+    const int64_t pax = sel3(ax, ps0, ps1, (int64_t)1);
+    const uint32_t kax = sel3(ax, ks0, ks1, 1u);
+    const int64_t anchor = pixel_index(d, (int)(kz >> 1), (int)(ky >> 1), (int)(kx >> 1));
+    const int64_t slot = 3 * anchor + ax;
+    // one group of loads: lanes 0/1 the edge's endpoints, lanes 2..9 the far
+    // vertices of the four squares around it, lane 10 the apparent code, lane 11
+    // the owner word
+    float pv = 0.0f;
+    uint32_t code = 0xFF;
+    uint64_t ow = NO_OWNER;
+    if (lane < 10) {
+      int64_t p = anchor;
+      bool ok = true;
+      if (lane == 1) {
+        p += pax;
+      } else if (lane >= 2) {
+        const int q = lane - 2;
+        const int bb = (q >> 2) ? b1 : b0;
+        const int sg = (q & 2) ? 1 : -1;
+        const int vb = (int)(sel3(bb, kz, ky, kx) >> 1) + sg;
+        ok = vb >= 0 && vb < sel3(bb, d.n[0], d.n[1], d.n[2]);
+        p += (q & 1) * pax + sg * sel3(bb, ps0, ps1, (int64_t)1);
+      }
+      if (ok) pv = pix_val(R.img, p);
+    } else if (lane == 10) {
+      code = R.eapp[slot];
+    } else if (lane == 11) {
+      ow = R.owner[slot];
+    }
+    code = (uint32_t)__builtin_amdgcn_readlane((int)code, 10);
+    W.adds += 1;
+    if (code != 0xFF) {
+      // apparent partner s: its boundary is e and three older edges
+      const int bb = (int)(code >> 1);
+      const int sg = (code & 1) ? 1 : -1;
+      const int q = 2 + ((bb == b1) ? 4 : 0) + (sg > 0 ? 2 : 0);
+      const float v0 = __shfl(pv, 0, 64), v1 = __shfl(pv, 1, 64);
+      const float w0 = __shfl(pv, q, 64), w1 = __shfl(pv, q + 1, 64);
+      const uint32_t kb = (uint32_t)((int)sel3(bb, ks0, ks1, 1u) * sg);
+      const uint64_t kw = make_skey(R.L, 1, im, ord_of(fmaxf(w0, w1)), kidx + 2 * kb);
+      const uint64_t ka0 = make_skey(R.L, 1, im, ord_of(fmaxf(v0, w0)), kidx - kax + kb);
+      const uint64_t ka1 = make_skey(R.L, 1, im, ord_of(fmaxf(v1, w1)), kidx + kax + kb);
+      if (kw >= e || ka0 >= e || ka1 >= e) {  // e must be the latest facet of s
+        if (lane == 0) raise_flag(R.st, &R.st->internal);
+        return;
+      }
+      w_pop(W, where, lane);
+      if (!w_insert(R, S, W, kw, lane) || !w_insert(R, S, W, ka0, lane) || !w_insert(R, S, W, ka1, lane)) return;
+      continue;
+    }
+    ow = rdlane64(ow, 11);
+    const int32_t o = ow == NO_OWNER ? -1 : (int32_t)(ow >> 32);
+    if (o >= 0 && (uint32_t)o < c) {  // add the column of o (its top key is e)
+      const uint64_t* q = R.arena + (uint32_t)ow;
+      const uint64_t head = q[lane];  // length word and the first 63 keys
+      const uint32_t len = (uint32_t)rdlane64(head, 0);
+      const uint32_t m = len - 1;     // keys below e
+      w_pop(W, where, lane);
+      if (m + W.np <= 64 && m <= 63) {  // the loaded head holds keys 0..62
+        if (lane >= 1 && (uint32_t)lane <= m) S.X[lane - 1] = head;
+        wsync();
+        w_p_add(S, W, S.X, m, lane);
+      } else if (m <= XN && m <= S.cap) {
+        // make room first: pushing F into T uses the stage for its tiles
+        if (W.nf + m > S.cap && !w_push_front(R, S, W, lane)) return;
+        if (lane >= 1 && (uint32_t)lane <= m) S.X[lane - 1] = head;
+        for (uint32_t i = 63 + lane; i < m; i += 64) S.X[i] = q[1 + i];
+        wsync();
+        if (!w_front_add(R, S, W, S.X, m, lane)) return;
+      } else {
+        if (!w_tail_add(R, S, W, q + 1, m, lane)) return;
+      }
+      continue;
+    }
+    if ((uint32_t)o == c) {
+      if (lane == 0) raise_flag(R.st, &R.st->internal);
+      return;
+    }
+    // store P ^ F ^ T and propose c for e
+    if (!w_flush_p(R, S, W, lane)) return;
+    const uint64_t off = w_alloc(R, (uint64_t)W.nf + W.nt + 1, lane);
+    if (off == ~0ull) return;
+    uint32_t len;
+    if (W.nt == 0) {
+      for (uint32_t i = lane; i < W.nf; i += 64) R.arena[off + 1 + i] = fbuf(S, W.cur)[i];
+      len = W.nf;
+    } else {
+      len = w_xor_glob(S, W.T, W.nt, false, fbuf(S, W.cur), W.nf, true, R.arena + off + 1, lane);
+    }
+    if (lane == 0) {
+      R.arena[off] = len;
+      R.col_ptr[c] = off;
+      R.piv[c] = e;
+      atomicMin(&R.claim[slot], (int32_t)c);
+    }
+    return;
+  }
+}
+
+// Wave-mode round over the long-column list (and the short list when it has at
+// most R.wave_short columns); columns are taken from a counter.
+__global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uint32_t* __restrict__ list_s,
+                                                             const unsigned long long* __restrict__ n_s,
+                                                             const uint32_t* __restrict__ list_l,
+                                                             const unsigned long long* __restrict__ n_l) {
+  extern __shared__ __align__(16) uint64_t lds_words[];
+  if (aborted(R.st)) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint64_t* base = lds_words + (size_t)wv * wave_lds_words(R.front_cap);
+  WaveBufs S;
+  S.cap = R.front_cap;
+  S.F0 = base;
+  S.F1 = base + S.cap;
+  S.X = base + 2 * (size_t)S.cap;
+  S.ps = S.X + XN;
+  const uint64_t nl = *n_l, ns0 = *n_s;
+  const uint64_t ns = ns0 <= R.wave_short ? ns0 : 0;
+  const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
+  WState W;
+  W.adds = 0;
+  W.merged = 0;
+  for (;;) {
+    unsigned long long li = 0;
+    if (lane == 0) li = atomicAdd(R.work, 1ull);
+    li = __shfl(li, 0, 64);
+    if (li >= nl + ns || aborted(R.st)) break;
+    const uint32_t c = li < nl ? list_l[li] : list_s[li - nl];
+    reduce_column_wave(R, S, W, c, off2, lane);
+    wsync();
+  }
+  if (lane == 0 && W.adds) {
+    atomicAdd(&R.st->adds, W.adds);
+    atomicAdd(&R.st->merged, W.merged);
   }
 }
 
@@ -713,7 +842,7 @@ __device__ inline int64_t pivot_slot(const RedCtx& R, uint64_t e) {
 
 // Commit: the leftmost proposer of each pivot becomes its owner; losers and
 // displaced owners go to the next round's lists (long stored columns to the
-// block-mode list).  Yielded columns were already listed.
+// wave-mode list).  Yielded columns were already listed.
 __global__ void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t, const unsigned long long* __restrict__ n_t,
                              const uint32_t* __restrict__ list_b, const unsigned long long* __restrict__ n_b,
                              int first, uint32_t* next_t, uint32_t* next_b, unsigned long long* __restrict__ n_next) {
@@ -739,15 +868,15 @@ __global__ void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t, cons
         const int64_t slot = pivot_slot(R, e);
         bool push = true;
         if (R.claim[slot] == (int32_t)c) {
-          const int32_t old = R.owner[slot];
-          R.owner[slot] = (int32_t)c;
-          push = old >= 0;
-          again = (uint32_t)old;
+          const uint64_t old = R.owner[slot];
+          R.owner[slot] = ((uint64_t)c << 32) | R.col_ptr[c];
+          push = old != NO_OWNER;
+          again = (uint32_t)(old >> 32);
         } else {
           again = c;
         }
         if (push) {
-          const bool lng = (uint32_t)(R.col_ptr[again] & ((1u << 24) - 1)) > R.long_len;
+          const bool lng = R.arena[R.col_ptr[again]] > R.long_len;
           again_long = lng;
           again_short = !lng;
         }
@@ -796,7 +925,8 @@ __global__ void k_h1_emit(RedCtx R, EmitCtx E) {
       const ImgDesc d = R.imgs[skey_img(R.L, e)];
       int ec[3];
       kidx_coords(d, skey_kidx(R.L, e), ec);
-      if (R.owner[edge_slot(d, ec)] != (int32_t)c) raise_flag(R.st, &R.st->internal);
+      const uint64_t ow = R.owner[edge_slot(d, ec)];
+      if (ow == NO_OWNER || (uint32_t)(ow >> 32) != (uint32_t)c) raise_flag(R.st, &R.st->internal);
       else active = pair_row(E, e, R.skeys[off2 + c], false, &im, &ck);
     }
     emit_rows(E, active, im, ck);
@@ -805,9 +935,9 @@ __global__ void k_h1_emit(RedCtx R, EmitCtx E) {
 
 RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64_t* skeys,
                    const unsigned long long* dim_count, const uint8_t* cleared, const uint8_t* eapp,
-                   int32_t* owner, int32_t* claim,
+                   uint64_t* owner, int32_t* claim,
                    uint64_t* piv, uint64_t* col_ptr, uint64_t* arena, uint64_t arena_cap,
-                   unsigned long long* arena_top, uint64_t* pbuf, Status* st) {
+                   unsigned long long* arena_top, unsigned long long* work, uint64_t* pbuf, Status* st) {
   RedCtx R;
   R.img = img;
   R.imgs = imgs;
@@ -823,32 +953,40 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.arena = arena;
   R.arena_cap = arena_cap;
   R.arena_top = arena_top;
+  R.work = work;
   R.pbuf = pbuf;
   R.st = st;
   R.long_len = 128;
   R.yield_iters = 32;
+  R.wave_short = 4096;
+  R.front_cap = 4096;
   return R;
 }
 
 void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round0,
                       int nrounds, hipStream_t s) {
-  static bool lds_set = false;
-  if (!lds_set) {
-    (void)hipFuncSetAttribute((const void*)k_red_round_block, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)sizeof(BlockLds));
-    lds_set = true;
+  const size_t lds = WPB * 8 * wave_lds_words(R.front_cap);
+  static size_t lds_set = 0;
+  if (lds_set < lds) {
+    (void)hipFuncSetAttribute((const void*)k_red_round_wave, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    lds_set = lds;
   }
+  int dev = 0, ncu = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int per_cu = lds <= 80 * 1024 ? 2 : 1;
+  const int wgrid = ncu * per_cu;
   for (int r = round0; r < round0 + nrounds; ++r) {
     const int cur = r & 1, nxt = (r + 1) & 1;
     const int first = r == 0;
-    // lists[2*k + 0] short (thread mode), lists[2*k + 1] long (block mode); counts likewise
+    // lists[2*k + 0] short (thread mode), lists[2*k + 1] long (wave mode); counts likewise
     uint32_t* lt = lists[2 * cur];
     uint32_t* lb = lists[2 * cur + 1];
     unsigned long long* ct = counts + 2 * cur;
     unsigned long long* cnx = counts + 2 * nxt;
-    k_fill_count<<<1, 1, 0, s>>>(cnx);
+    k_fill_count<<<1, 1, 0, s>>>(cnx, R.work);
     k_red_round<<<grid, 256, 0, s>>>(R, lt, ct, first, lists[2 * nxt + 1], cnx + 1);
-    if (!first) k_red_round_block<<<BLOCK_GRID, BT, sizeof(BlockLds), s>>>(R, lb, ct + 1);
+    if (!first) k_red_round_wave<<<wgrid, 64 * WPB, lds, s>>>(R, lt, ct, lb, ct + 1);
     k_red_commit<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first, lists[2 * nxt], lists[2 * nxt + 1], cnx);
     k_red_reset<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first);
   }

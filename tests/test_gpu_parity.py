@@ -161,10 +161,20 @@ def test_deterministic_repeat():
         assert_same(b, a, "repeat")
 
 
-def test_block_mode_forced():
-    """Volumes whose columns are handed to the workgroup-per-column mode after a
-    few additions (thresholds lowered through the environment, which the
-    library reads at every call)."""
+WAVE_ENV = ("CR_LONG_LEN", "CR_YIELD_ITERS", "CR_WAVE_SHORT", "CR_FRONT_CAP")
+
+
+@pytest.mark.parametrize("setting", [
+    ("0", "2", "0", "4096"),        # every column to wave mode after two additions
+    ("8", "8", "0", "4096"),
+    ("0", "1", "1000000", "128"),   # whole rounds in wave mode, tiny front list: tail merges
+    ("4", "4", "64", "200"),
+])
+def test_wave_mode_forced(setting):
+    """Volumes whose columns are handed to the wavefront-per-column mode after a
+    few additions, with small front lists so that the tail merges run (the
+    thresholds are lowered through the environment, which the library reads at
+    every call)."""
     import os
     rng = np.random.default_rng(5)
     cases = [(synth.blobs3d(16, 1), "blobs 16"), (synth.blobs3d(24, 2), "blobs 24"),
@@ -172,11 +182,10 @@ def test_block_mode_forced():
              (rng.integers(0, 3, size=(9, 10, 11)).astype(np.float32), "ties"),
              (synth.grf_seeded((20, 18, 22), 1.5, 4), "grf")]
     try:
-        for long_len, yield_iters in [("0", "2"), ("8", "8")]:
-            os.environ["CR_LONG_LEN"] = long_len
-            os.environ["CR_YIELD_ITERS"] = yield_iters
-            for img, label in cases:
-                check(img, label=f"{label} long_len={long_len}")
+        for k, v in zip(WAVE_ENV, setting):
+            os.environ[k] = v
+        for img, label in cases:
+            check(img, label=f"{label} {setting}")
     finally:
-        os.environ.pop("CR_LONG_LEN", None)
-        os.environ.pop("CR_YIELD_ITERS", None)
+        for k in WAVE_ENV:
+            os.environ.pop(k, None)
