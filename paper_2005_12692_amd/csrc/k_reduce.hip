@@ -348,8 +348,10 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
 // lanes.  Every step is wave-synchronous: no workgroup barriers.
 constexpr int WPB = 2;                 // wavefronts per workgroup
 constexpr uint32_t XN = 1024;          // addend stage / two merge tiles
-constexpr int PER = 8;                 // merge positions per lane per chunk
-constexpr uint32_t CHUNK = 64 * PER;   // merge positions per chunk (= one tile)
+constexpr int PER = 8;                 // merge positions per lane per chunk of a tiled (global) merge
+constexpr uint32_t CHUNK = 64 * PER;   // merge positions per tile chunk (= one tile)
+constexpr int PER_WIDE = 16;           // ... of a long LDS merge
+constexpr int PER_NARROW = 2;          // ... of a merge of at most 128 keys
 constexpr uint64_t KEY_INF = ~0ull;    // above every key
 static_assert(2 * CHUNK <= XN, "two merge tiles must fit the stage");
 
@@ -390,15 +392,19 @@ __device__ __forceinline__ uint64_t rdlane64(uint64_t v, uint32_t i) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Wave exclusive scan of one value per lane; returns the prefix, sets *total.
-__device__ __forceinline__ uint32_t w_excl(uint32_t v, int lane, uint32_t* total) {
-  uint32_t incl = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t up = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += up;
+// Exclusive prefix over the wave of a count below 2^BITS per lane, from one
+// ballot per bit; sets *total.
+template <int BITS>
+__device__ __forceinline__ uint32_t w_excl_small(uint32_t v, uint32_t* total) {
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int bit = 0; bit < BITS; ++bit) {
+    const uint64_t bm = __ballot((v >> bit) & 1u);
+    pre += __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u)) << bit;
+    tot += (uint32_t)__popcll(bm) << bit;
   }
-  *total = uni(__shfl(incl, 63, 64));
-  return incl - v;
+  *total = tot;
+  return pre;
 }
 
 // Number of A elements among the first d positions of the merge of A and B,
@@ -414,14 +420,18 @@ __device__ __forceinline__ uint32_t mp_split(const uint64_t* A, uint32_t na, con
 }
 
 // Writes the XOR of the first d merge positions of A and B (LDS, ascending;
-// equal pairs dropped) ascending to out, d <= CHUNK.  An equal pair is never
+// equal pairs dropped) ascending to out, d <= 64 * P.  An equal pair is never
 // split: if position d falls between its two copies the second is consumed
 // too.  A or B may be a tile of a longer list as long as it holds at least d
 // keys or all that remain.  Sets *ka, *kb to the keys consumed; returns the
 // number written.
-__device__ __forceinline__ uint32_t w_merge_seg(const uint64_t* A, uint32_t na, const uint64_t* B, uint32_t nb, uint32_t d,
-                                uint64_t* out, int lane, uint32_t* ka, uint32_t* kb) {
-  const uint32_t dend = (uint32_t)(lane + 1) * PER < d ? (uint32_t)(lane + 1) * PER : d;
+struct SegResult {
+  uint32_t written, ka, kb;
+};
+template <int P>
+__device__ __forceinline__ SegResult w_merge_seg(const uint64_t* A, uint32_t na, const uint64_t* B, uint32_t nb,
+                                                 uint32_t d, uint64_t* out, int lane) {
+  const uint32_t dend = (uint32_t)(lane + 1) * P < d ? (uint32_t)(lane + 1) * P : d;
   const uint32_t ie = mp_split(A, na, B, nb, dend);
   uint32_t je = dend - ie;
   if (ie > 0 && je < nb && A[ie - 1] == B[je]) ++je;
@@ -433,10 +443,10 @@ __device__ __forceinline__ uint32_t w_merge_seg(const uint64_t* A, uint32_t na, 
   uint32_t i = is, j = js;
   uint64_t a = i < ie ? A[i] : KEY_INF;
   uint64_t b = j < je ? B[j] : KEY_INF;
-  uint64_t buf[PER + 1];
+  uint64_t buf[P + 1];
   uint32_t keep = 0;
 #pragma unroll
-  for (int t = 0; t <= PER; ++t) {
+  for (int t = 0; t <= P; ++t) {
     buf[t] = 0;
     if (a < b) {
       buf[t] = a;
@@ -456,25 +466,30 @@ __device__ __forceinline__ uint32_t w_merge_seg(const uint64_t* A, uint32_t na, 
     }
   }
   uint32_t total;
-  uint32_t pos = w_excl((uint32_t)__popc(keep), lane, &total);
+  uint32_t pos = w_excl_small<(P < 8 ? 3 : (P < 16 ? 4 : 5))>((uint32_t)__popc(keep), &total);
 #pragma unroll
-  for (int t = 0; t <= PER; ++t)
+  for (int t = 0; t <= P; ++t)
     if (keep & (1u << t)) out[pos++] = buf[t];
-  *ka = uni(__shfl(ie, 63, 64));
-  *kb = uni(__shfl(je, 63, 64));
-  return total;
+  SegResult r;
+  r.written = total;
+  r.ka = (uint32_t)__builtin_amdgcn_readlane((int)ie, 63);
+  r.kb = (uint32_t)__builtin_amdgcn_readlane((int)je, 63);
+  return r;
 }
 
-// out = A XOR B for sorted lists in LDS; out (LDS) distinct from both.
-__device__ __forceinline__ uint32_t w_xor_lds(const uint64_t* A, uint32_t na, const uint64_t* B, uint32_t nb, uint64_t* out,
-                              int lane) {
+// out = A XOR B for sorted lists in LDS; out (LDS) distinct from both.  Out of
+// line (like the global merge) to keep the per-iteration code compact.
+template <int P>
+__device__ __noinline__ uint32_t w_xor_lds(const uint64_t* A, uint32_t na, const uint64_t* B, uint32_t nb,
+                                           uint64_t* out, int lane) {
   uint32_t ia = 0, ib = 0, o = 0;
   while (ia < na || ib < nb) {
     const uint32_t rem = (na - ia) + (nb - ib);
-    uint32_t ka, kb;
-    o += w_merge_seg(A + ia, na - ia, B + ib, nb - ib, rem < CHUNK ? rem : CHUNK, out + o, lane, &ka, &kb);
-    ia += ka;
-    ib += kb;
+    const SegResult r =
+        w_merge_seg<P>(A + ia, na - ia, B + ib, nb - ib, rem < 64u * P ? rem : 64u * P, out + o, lane);
+    o += r.written;
+    ia += r.ka;
+    ib += r.kb;
   }
   wsync();
   return o;
@@ -482,8 +497,8 @@ __device__ __forceinline__ uint32_t w_xor_lds(const uint64_t* A, uint32_t na, co
 
 // out (arena) = A XOR B; each of A and B is in LDS (a_lds / b_lds) or in global
 // memory, in which case it is read through a tile in the stage.
-__device__ __forceinline__ uint32_t w_xor_glob(const WaveBufs& S, const uint64_t* A, uint32_t na, bool a_lds, const uint64_t* B,
-                               uint32_t nb, bool b_lds, uint64_t* out, int lane) {
+__device__ __noinline__ uint32_t w_xor_glob(uint64_t* X, const uint64_t* A, uint32_t na, bool a_lds,
+                                            const uint64_t* B, uint32_t nb, bool b_lds, uint64_t* out, int lane) {
   uint32_t ia = 0, ib = 0, o = 0;
   while (ia < na || ib < nb) {
     const uint32_t la = na - ia < CHUNK ? na - ia : CHUNK;
@@ -491,18 +506,18 @@ __device__ __forceinline__ uint32_t w_xor_glob(const WaveBufs& S, const uint64_t
     const uint64_t* tA = A + ia;
     const uint64_t* tB = B + ib;
     if (!a_lds) {
-      for (uint32_t t = lane; t < la; t += 64) S.X[t] = A[ia + t];
-      tA = S.X;
+      for (uint32_t t = lane; t < la; t += 64) X[t] = A[ia + t];
+      tA = X;
     }
     if (!b_lds) {
-      for (uint32_t t = lane; t < lb; t += 64) S.X[CHUNK + t] = B[ib + t];
-      tB = S.X + CHUNK;
+      for (uint32_t t = lane; t < lb; t += 64) X[CHUNK + t] = B[ib + t];
+      tB = X + CHUNK;
     }
     wsync();
-    uint32_t ka, kb;
-    o += w_merge_seg(tA, la, tB, lb, la + lb < CHUNK ? la + lb : CHUNK, out + o, lane, &ka, &kb);
-    ia += ka;
-    ib += kb;
+    const SegResult r = w_merge_seg<PER>(tA, la, tB, lb, la + lb < CHUNK ? la + lb : CHUNK, out + o, lane);
+    o += r.written;
+    ia += r.ka;
+    ib += r.kb;
     wsync();
   }
   wsync_global();
@@ -535,7 +550,7 @@ __device__ __forceinline__ bool w_push_front(const RedCtx& R, const WaveBufs& S,
   if (W.nf == 0) return true;
   const uint64_t off = w_alloc(R, (uint64_t)W.nt + W.nf, lane);
   if (off == ~0ull) return false;
-  const uint32_t len = w_xor_glob(S, W.T, W.nt, false, fbuf(S, W.cur), W.nf, true, R.arena + off, lane);
+  const uint32_t len = w_xor_glob(S.X, W.T, W.nt, false, fbuf(S, W.cur), W.nf, true, R.arena + off, lane);
   W.merged += W.nt + W.nf;
   W.nf = 0;
   w_set_tail(W, R.arena + off, len, lane);
@@ -547,7 +562,7 @@ __device__ __forceinline__ bool w_tail_add(const RedCtx& R, const WaveBufs& S, W
                            int lane) {
   const uint64_t off = w_alloc(R, (uint64_t)W.nt + nb, lane);
   if (off == ~0ull) return false;
-  const uint32_t len = w_xor_glob(S, W.T, W.nt, false, b, nb, false, R.arena + off, lane);
+  const uint32_t len = w_xor_glob(S.X, W.T, W.nt, false, b, nb, false, R.arena + off, lane);
   W.merged += W.nt + nb;
   w_set_tail(W, R.arena + off, len, lane);
   return true;
@@ -558,7 +573,7 @@ __device__ __forceinline__ bool w_front_add(const RedCtx& R, const WaveBufs& S, 
                             int lane) {
   if (W.nf + m > S.cap && !w_push_front(R, S, W, lane)) return false;
   W.merged += W.nf + m;
-  W.nf = w_xor_lds(fbuf(S, W.cur), W.nf, X, m, fbuf(S, W.cur ^ 1), lane);
+  W.nf = w_xor_lds<PER_WIDE>(fbuf(S, W.cur), W.nf, X, m, fbuf(S, W.cur ^ 1), lane);
   W.cur ^= 1;
   return true;
 }
@@ -573,19 +588,34 @@ __device__ __forceinline__ bool w_flush_p(const RedCtx& R, const WaveBufs& S, WS
   return w_front_add(R, S, W, S.ps, np, lane);
 }
 
+// Whole-wavefront lane shifts (DPP): lane i receives lane i+1 (down) or lane
+// i-1 (up); the end lane keeps its own value.
+__device__ __forceinline__ uint64_t wave_down1(uint64_t v) {
+  const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+  const uint32_t l = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xF, 0xF, false);
+  const uint32_t h = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xF, 0xF, false);
+  return ((uint64_t)h << 32) | l;
+}
+__device__ __forceinline__ uint64_t wave_up1(uint64_t v) {
+  const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+  const uint32_t l = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xF, 0xF, false);
+  const uint32_t h = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xF, 0xF, false);
+  return ((uint64_t)h << 32) | l;
+}
+
 // XOR-inserts one wave-uniform key into P (flushing P first if it is full).
 __device__ __forceinline__ bool w_insert(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t b, int lane) {
   const uint64_t hit = __ballot((uint32_t)lane < W.np && W.p == b);
   if (hit) {
     const int pos = __ffsll((unsigned long long)hit) - 1;
-    const uint64_t q = __shfl_down(W.p, 1, 64);
+    const uint64_t q = wave_down1(W.p);
     if (lane >= pos) W.p = q;
     --W.np;
     return true;
   }
   if (W.np == 64 && !w_flush_p(R, S, W, lane)) return false;
   const int pos = __popcll(__ballot((uint32_t)lane < W.np && W.p < b));
-  const uint64_t q = __shfl_up(W.p, 1, 64);
+  const uint64_t q = wave_up1(W.p);
   if (lane > pos) W.p = q;
   if (lane == pos) W.p = b;
   ++W.np;
@@ -597,7 +627,7 @@ __device__ __forceinline__ void w_p_add(const WaveBufs& S, WState& W, const uint
   if ((uint32_t)lane < W.np) S.ps[lane] = W.p;
   wsync();
   uint64_t* out = fbuf(S, W.cur ^ 1);
-  const uint32_t n = w_xor_lds(S.ps, W.np, X, m, out, lane);
+  const uint32_t n = w_xor_lds<PER_NARROW>(S.ps, W.np, X, m, out, lane);
   W.merged += W.np + m;
   W.p = (uint32_t)lane < n ? out[lane] : 0;
   W.np = n;
@@ -639,9 +669,8 @@ __device__ __forceinline__ void w_pop(WState& W, int where, int lane) {
 
 template <typename T>
 __device__ __forceinline__ T sel3(int i, T a, T b, T c) { return i == 0 ? a : (i == 1 ? b : c); }
-__device__ __forceinline__ float pix_val(const float* img, int64_t p) {
-  const float v = img[p];
-  return (v != v) ? INFINITY : canon(v);
+__device__ __forceinline__ float rdlane_f(float v, uint32_t i) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)i));
 }
 __device__ __forceinline__ uint32_t ord_of(float v) {
   uint32_t bits;
@@ -704,28 +733,26 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
     // one group of loads: lanes 0/1 the edge's endpoints, lanes 2..9 the far
     // vertices of the four squares around it, lane 10 the apparent code, lane 11
     // the owner word
-    float pv = 0.0f;
+    int64_t p = anchor;
+    bool pix_ok = lane < 10;
+    if (lane == 1) {
+      p += pax;
+    } else if (lane >= 2 && lane < 10) {
+      const int q = lane - 2;
+      const int bb = (q >> 2) ? b1 : b0;
+      const int sg = (q & 2) ? 1 : -1;
+      const int vb = (int)(sel3(bb, kz, ky, kx) >> 1) + sg;
+      pix_ok = vb >= 0 && vb < sel3(bb, d.n[0], d.n[1], d.n[2]);
+      p += (q & 1) * pax + sg * sel3(bb, ps0, ps1, (int64_t)1);
+    }
+    // raw loads first, every use after them, so that the three are in flight together
+    float praw = 0.0f;
     uint32_t code = 0xFF;
     uint64_t ow = NO_OWNER;
-    if (lane < 10) {
-      int64_t p = anchor;
-      bool ok = true;
-      if (lane == 1) {
-        p += pax;
-      } else if (lane >= 2) {
-        const int q = lane - 2;
-        const int bb = (q >> 2) ? b1 : b0;
-        const int sg = (q & 2) ? 1 : -1;
-        const int vb = (int)(sel3(bb, kz, ky, kx) >> 1) + sg;
-        ok = vb >= 0 && vb < sel3(bb, d.n[0], d.n[1], d.n[2]);
-        p += (q & 1) * pax + sg * sel3(bb, ps0, ps1, (int64_t)1);
-      }
-      if (ok) pv = pix_val(R.img, p);
-    } else if (lane == 10) {
-      code = R.eapp[slot];
-    } else if (lane == 11) {
-      ow = R.owner[slot];
-    }
+    if (pix_ok) praw = R.img[p];
+    if (lane == 10) code = R.eapp[slot];
+    if (lane == 11) ow = R.owner[slot];
+    const float pv = (praw != praw) ? INFINITY : canon(praw);
     code = (uint32_t)__builtin_amdgcn_readlane((int)code, 10);
     W.adds += 1;
     if (code != 0xFF) {
@@ -733,8 +760,8 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
       const int bb = (int)(code >> 1);
       const int sg = (code & 1) ? 1 : -1;
       const int q = 2 + ((bb == b1) ? 4 : 0) + (sg > 0 ? 2 : 0);
-      const float v0 = __shfl(pv, 0, 64), v1 = __shfl(pv, 1, 64);
-      const float w0 = __shfl(pv, q, 64), w1 = __shfl(pv, q + 1, 64);
+      const float v0 = rdlane_f(pv, 0), v1 = rdlane_f(pv, 1);
+      const float w0 = rdlane_f(pv, (uint32_t)q), w1 = rdlane_f(pv, (uint32_t)q + 1);
       const uint32_t kb = (uint32_t)((int)sel3(bb, ks0, ks1, 1u) * sg);
       const uint64_t kw = make_skey(R.L, 1, im, ord_of(fmaxf(w0, w1)), kidx + 2 * kb);
       const uint64_t ka0 = make_skey(R.L, 1, im, ord_of(fmaxf(v0, w0)), kidx - kax + kb);
@@ -784,7 +811,7 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
       for (uint32_t i = lane; i < W.nf; i += 64) R.arena[off + 1 + i] = fbuf(S, W.cur)[i];
       len = W.nf;
     } else {
-      len = w_xor_glob(S, W.T, W.nt, false, fbuf(S, W.cur), W.nf, true, R.arena + off + 1, lane);
+      len = w_xor_glob(S.X, W.T, W.nt, false, fbuf(S, W.cur), W.nf, true, R.arena + off + 1, lane);
     }
     if (lane == 0) {
       R.arena[off] = len;
