@@ -43,6 +43,23 @@ def stencil_bytes(shape, survivors_total: int) -> int:
     return 4 * P + 8 * survivors_total + 4 * P + 4 * C
 
 
+def copy_ceiling(nbytes: int = 1 << 28, reps: int = 5) -> float:
+    """GB/s (read + write) of a device-to-device copy of nbytes: the practical
+    HBM ceiling the stencil is compared with."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    return 2 * nbytes * reps / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
+
+
 def cpu_baseline(vol):
     import numpy as np
     import oracle
@@ -62,6 +79,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only time a 256 MiB device copy (the reference kernel for profiler byte counts)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -70,6 +89,10 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_only:
+        print(json.dumps({"copy_GBs": copy_ceiling(), "bytes_per_copy": 2 * (1 << 28)}), flush=True)
+        return
 
     import paper_2005_12692_amd as cr
     import synth

@@ -168,6 +168,64 @@ cr_status cr_get_stats(cr_context* ctx, cr_stats* out);
  * *n_stages = 6. */
 cr_status cr_get_stage_times(cr_context* ctx, float* ms, int capacity, int* n_stages);
 
+/* ---- launch parameters, autotuning and graphs (batched form) ------------------ */
+
+/* Launch parameters of one ndim.  They change speed only: every setting gives
+ * the same diagrams. */
+typedef struct cr_tuning {
+  int32_t tile;         /* stencil tile shape, 0 .. cr_tile_variants(ndim)-1 (see cr_tile_shape) */
+  int32_t grid;         /* workgroups of the grid-stride kernels (union-find, output), 64 .. 65536 */
+  int32_t long_len;     /* degree-1 reduction of a volume: a stored column longer than this
+                           continues one per wavefront instead of one per thread */
+  int32_t yield_iters;  /* ... a column reduced one per thread moves to a wavefront after this
+                           many additions (>= 1) */
+  int32_t wave_short;   /* ... a list of at most this many short columns is run one per wavefront */
+  int32_t front_cap;    /* ... keys of a wavefront's LDS front list, 128 .. 4096 */
+} cr_tuning;
+
+/* The parameters the context uses for ndim (2 or 3), and a validated setter
+ * (INVALID_ARGUMENT for a value out of range). */
+cr_status cr_get_tuning(cr_context* ctx, int ndim, cr_tuning* out);
+cr_status cr_set_tuning(cr_context* ctx, int ndim, const cr_tuning* t);
+
+/* Number of stencil tile shapes for ndim (0 for another ndim), and the
+ * extents (z, y, x) of shape `variant`; a 2D tile has z extent 1. */
+int cr_tile_variants(int ndim);
+cr_status cr_tile_shape(int ndim, int variant, int32_t extents[3]);
+
+/* Autotuner: runs the batched call on the caller's batch (same arguments and
+ * output buffers as cr_persistence_batched) for candidate parameter sets --
+ * one parameter at a time: tile shape, grid, then for volumes with maxdim >= 1
+ * the reduction thresholds -- each as one warm-up call plus `repeats` calls
+ * timed with HIP events on `stream`, keeps the fastest, makes it the context's
+ * setting for ndim and copies it to *chosen (may be NULL).  Synchronises;
+ * returns the first error of a candidate run (the previous setting is then
+ * kept).  The outputs hold the diagrams of the last run. */
+cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed, const int64_t* pixel_offsets,
+                              const int64_t* shapes, int ndim, int maxdim, void* stream, int32_t* dim, float* birth,
+                              float* death, int64_t* birth_pixel, int64_t* death_pixel, int64_t capacity,
+                              int64_t* pair_offsets, int32_t* status, int repeats, cr_tuning* chosen);
+
+/* A batched call captured in a HIP graph: every kernel of cr_persistence_batched
+ * for these arguments (shapes, device buffers and the context's current
+ * tuning fixed at creation), on scratch memory the graph owns, so that a
+ * replay enqueues no host work and allocates nothing.  Creation uploads the
+ * image descriptors (synchronously) and captures on `stream`, which must not be
+ * the default stream.  cr_graph_launch replays it on any stream of the device;
+ * the input buffer is read at replay time, so new pixel values of the same
+ * shapes need no new graph.  cr_graph_sync_status synchronises `stream` and
+ * reports the device-side status of the last replay (as cr_sync_status).
+ * The context must outlive the graph; replays of one graph must not overlap. */
+typedef struct cr_graph cr_graph;
+cr_status cr_batched_graph_create(cr_context* ctx, int n_images, const float* packed, const int64_t* pixel_offsets,
+                                  const int64_t* shapes, int ndim, int maxdim, uint32_t flags, void* stream,
+                                  int32_t* dim, float* birth, float* death, int64_t* birth_pixel,
+                                  int64_t* death_pixel, int64_t capacity, int64_t* pair_offsets, int32_t* status,
+                                  cr_graph** out);
+cr_status cr_graph_launch(cr_graph* g, void* stream);
+cr_status cr_graph_sync_status(cr_graph* g, void* stream);
+void cr_graph_destroy(cr_graph* g);
+
 #ifdef __cplusplus
 }
 #endif

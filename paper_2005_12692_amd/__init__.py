@@ -48,6 +48,13 @@ class _Stats(ctypes.Structure):
                 ("red_rounds", ctypes.c_int64)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("grid", ctypes.c_int32), ("long_len", ctypes.c_int32),
+                ("yield_iters", ctypes.c_int32), ("wave_short", ctypes.c_int32), ("front_cap", ctypes.c_int32)]
+
+
+TUNING_FIELDS = tuple(f for f, _ in _Tuning._fields_)
+
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -97,8 +104,22 @@ def lib():
         L.cr_persistence_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, i64, vp]
         L.cr_get_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
         L.cr_get_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
+        batch = [vp, i32, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), i32, i32]
+        outs = [vp, vp, vp, vp, vp, i64, vp, vp]
+        L.cr_get_tuning.argtypes = [vp, i32, ctypes.POINTER(_Tuning)]
+        L.cr_set_tuning.argtypes = [vp, i32, ctypes.POINTER(_Tuning)]
+        L.cr_tile_variants.argtypes = [i32]
+        L.cr_tile_shape.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_int32)]
+        L.cr_autotune_batched.argtypes = batch + [vp] + outs + [i32, ctypes.POINTER(_Tuning)]
+        L.cr_batched_graph_create.argtypes = batch + [ctypes.c_uint32, vp] + outs + [ctypes.POINTER(vp)]
+        L.cr_graph_launch.argtypes = [vp, vp]
+        L.cr_graph_sync_status.argtypes = [vp, vp]
+        L.cr_graph_destroy.argtypes = [vp]
+        L.cr_graph_destroy.restype = None
         for f in ("cr_create", "cr_persistence", "cr_persistence_batched", "cr_sync_status",
-                  "cr_persistence_backward", "cr_get_stats", "cr_get_stage_times"):
+                  "cr_persistence_backward", "cr_get_stats", "cr_get_stage_times", "cr_get_tuning",
+                  "cr_set_tuning", "cr_tile_variants", "cr_tile_shape", "cr_autotune_batched",
+                  "cr_batched_graph_create", "cr_graph_launch", "cr_graph_sync_status"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -262,6 +283,141 @@ def persistence_batched(packed: torch.Tensor, shapes, pixel_offsets=None, maxdim
     _check(code)
     return BatchedDiagram(out.dim[:total], out.birth[:total], out.death[:total], out.birth_pixel[:total],
                           out.death_pixel[:total], out.pair_offsets, out.status)
+
+
+def _batch_prefix(packed, shapes, pixel_offsets, maxdim):
+    if packed.device.type != "cuda" or packed.dtype != torch.float32 or not packed.is_contiguous():
+        raise TypeError("packed must be a contiguous float32 CUDA tensor")
+    shapes = [tuple(int(e) for e in s) for s in shapes]
+    ndim = len(shapes[0])
+    if any(len(s) != ndim for s in shapes):
+        raise ValueError("all images must have the same ndim")
+    if pixel_offsets is None:
+        pixel_offsets = [0]
+        for s in shapes:
+            n = 1
+            for e in s:
+                n *= e
+            pixel_offsets.append(pixel_offsets[-1] + n)
+    if maxdim is None:
+        maxdim = ndim - 1
+    nimg = len(shapes)
+    h, _ = _context(packed.device)
+    flat = [e for s in shapes for e in s]
+    c_shapes = (ctypes.c_int64 * len(flat))(*flat)
+    c_offs = (ctypes.c_int64 * (nimg + 1))(*pixel_offsets)
+    args = [h, nimg, ctypes.c_void_p(packed.data_ptr()), c_offs, c_shapes, ndim, int(maxdim)]
+    return args, ndim, nimg, pixel_offsets, shapes, maxdim
+
+
+def _empty_out(n_rows: int, nimg: int, device) -> BatchedDiagram:
+    return BatchedDiagram(torch.empty(n_rows, dtype=torch.int32, device=device),
+                          torch.empty(n_rows, dtype=torch.float32, device=device),
+                          torch.empty(n_rows, dtype=torch.float32, device=device),
+                          torch.empty(n_rows, dtype=torch.int64, device=device),
+                          torch.empty(n_rows, dtype=torch.int64, device=device),
+                          torch.empty(nimg + 1, dtype=torch.int64, device=device),
+                          torch.empty(nimg, dtype=torch.int32, device=device))
+
+
+def _out_args(out: BatchedDiagram):
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    return [p(out.dim), p(out.birth), p(out.death), p(out.birth_pixel), p(out.death_pixel), out.dim.shape[0],
+            p(out.pair_offsets), p(out.status)]
+
+
+def get_tuning(ndim: int, device=None) -> dict:
+    """Launch parameters the context uses for ndim (see cr_tuning in cr.h)."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    h, _ = _context(dev)
+    t = _Tuning()
+    _check(lib().cr_get_tuning(h, ndim, ctypes.byref(t)))
+    return {f: int(getattr(t, f)) for f in TUNING_FIELDS}
+
+
+def set_tuning(ndim: int, device=None, **fields) -> dict:
+    """Sets some launch parameters for ndim; returns the full setting."""
+    cur = get_tuning(ndim, device)
+    unknown = set(fields) - set(TUNING_FIELDS)
+    if unknown:
+        raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+    cur.update({k: int(v) for k, v in fields.items()})
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    h, _ = _context(dev)
+    _check(lib().cr_set_tuning(h, ndim, ctypes.byref(_Tuning(**cur))))
+    return cur
+
+
+def tile_shapes(ndim: int) -> list:
+    """Extents (z, y, x) of the stencil tile variants for ndim."""
+    out = []
+    for v in range(lib().cr_tile_variants(ndim)):
+        e = (ctypes.c_int32 * 3)()
+        _check(lib().cr_tile_shape(ndim, v, e))
+        out.append(tuple(int(x) for x in e))
+    return out
+
+
+def autotune(packed: torch.Tensor, shapes, pixel_offsets=None, maxdim: int | None = None,
+             capacity: int | None = None, repeats: int = 2) -> dict:
+    """Runs the library's autotuner on this batch (see cr_autotune_batched) and
+    returns the chosen launch parameters, which the context keeps for this ndim."""
+    args, ndim, nimg, offs, shapes, maxdim = _batch_prefix(packed, shapes, pixel_offsets, maxdim)
+    cap = int(offs[-1]) if capacity is None else int(capacity)
+    out = _empty_out(cap, nimg, packed.device)
+    t = _Tuning()
+    _check(lib().cr_autotune_batched(*args, _stream(packed.device), *_out_args(out), int(repeats), ctypes.byref(t)))
+    return {f: int(getattr(t, f)) for f in TUNING_FIELDS}
+
+
+class BatchedGraph:
+    """A batched call captured once in a HIP graph (cr_batched_graph_create) and
+    replayed with launch().  The packed input tensor is read at each replay, so
+    refreshed pixel values of the same shapes need no new graph; the rows land in
+    the fixed buffers of ``out`` (call result() after a replay)."""
+
+    def __init__(self, packed: torch.Tensor, shapes, pixel_offsets=None, maxdim: int | None = None,
+                 capacity: int | None = None):
+        args, ndim, nimg, offs, shapes, maxdim = _batch_prefix(packed, shapes, pixel_offsets, maxdim)
+        self.packed = packed  # keeps the captured input buffer alive
+        cap = int(offs[-1]) if capacity is None else int(capacity)
+        self.out = _empty_out(cap, nimg, packed.device)
+        self.capture_stream = torch.cuda.Stream(packed.device)
+        self.capture_stream.wait_stream(torch.cuda.current_stream(packed.device))
+        g = ctypes.c_void_p()
+        torch.cuda.synchronize(packed.device)
+        _check(lib().cr_batched_graph_create(*args, 0, ctypes.c_void_p(self.capture_stream.cuda_stream),
+                                             *_out_args(self.out), ctypes.byref(g)))
+        self._g = g
+        self.device = packed.device
+
+    def launch(self, stream: torch.cuda.Stream | None = None):
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        _check(lib().cr_graph_launch(self._g, ctypes.c_void_p(s.cuda_stream)))
+
+    def result(self, check: bool = True) -> BatchedDiagram:
+        """Rows of the last replay (synchronises the current stream)."""
+        s = torch.cuda.current_stream(self.device)
+        code = lib().cr_graph_sync_status(self._g, ctypes.c_void_p(s.cuda_stream))
+        total = int(self.out.pair_offsets[-1])
+        if total > self.out.dim.shape[0]:
+            raise CRError(CR_ERR_CAPACITY, f"{total} rows do not fit the capacity {self.out.dim.shape[0]}")
+        if check:
+            _check(code)
+        o = self.out
+        return BatchedDiagram(o.dim[:total], o.birth[:total], o.death[:total], o.birth_pixel[:total],
+                              o.death_pixel[:total], o.pair_offsets, o.status)
+
+    def close(self):
+        if getattr(self, "_g", None) and self._g.value:
+            lib().cr_graph_destroy(self._g)
+            self._g = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def backward(birth_pixel: torch.Tensor, death_pixel: torch.Tensor, grad_birth: torch.Tensor | None,

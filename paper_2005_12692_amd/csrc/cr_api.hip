@@ -12,7 +12,7 @@
 
 namespace cr {
 // launchers defined in the kernel translation units
-void launch_apparent(int ndim, int ntiles, const float* img, const ImgDesc* imgs, const int4* tiles,
+void launch_apparent(int ndim, int variant, int ntiles, const float* img, const ImgDesc* imgs, const int4* tiles,
                      Layout L, uint64_t* surv, uint64_t surv_cap, unsigned long long* surv_count,
                      int32_t* vlink, int32_t* tlink, uint8_t* eapp, uint32_t* img_status, Status* st,
                      hipStream_t stream);
@@ -36,6 +36,7 @@ void launch_img_offsets(const uint32_t* cnt, const uint32_t* img_status, int nim
 void launch_backward(const int64_t* bpix, const int64_t* dpix, const float* gb, const float* gd, int64_t n,
                      float* grad, int64_t n_pixels, uint32_t* bad, hipStream_t s);
 void launch_check_empty(const unsigned long long* count, Status* st, hipStream_t s);
+bool stencil_tile(int ndim, int variant, int ext[3]);
 constexpr int SORT_HIST_WORDS = 256 * 1024;
 
 }  // namespace cr
@@ -64,10 +65,21 @@ int bits_for(uint64_t x) {  // smallest b with x < 2^b
   return b;
 }
 
-constexpr int TILE2[3] = {1, 8, 32};  // z y x extents of a 2D stencil tile
-constexpr int TILE3[3] = {4, 4, 16};  // of a 3D stencil tile
-constexpr int KGRID = 2048;           // workgroups of the grid-stride kernels
-constexpr int RGRID = 512;            // workgroups of the reduction (256 threads each)
+constexpr int RGRID = 512;            // workgroups of the thread-mode reduction (256 threads each)
+constexpr int N_TILE_VARIANTS = 3;    // stencil tile shapes (see stencil_tile)
+
+// Default launch parameters (cr_tuning) per ndim.
+cr_tuning default_tuning(int ndim) {
+  cr_tuning t;
+  t.tile = 0;
+  t.grid = 2048;
+  t.long_len = 128;
+  t.yield_iters = 32;
+  t.wave_short = 4096;
+  t.front_cap = 4096;
+  (void)ndim;
+  return t;
+}
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -111,6 +123,7 @@ struct cr_context {
   bool ev_ready = false;
   bool timing = false;
   float stage_ms[6] = {};
+  cr_tuning tune[4] = {};        // launch parameters per ndim (2, 3)
 };
 
 namespace {
@@ -119,7 +132,7 @@ namespace {
 enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* four words */, C_WORK = 11, C_WORDS = 12 };
 
 cr_status build_problem(Problem& pb, int nimg, const int64_t* pixel_offsets, const int64_t* shapes, int ndim,
-                        int maxdim) {
+                        int maxdim, int tile_variant) {
   if (nimg < 1) return fail(CR_ERR_INVALID_ARGUMENT, "n_images must be >= 1");
   if (ndim != 2 && ndim != 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
   if (maxdim < 0) return fail(CR_ERR_INVALID_ARGUMENT, "maxdim must be >= 0");
@@ -132,7 +145,8 @@ cr_status build_problem(Problem& pb, int nimg, const int64_t* pixel_offsets, con
   pb.P = 0;
   pb.N = 0;
   uint64_t maxN = 1, maxP = 1;
-  const int* tile = ndim == 2 ? TILE2 : TILE3;
+  int tile[3];
+  if (!stencil_tile(ndim, tile_variant, tile)) return fail(CR_ERR_INVALID_ARGUMENT, "bad stencil tile variant");
   for (int i = 0; i < nimg; ++i) {
     int64_t n[3] = {1, 1, 1};
     for (int a = 0; a < ndim; ++a) {
@@ -299,8 +313,33 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
   return CR_OK;
 }
 
-// Enqueues every stage up to sorted canonical keys.  Returns the buffer holding them.
-cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, uint64_t** cand_out) {
+// Copies the image descriptors and stencil tiles of ctx->prob into scratch.
+// Asynchronous through the pinned stage unless `sync` (then the copy is
+// complete on return, as graph capture needs).
+cr_status upload_descriptors(cr_context* ctx, hipStream_t s, bool sync) {
+  const Problem& pb = ctx->prob;
+  const Plan& p = ctx->plan;
+  const size_t bi = sizeof(ImgDesc) * pb.nimg, bt = sizeof(int4) * pb.tiles.size();
+  cr_status rc = ensure_stage(ctx, bi + bt);
+  if (rc != CR_OK) return rc;
+  std::memcpy(ctx->host_stage, pb.imgs.data(), bi);
+  std::memcpy(ctx->host_stage + bi, pb.tiles.data(), bt);
+  HIP_TRY(hipMemcpyAsync(at<ImgDesc>(ctx, p.imgs), ctx->host_stage, bi, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<int4>(ctx, p.tiles), ctx->host_stage + bi, bt, hipMemcpyHostToDevice, s));
+  if (sync) {
+    HIP_TRY(hipStreamSynchronize(s));
+  } else {
+    HIP_TRY(hipEventRecord(ctx->stage_done, s));
+    ctx->stage_pending = true;
+  }
+  return CR_OK;
+}
+
+// Enqueues every stage up to sorted canonical keys.  Returns the buffer holding
+// them.  With upload = false the descriptors are already in scratch and only
+// kernels are enqueued.
+cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, uint64_t** cand_out,
+                           bool upload = true) {
   const Problem& pb = ctx->prob;
   const Plan& p = ctx->plan;
   const Layout L = pb.L;
@@ -311,16 +350,10 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
   ImgDesc* d_imgs = at<ImgDesc>(ctx, p.imgs);
   int4* d_tiles = at<int4>(ctx, p.tiles);
 
-  // upload image descriptors and tiles
-  const size_t bi = sizeof(ImgDesc) * pb.nimg, bt = sizeof(int4) * pb.tiles.size();
-  cr_status rc = ensure_stage(ctx, bi + bt);
-  if (rc != CR_OK) return rc;
-  std::memcpy(ctx->host_stage, pb.imgs.data(), bi);
-  std::memcpy(ctx->host_stage + bi, pb.tiles.data(), bt);
-  HIP_TRY(hipMemcpyAsync(d_imgs, ctx->host_stage, bi, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(d_tiles, ctx->host_stage + bi, bt, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipEventRecord(ctx->stage_done, s));
-  ctx->stage_pending = true;
+  if (upload) {
+    cr_status rc = upload_descriptors(ctx, s, false);
+    if (rc != CR_OK) return rc;
+  }
 
   // zero the status words, counters and per-image counts (one contiguous range)
   launch_fill_u32(reinterpret_cast<uint32_t*>(st), 0, (p.img_pairs + 4 * (pb.nimg + 1) - p.status) / 4, s);
@@ -331,7 +364,8 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
   int32_t* tlink = at<int32_t>(ctx, p.tlink);
   mark(ctx, EV_START, s);
   uint8_t* eapp = (pb.ndim == 3 && pb.maxdim >= 1) ? at<uint8_t>(ctx, p.eapp) : nullptr;
-  launch_apparent(pb.ndim, (int)pb.tiles.size(), image, d_imgs, d_tiles, L, surv, p.surv_cap, &cnt[C_SURV],
+  const cr_tuning& tu = ctx->tune[pb.ndim];
+  launch_apparent(pb.ndim, tu.tile, (int)pb.tiles.size(), image, d_imgs, d_tiles, L, surv, p.surv_cap, &cnt[C_SURV],
                   vlink, tlink, eapp, img_status, st, s);
   mark(ctx, EV_STENCIL, s);
   uint32_t* hist = at<uint32_t>(ctx, p.hist);
@@ -353,12 +387,12 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
   uint8_t* neg = at<uint8_t>(ctx, p.neg);
   launch_fill_u32(reinterpret_cast<uint32_t*>(neg), 0, p.e_cap / 4, s);
   uint64_t* T = at<uint64_t>(ctx, p.T);
-  launch_h0(KGRID, skeys, &cnt[C_DIM], d_imgs, L, vlink, T, neg, E, st, s);
+  launch_h0(tu.grid, skeys, &cnt[C_DIM], d_imgs, L, vlink, T, neg, E, st, s);
   mark(ctx, EV_H0, s);
 
   uint64_t* owner = at<uint64_t>(ctx, p.owner);
   if (pb.ndim == 2) {
-    if (pb.maxdim >= 1) launch_dual(KGRID, 2, skeys, &cnt[C_DIM], d_imgs, L, tlink, neg, nullptr, 1, T, E, st, s);
+    if (pb.maxdim >= 1) launch_dual(tu.grid, 2, skeys, &cnt[C_DIM], d_imgs, L, tlink, neg, nullptr, 1, T, E, st, s);
     mark(ctx, EV_A, s);
     mark(ctx, EV_B, s);
   } else if (pb.maxdim >= 1) {
@@ -366,13 +400,17 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     // squares that give birth to a void, whose degree-1 columns are zero
     uint8_t* cleared = at<uint8_t>(ctx, p.cleared);
     launch_fill_u32(reinterpret_cast<uint32_t*>(cleared), 0, p.e_cap / 4, s);
-    launch_dual(KGRID, 3, skeys, &cnt[C_DIM], d_imgs, L, tlink, nullptr, cleared, pb.maxdim >= 2, T, E, st, s);
+    launch_dual(tu.grid, 3, skeys, &cnt[C_DIM], d_imgs, L, tlink, nullptr, cleared, pb.maxdim >= 2, T, E, st, s);
     mark(ctx, EV_A, s);
     launch_fill_u32(reinterpret_cast<uint32_t*>(owner), 0xFFFFFFFFu, 2 * 3 * pb.P, s);
     launch_fill_u32(at<uint32_t>(ctx, p.claim), 0x7FFFFFFFu, 3 * pb.P, s);
     RedCtx R = make_redctx(image, d_imgs, L, skeys, &cnt[C_DIM], cleared, eapp, owner, at<int32_t>(ctx, p.claim),
                            at<uint64_t>(ctx, p.piv), at<uint64_t>(ctx, p.colptr), at<uint64_t>(ctx, p.arena),
                            p.arena_cap, &cnt[C_ARENA], &cnt[C_WORK], at<uint64_t>(ctx, p.pbuf), st);
+    R.long_len = (uint32_t)tu.long_len;
+    R.yield_iters = (uint32_t)tu.yield_iters;
+    R.wave_short = (uint32_t)tu.wave_short;
+    R.front_cap = (uint32_t)tu.front_cap;
     // thresholds between thread and wave mode and the wave-mode front capacity
     // (CR_LONG_LEN / CR_YIELD_ITERS / CR_WAVE_SHORT / CR_FRONT_CAP override them,
     // e.g. to exercise wave mode and its tail merges on small inputs)
@@ -387,7 +425,7 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
                           at<uint32_t>(ctx, p.list[3])};
     cr_status rrc = run_rounds(ctx, R, lists, &cnt[C_LIST], s);
     if (rrc != CR_OK) return rrc;
-    launch_h1_emit(KGRID, R, E, s);
+    launch_h1_emit(tu.grid, R, E, s);
     mark(ctx, EV_B, s);
   } else {
     mark(ctx, EV_A, s);
@@ -456,7 +494,89 @@ cr_status status_error(const Status& st, bool* arena_overflow) {
   return CR_OK;
 }
 
+struct BatchArgs {
+  int n_images;
+  const float* packed;
+  const int64_t* pixel_offsets;
+  const int64_t* shapes;
+  int ndim, maxdim;
+  uint32_t flags;
+  int32_t* dim;
+  float* birth;
+  float* death;
+  int64_t* birth_pixel;
+  int64_t* death_pixel;
+  int64_t capacity;
+  int64_t* pair_offsets;
+  int32_t* status;
+};
+
+cr_status check_batch_args(cr_context* ctx, const BatchArgs& a) {
+  if (!ctx) return fail(CR_ERR_INVALID_ARGUMENT, "ctx is NULL");
+  if (!a.packed || !a.pixel_offsets || !a.pair_offsets || !a.status)
+    return fail(CR_ERR_INVALID_ARGUMENT, "a required pointer is NULL");
+  if (a.capacity < 0 || (a.capacity > 0 && (!a.dim || !a.birth || !a.death || !a.birth_pixel || !a.death_pixel)))
+    return fail(CR_ERR_INVALID_ARGUMENT, "bad output buffers");
+  if (a.flags != 0) return fail(CR_ERR_INVALID_ARGUMENT, "flags must be 0");
+  if (a.ndim != 2 && a.ndim != 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
+  if (a.n_images < 1) return fail(CR_ERR_INVALID_ARGUMENT, "n_images must be >= 1");
+  if (a.pixel_offsets[0] != 0) return fail(CR_ERR_INVALID_ARGUMENT, "pixel_offsets[0] must be 0");
+  return CR_OK;
+}
+
+// Enqueues the batched pipeline for ctx->prob / ctx->plan / ctx->scratch:
+// every stage, the row gather and the per-image offsets.  No synchronisation.
+cr_status enqueue_batch(cr_context* ctx, const BatchArgs& a, hipStream_t s, bool upload) {
+  ctx->timing = false;
+  ctx->sync_allowed = false;
+  uint64_t* cand = nullptr;
+  cr_status rc = enqueue_pipeline(ctx, a.packed, s, &cand, upload);
+  if (rc != CR_OK) return rc;
+  const Plan& p = ctx->plan;
+  launch_gather(ctx->tune[a.ndim].grid, cand, at<unsigned long long>(ctx, p.counters) + C_CAND,
+                (uint64_t)a.capacity, a.packed, at<ImgDesc>(ctx, p.imgs), ctx->prob.L, a.dim, a.birth, a.death,
+                a.birth_pixel, a.death_pixel, s);
+  launch_img_offsets(at<uint32_t>(ctx, p.img_pairs), at<uint32_t>(ctx, p.img_status), a.n_images,
+                     a.pair_offsets, a.status, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(CR_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return CR_OK;
+}
+
+cr_status check_tuning(int ndim, const cr_tuning& t) {
+  int ext[3];
+  if (!stencil_tile(ndim, t.tile, ext)) return fail(CR_ERR_INVALID_ARGUMENT, "tile variant out of range");
+  if (t.grid < 64 || t.grid > 65536) return fail(CR_ERR_INVALID_ARGUMENT, "grid must be in [64, 65536]");
+  if (t.long_len < 0 || t.yield_iters < 1 || t.wave_short < 0)
+    return fail(CR_ERR_INVALID_ARGUMENT, "reduction thresholds out of range");
+  if (t.front_cap < (int)FRONT_CAP_MIN || t.front_cap > (int)FRONT_CAP_MAX)
+    return fail(CR_ERR_INVALID_ARGUMENT, "front_cap out of range");
+  return CR_OK;
+}
+
+// Scratch, problem and plan of a context, swapped in and out around work on a
+// graph's own scratch.
+struct ScratchState {
+  char* scratch;
+  size_t bytes;
+  Problem prob;
+  Plan plan;
+};
+void swap_state(cr_context* ctx, ScratchState& st) {
+  std::swap(ctx->scratch, st.scratch);
+  std::swap(ctx->scratch_bytes, st.bytes);
+  std::swap(ctx->prob, st.prob);
+  std::swap(ctx->plan, st.plan);
+}
+
 }  // namespace
+
+struct cr_graph {
+  cr_context* ctx = nullptr;
+  ScratchState own{};  // the graph's scratch, problem and plan
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -474,6 +594,7 @@ cr_status cr_create(cr_context** out, int device, cr_alloc_fn alloc, cr_free_fn 
   cr_context* c = new (std::nothrow) cr_context();
   if (!c) return fail(CR_ERR_OUT_OF_MEMORY, "context allocation failed");
   c->device = device;
+  for (int d = 0; d < 4; ++d) c->tune[d] = default_tuning(d);
   c->alloc = alloc;
   c->free_fn = free_fn;
   c->user = user;
@@ -514,7 +635,8 @@ cr_status cr_persistence(cr_context* ctx, const float* image, int ndim, const in
   ctx->timing = (flags & CR_FLAG_STAGE_TIMES) != 0;
   ctx->sync_allowed = true;
   hipStream_t s = (hipStream_t)stream;
-  cr_status rc = build_problem(ctx->prob, 1, nullptr, shape, ndim, maxdim);
+  if (ndim != 2 && ndim != 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
+  cr_status rc = build_problem(ctx->prob, 1, nullptr, shape, ndim, maxdim, ctx->tune[ndim].tile);
   if (rc != CR_OK) return rc;
   for (int attempt = 0; attempt < 4; ++attempt) {
     ctx->plan = make_plan(ctx->prob, ctx->arena_entries);
@@ -561,7 +683,8 @@ cr_status cr_persistence(cr_context* ctx, const float* image, int ndim, const in
     out->birth_pixel = (int64_t*)b;
     b += align_up(8 * n, 256);
     out->death_pixel = (int64_t*)b;
-    launch_gather(KGRID, cand, at<unsigned long long>(ctx, ctx->plan.counters) + C_CAND, (uint64_t)n, image,
+    launch_gather(ctx->tune[ndim].grid, cand, at<unsigned long long>(ctx, ctx->plan.counters) + C_CAND, (uint64_t)n,
+                  image,
                   at<ImgDesc>(ctx, ctx->plan.imgs), ctx->prob.L, out->dim, out->birth, out->death,
                   out->birth_pixel, out->death_pixel, s);
     hipError_t e = hipGetLastError();
@@ -587,33 +710,20 @@ cr_status cr_persistence_batched(cr_context* ctx, int n_images, const float* pac
                                  const int64_t* shapes, int ndim, int maxdim, uint32_t flags, void* stream,
                                  int32_t* dim, float* birth, float* death, int64_t* birth_pixel,
                                  int64_t* death_pixel, int64_t capacity, int64_t* pair_offsets, int32_t* status) {
-  if (!ctx) return fail(CR_ERR_INVALID_ARGUMENT, "ctx is NULL");
-  if (!packed || !pixel_offsets || !pair_offsets || !status)
-    return fail(CR_ERR_INVALID_ARGUMENT, "a required pointer is NULL");
-  if (capacity < 0 || (capacity > 0 && (!dim || !birth || !death || !birth_pixel || !death_pixel)))
-    return fail(CR_ERR_INVALID_ARGUMENT, "bad output buffers");
-  if (flags != 0) return fail(CR_ERR_INVALID_ARGUMENT, "flags must be 0");
-  if (pixel_offsets[0] != 0) return fail(CR_ERR_INVALID_ARGUMENT, "pixel_offsets[0] must be 0");
+  const BatchArgs a{n_images, packed, pixel_offsets, shapes, ndim, maxdim, flags, dim, birth, death,
+                    birth_pixel, death_pixel, capacity, pair_offsets, status};
+  cr_status rc = check_batch_args(ctx, a);
+  if (rc != CR_OK) return rc;
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  ctx->timing = false;
-  ctx->sync_allowed = false;
   ctx->last_batched_valid = false;
-  cr_status rc = build_problem(ctx->prob, n_images, pixel_offsets, shapes, ndim, maxdim);
+  rc = build_problem(ctx->prob, n_images, pixel_offsets, shapes, ndim, maxdim, ctx->tune[ndim].tile);
   if (rc != CR_OK) return rc;
   ctx->plan = make_plan(ctx->prob, ctx->arena_entries);
   rc = ensure_scratch(ctx, ctx->plan.total);
   if (rc != CR_OK) return rc;
-  uint64_t* cand = nullptr;
-  rc = enqueue_pipeline(ctx, packed, s, &cand);
+  rc = enqueue_batch(ctx, a, s, true);
   if (rc != CR_OK) return rc;
-  const Plan& p = ctx->plan;
-  launch_gather(KGRID, cand, at<unsigned long long>(ctx, p.counters) + C_CAND, (uint64_t)capacity, packed,
-                at<ImgDesc>(ctx, p.imgs), ctx->prob.L, dim, birth, death, birth_pixel, death_pixel, s);
-  launch_img_offsets(at<uint32_t>(ctx, p.img_pairs), at<uint32_t>(ctx, p.img_status), n_images, pair_offsets,
-                     status, s);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(CR_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   ctx->last_batched_valid = true;
   return CR_OK;
 }
@@ -669,6 +779,190 @@ cr_status cr_get_stats(cr_context* ctx, cr_stats* out) {
   if (!ctx || !out) return fail(CR_ERR_INVALID_ARGUMENT, "NULL argument");
   *out = ctx->stats;
   return CR_OK;
+}
+
+
+cr_status cr_get_tuning(cr_context* ctx, int ndim, cr_tuning* out) {
+  if (!ctx || !out) return fail(CR_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (ndim != 2 && ndim != 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
+  *out = ctx->tune[ndim];
+  return CR_OK;
+}
+
+cr_status cr_set_tuning(cr_context* ctx, int ndim, const cr_tuning* t) {
+  if (!ctx || !t) return fail(CR_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (ndim != 2 && ndim != 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
+  cr_status rc = check_tuning(ndim, *t);
+  if (rc != CR_OK) return rc;
+  ctx->tune[ndim] = *t;
+  return CR_OK;
+}
+
+int cr_tile_variants(int ndim) { return (ndim == 2 || ndim == 3) ? N_TILE_VARIANTS : 0; }
+
+cr_status cr_tile_shape(int ndim, int variant, int32_t extents[3]) {
+  if (!extents) return fail(CR_ERR_INVALID_ARGUMENT, "extents is NULL");
+  int e[3];
+  if (!stencil_tile(ndim, variant, e)) return fail(CR_ERR_INVALID_ARGUMENT, "no such tile variant");
+  for (int i = 0; i < 3; ++i) extents[i] = e[i];
+  return CR_OK;
+}
+
+cr_status cr_batched_graph_create(cr_context* ctx, int n_images, const float* packed, const int64_t* pixel_offsets,
+                                  const int64_t* shapes, int ndim, int maxdim, uint32_t flags, void* stream,
+                                  int32_t* dim, float* birth, float* death, int64_t* birth_pixel,
+                                  int64_t* death_pixel, int64_t capacity, int64_t* pair_offsets, int32_t* status,
+                                  cr_graph** out) {
+  if (!out) return fail(CR_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  const BatchArgs a{n_images, packed, pixel_offsets, shapes, ndim, maxdim, flags, dim, birth, death,
+                    birth_pixel, death_pixel, capacity, pair_offsets, status};
+  cr_status rc = check_batch_args(ctx, a);
+  if (rc != CR_OK) return rc;
+  if (!stream) return fail(CR_ERR_INVALID_ARGUMENT, "graph capture needs a non-default stream");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  cr_graph* g = new (std::nothrow) cr_graph();
+  if (!g) return fail(CR_ERR_OUT_OF_MEMORY, "graph allocation failed");
+  g->ctx = ctx;
+  rc = build_problem(g->own.prob, n_images, pixel_offsets, shapes, ndim, maxdim, ctx->tune[ndim].tile);
+  if (rc != CR_OK) {
+    delete g;
+    return rc;
+  }
+  g->own.plan = make_plan(g->own.prob, ctx->arena_entries);
+  g->own.bytes = align_up(g->own.plan.total, 1 << 21);
+  if (hipMalloc(&g->own.scratch, g->own.bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete g;
+    return fail(CR_ERR_OUT_OF_MEMORY, "graph scratch allocation failed");
+  }
+  // work on the graph's scratch: upload the descriptors once, then capture kernels only
+  swap_state(ctx, g->own);
+  rc = upload_descriptors(ctx, s, true);
+  if (rc == CR_OK) {
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+      rc = fail(CR_ERR_HIP, std::string("hipStreamBeginCapture failed: ") + hipGetErrorString(e));
+    } else {
+      rc = enqueue_batch(ctx, a, s, false);
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(s, &graph);
+      if (rc == CR_OK && e != hipSuccess)
+        rc = fail(CR_ERR_HIP, std::string("hipStreamEndCapture failed: ") + hipGetErrorString(e));
+      g->graph = graph;
+      if (rc == CR_OK) {
+        e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = fail(CR_ERR_HIP, std::string("hipGraphInstantiate failed: ") + hipGetErrorString(e));
+      }
+    }
+  }
+  swap_state(ctx, g->own);
+  if (rc != CR_OK) {
+    cr_graph_destroy(g);
+    return rc;
+  }
+  *out = g;
+  return CR_OK;
+}
+
+cr_status cr_graph_launch(cr_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(CR_ERR_INVALID_ARGUMENT, "graph is NULL");
+  HIP_TRY(hipSetDevice(g->ctx->device));
+  HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return CR_OK;
+}
+
+cr_status cr_graph_sync_status(cr_graph* g, void* stream) {
+  if (!g) return fail(CR_ERR_INVALID_ARGUMENT, "graph is NULL");
+  cr_context* ctx = g->ctx;
+  HIP_TRY(hipSetDevice(ctx->device));
+  swap_state(ctx, g->own);
+  HostCounters h;
+  cr_status rc = read_counters(ctx, (hipStream_t)stream, &h);
+  swap_state(ctx, g->own);
+  if (rc != CR_OK) return rc;
+  bool arena_over = false;
+  return status_error(h.st, &arena_over);
+}
+
+void cr_graph_destroy(cr_graph* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->ctx->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->own.scratch) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g->own.scratch);
+  }
+  delete g;
+}
+
+cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed, const int64_t* pixel_offsets,
+                              const int64_t* shapes, int ndim, int maxdim, void* stream, int32_t* dim, float* birth,
+                              float* death, int64_t* birth_pixel, int64_t* death_pixel, int64_t capacity,
+                              int64_t* pair_offsets, int32_t* status, int repeats, cr_tuning* chosen) {
+  const BatchArgs a{n_images, packed, pixel_offsets, shapes, ndim, maxdim, 0u, dim, birth, death,
+                    birth_pixel, death_pixel, capacity, pair_offsets, status};
+  cr_status rc = check_batch_args(ctx, a);
+  if (rc != CR_OK) return rc;
+  if (repeats < 1) return fail(CR_ERR_INVALID_ARGUMENT, "repeats must be >= 1");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const cr_tuning start = ctx->tune[ndim];
+  // time one candidate: a warm-up call, then `repeats` timed calls
+  auto time_it = [&](const cr_tuning& t, float* ms) -> cr_status {
+    ctx->tune[ndim] = t;
+    for (int r = 0; r <= repeats; ++r) {
+      if (r == 1) HIP_TRY(hipEventRecord(e0, s));
+      cr_status c = cr_persistence_batched(ctx, n_images, packed, pixel_offsets, shapes, ndim, maxdim, 0, stream,
+                                           dim, birth, death, birth_pixel, death_pixel, capacity, pair_offsets,
+                                           status);
+      if (c != CR_OK) return c;
+    }
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    cr_status c = cr_sync_status(ctx, stream);
+    if (c != CR_OK) return c;
+    HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+    *ms /= (float)repeats;
+    return CR_OK;
+  };
+  cr_tuning best = start;
+  float best_ms = 0.0f;
+  rc = time_it(best, &best_ms);
+  // coordinate descent: one parameter at a time, in the order they matter
+  const bool red = ndim == 3 && maxdim >= 1;
+  for (int coord = 0; rc == CR_OK && coord < (red ? 5 : 2); ++coord) {
+    std::vector<int> vals;
+    if (coord == 0) for (int v = 0; v < N_TILE_VARIANTS; ++v) vals.push_back(v);
+    if (coord == 1) vals = {512, 1024, 2048, 4096, 8192};
+    if (coord == 2) vals = {32, 64, 128, 256, 512};
+    if (coord == 3) vals = {8, 16, 32, 64};
+    if (coord == 4) vals = {1024, 2048, 4096};
+    for (int v : vals) {
+      cr_tuning t = best;
+      int* field = coord == 0 ? &t.tile : coord == 1 ? &t.grid : coord == 2 ? &t.long_len
+                 : coord == 3 ? &t.yield_iters : &t.front_cap;
+      if (*field == v) continue;
+      *field = v;
+      float ms = 0.0f;
+      rc = time_it(t, &ms);
+      if (rc != CR_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->tune[ndim] = rc == CR_OK ? best : start;
+  if (rc == CR_OK && chosen) *chosen = best;
+  return rc;
 }
 
 }  // extern "C"

@@ -283,18 +283,37 @@ __global__ void k_dim_bounds(const uint64_t* __restrict__ keys, const unsigned l
 }
 
 // ---- host launcher ----------------------------------------------------------
-void launch_apparent(int ndim, int ntiles, const float* img, const ImgDesc* imgs, const int4* tiles,
+void launch_apparent(int ndim, int variant, int ntiles, const float* img, const ImgDesc* imgs, const int4* tiles,
                      Layout L, uint64_t* surv, uint64_t surv_cap, unsigned long long* surv_count,
                      int32_t* vlink, int32_t* tlink, uint8_t* eapp, uint32_t* img_status, Status* st,
                      hipStream_t stream) {
   if (ntiles <= 0) return;
+#define CR_APPARENT(N, X, Y, Z)                                                                     \
+  k_apparent<N, X, Y, Z><<<ntiles, X * Y * Z, 0, stream>>>(img, imgs, tiles, L, surv, surv_cap, surv_count, \
+                                                         vlink, tlink, eapp, img_status, st)
+  // tile shapes (x, y, z extents) indexed by variant; they must match stencil_tile()
   if (ndim == 2) {
-    k_apparent<2, 32, 8, 1><<<ntiles, 256, 0, stream>>>(img, imgs, tiles, L, surv, surv_cap, surv_count,
-                                                        vlink, tlink, eapp, img_status, st);
+    if (variant == 1) CR_APPARENT(2, 64, 4, 1);
+    else if (variant == 2) CR_APPARENT(2, 16, 16, 1);
+    else CR_APPARENT(2, 32, 8, 1);
   } else {
-    k_apparent<3, 16, 4, 4><<<ntiles, 256, 0, stream>>>(img, imgs, tiles, L, surv, surv_cap, surv_count,
-                                                        vlink, tlink, eapp, img_status, st);
+    if (variant == 1) CR_APPARENT(3, 32, 4, 2);
+    else if (variant == 2) CR_APPARENT(3, 8, 8, 4);
+    else CR_APPARENT(3, 16, 4, 4);
   }
+#undef CR_APPARENT
+}
+
+// Extents (z, y, x) of stencil tile `variant` for ndim; returns false if there is no such variant.
+bool stencil_tile(int ndim, int variant, int ext[3]) {
+  static const int t2[3][3] = {{1, 8, 32}, {1, 4, 64}, {1, 16, 16}};
+  static const int t3[3][3] = {{4, 4, 16}, {2, 4, 32}, {4, 8, 8}};
+  if (variant < 0 || variant >= 3 || (ndim != 2 && ndim != 3)) return false;
+  const int* t = ndim == 2 ? t2[variant] : t3[variant];
+  ext[0] = t[0];
+  ext[1] = t[1];
+  ext[2] = t[2];
+  return true;
 }
 
 void launch_dim_bounds(const uint64_t* keys, const unsigned long long* n_ptr, uint64_t cap, Layout L,

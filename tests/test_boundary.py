@@ -83,3 +83,25 @@ def test_no_gpu_means_an_error_not_a_fallback():
     import paper_2005_12692_amd as cr
     with pytest.raises(Exception):
         cr.persistence(torch.rand(8, 8))  # CPU tensor: refused
+
+
+def test_tile_shapes_and_null_handles(libcr):
+    """Host-only entry points: tile shapes, and NULL handles rejected."""
+    libcr.cr_tile_variants.restype = ctypes.c_int
+    libcr.cr_tile_shape.restype = ctypes.c_int
+    for ndim in (2, 3):
+        n = libcr.cr_tile_variants(ndim)
+        assert n >= 1
+        for v in range(n):
+            e = (ctypes.c_int32 * 3)()
+            assert libcr.cr_tile_shape(ndim, v, e) == 0
+            assert e[0] * e[1] * e[2] == 256 and (ndim == 3 or e[0] == 1)
+        e = (ctypes.c_int32 * 3)()
+        assert libcr.cr_tile_shape(ndim, n, e) == 1
+    assert libcr.cr_tile_variants(4) == 0
+    for f in ("cr_graph_launch", "cr_graph_sync_status"):
+        getattr(libcr, f).restype = ctypes.c_int
+        assert getattr(libcr, f)(None, None) == 1
+    libcr.cr_get_tuning.restype = ctypes.c_int
+    assert libcr.cr_get_tuning(None, 3, None) == 1
+    libcr.cr_graph_destroy(None)  # a no-op
