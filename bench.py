@@ -13,9 +13,16 @@ Also reported (one JSON line):
                   its duration is the mean of HIP events recorded around it on the
                   call's stream during the timed steps;
   cpu_baseline -- the CPU oracle timed on a bounded sample of the workload;
-  stages       -- mean per-stage times over the timed steps.
+  stages       -- mean per-stage times over the timed steps;
+  batched      -- 512 2D images of sides 28..512 (half uniform noise, half
+                  sigma-2 fields): images/s of one batched call replayed from a
+                  HIP graph (after the autotuner picked its launch parameters),
+                  of the eager batched call, and of 512 plain calls;
+  fwd_bwd      -- 32 volumes of 128^3 (sigma-3 fields), loss = sum over finite
+                  degree-1/2 bars with lifetime > 0.1 of lifetime^2: one batched
+                  forward + backward against 32 per-volume forward + backward.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-forms]
 """
 from __future__ import annotations
 
@@ -73,12 +80,110 @@ def cpu_baseline(vol):
                       f"{cells} cells, {len(d)} bars, {dt:.2f} s on one host core"}
 
 
+def bench_batched(reps: int = 3) -> dict:
+    """512 images: HIP-graph replay, eager batched call and 512 plain calls."""
+    import torch
+    import paper_2005_12692_amd as cr
+    import synth
+    imgs = synth.config("C4")
+    ts = [torch.from_numpy(i).cuda() for i in imgs]
+    packed, shapes, offs = cr.pack(ts)
+    n = len(imgs)
+    d = cr.persistence_batched(packed, shapes, offs)            # sizes the capacity and warms up
+    cap = int(d.pair_offsets[-1].item())
+    t = time.perf_counter()
+    tuned = cr.autotune(packed, shapes, offs, capacity=cap, repeats=1)
+    tune_s = time.perf_counter() - t
+    print(f"batched: autotuned in {tune_s:.1f} s: {tuned}", file=sys.stderr, flush=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    prealloc = cr._empty_out(cap, n, packed.device)
+    eager_s = timed(lambda: cr.persistence_batched(packed, shapes, offs, out=prealloc, check=False))
+    g = cr.BatchedGraph(packed, shapes, offs, capacity=cap)
+    graph_s = timed(g.launch)
+    rows = int(g.result().dim.shape[0])
+    g.close()
+    print(f"batched: graph {graph_s * 1e3:.1f} ms, eager {eager_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    plain_s = timed(lambda: [cr.persistence(x) for x in ts])
+    print(f"batched: plain loop {plain_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return {"workload": "512 2D float32 images, sides uniform in 28..512, half U[0,1) noise, half sigma-2 "
+                        "Gaussian fields (seed 3); H0+H1",
+            "images": n, "pixels": int(offs[-1]), "rows": rows,
+            "graph_img_per_s": n / graph_s, "eager_batched_img_per_s": n / eager_s,
+            "plain_img_per_s": n / plain_s, "graph_vs_plain": plain_s / graph_s,
+            "graph_ms": graph_s * 1e3, "eager_batched_ms": eager_s * 1e3, "plain_loop_ms": plain_s * 1e3,
+            "tuning": tuned, "autotune_s": tune_s}
+
+
+def bench_fwd_bwd(reps: int = 2) -> dict:
+    """32 volumes: batched forward + backward against a per-volume loop."""
+    import torch
+    import paper_2005_12692_amd as cr
+    import synth
+    vols = synth.config("C5")
+    ts = [torch.from_numpy(v).cuda() for v in vols]
+    packed, shapes, offs = cr.pack(ts)
+
+    def loss_of(birth, death, dim):
+        life = death - birth
+        act = (dim >= 1) & torch.isfinite(death) & (life > 0.1)
+        return (life[act] ** 2).sum(), int(act.sum())
+
+    def batched():
+        x = packed.detach().requires_grad_(True)
+        dim, birth, death, bp, dp, po = cr.PersistenceBatchedFn.apply(x, shapes)
+        loss, nact = loss_of(birth, death, dim)
+        loss.backward()
+        return x.grad, nact
+
+    def per_volume():
+        grads, nact = [], 0
+        for v in ts:
+            x = v.detach().requires_grad_(True)
+            dim, birth, death, bp, dp = cr.PersistenceFn.apply(x)
+            loss, k = loss_of(birth, death, dim)
+            loss.backward()
+            grads.append(x.grad.reshape(-1))
+            nact += k
+        return torch.cat(grads), nact
+
+    gb, nact = batched()
+    gp, nact_p = per_volume()
+    same = bool(torch.equal(gb, gp)) or bool(torch.allclose(gb, gp, rtol=1e-6, atol=1e-6))
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    b_s = timed(batched)
+    print(f"fwd_bwd: batched {b_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    p_s = timed(per_volume)
+    print(f"fwd_bwd: per-volume loop {p_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return {"workload": "32 x 128^3 float32 sigma-3 Gaussian fields (seed 4); loss = sum over finite H1/H2 "
+                        "bars with lifetime > 0.1 of lifetime^2; forward + backward",
+            "volumes": len(vols), "active_bars": nact, "batched_ms": b_s * 1e3, "per_volume_loop_ms": p_s * 1e3,
+            "batched_vs_loop": p_s / b_s, "gradients_agree": same and nact == nact_p}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and fwd+bwd measurements")
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a 256 MiB device copy (the reference kernel for profiler byte counts)")
     args = ap.parse_args()
@@ -150,6 +255,10 @@ def main():
                       "entries_merged": st["red_merged"], "max_column": st["red_max_col"],
                       "rounds": st["red_rounds"]},
     }
+    line["copy_ceiling_GBs"] = copy_ceiling()
+    if not args.no_forms:
+        line["batched"] = bench_batched()
+        line["fwd_bwd"] = bench_fwd_bwd()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(vol)
     print(json.dumps(line), flush=True)
