@@ -1,17 +1,25 @@
 // Fused stencil pass: filtration values, apparent pairs, survivor compaction.
 //
-// One workgroup owns a tile of pixels and every cell anchored at them (cell k
-// is anchored at pixel floor(k/2)).  It stages the pixel tile plus a halo in
-// LDS (reads are coalesced along x), derives the value of every cell within
-// Khalimsky distance 2 of the tile -- the maximum over the cell's vertices,
-// the V-construction of Sec. 2 -- and then decides for each owned cell whether
-// it belongs to an apparent pair:
-//   (s, t) is apparent iff t is the earliest cofacet of s and s is the latest
-//   facet of t, in the total order (value, dim, kidx).
-// An apparent pair is a persistence pair of length zero (value(t) is the
-// maximum over its facets, attained by its latest facet s), so it emits nothing
-// and both cells leave the problem.  The remaining cells ("survivors") are
-// compacted with wave64 ballots into one key array, dimension-major.
+// Every cell of the V-construction complex (Sec. 2) is anchored at the pixel
+// of its smallest coordinates and takes the maximum of its vertices.  A cell
+// pair (s, t) is apparent iff t is the earliest cofacet of s and s is the
+// latest facet of t in the total order (value, dim, kidx).  Such a pair has
+// length zero (value(t) is the maximum over its facets, attained by s), so it
+// emits nothing and both cells leave the problem; the remaining cells
+// ("survivors") are compacted into one key array.
+//
+// Layout: a workgroup is RW wavefronts; wavefront w owns image row y0-1+w and
+// lane l owns column x0-1+l, so the rows and lanes at the edge of the
+// workgroup are a one-pixel halo and the interior is (RW-2) x 62 pixels.  In
+// 3D the workgroup marches along z over ZC planes.  Per pixel and plane a
+// thread keeps the record of the 8 cells anchored there (their values as
+// order-preserving 32-bit keys; a cell that leaves the image has none), and
+// computes for each cell the direction of its earliest cofacet and of its
+// latest facet (3-bit codes: 0 -z, 1 -y, 2 -x, 3 +x, 4 +y, 5 +z, i.e. ascending
+// kidx of the neighbour; 7 none).  Neighbouring records and codes come from the
+// lane next door (DPP), the wavefront above or below (LDS) and the previous or
+// next plane (registers).  A cell is paired iff the code of its partner points
+// back at it.
 //
 // Two forests are written alongside:
 //  * vlink[pixel]: a vertex v paired with edge e links to the other endpoint
@@ -22,242 +30,410 @@
 //    cofacet of s (older in the reversed order), or to the image's exterior
 //    node when s lies on the boundary.  This is the same forest for the dual
 //    union-find of the top dimension.
+// and, for the degree-1 reduction of a volume, eapp[3 * pixel + axis] of every
+// edge: 2 * axis + (direction > 0) of its apparent partner square, 0xFF if none.
 #include "cr_internal.h"
 
 namespace cr {
 
-template <int NDIM, int TX, int TY, int TZ>
-struct ApparentTile {
-  static constexpr int PX = TX + 3, PY = TY + 3, PZ = (NDIM == 3) ? TZ + 3 : 1;
-  static constexpr int RX = 2 * TX + 4, RY = 2 * TY + 4, RZ = (NDIM == 3) ? 2 * TZ + 4 : 1;
-  static constexpr int NT = TX * TY * TZ;
+constexpr uint32_t NONE = 0xFFFFFFFFu;  // key of a cell outside the image (above every value key)
+constexpr uint32_t NO_CODES = 0xFFFFFFu; // eight "none" codes
+
+// axis of direction d (0 z, 1 y, 2 x) and the bit of an axis in a cell type
+// t = 4 tz + 2 ty + tx
+__host__ __device__ constexpr int dir_axis(int d) { return d < 3 ? d : 5 - d; }
+__host__ __device__ constexpr int abit(int a) { return 4 >> a; }
+__host__ __device__ constexpr int popc3(int t) { return (t & 1) + ((t >> 1) & 1) + ((t >> 2) & 1); }
+
+struct Rec {
+  uint32_t v[8];  // keys of the 8 cells anchored at one pixel, by type
 };
 
-__device__ inline bool key_less(float va, uint32_t ka, float vb, uint32_t kb) {
-  return va < vb || (va == vb && ka < kb);
+__device__ __forceinline__ uint32_t lane_down1(uint32_t v) {  // lane i gets lane i+1 (lane 63 keeps its own)
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x130, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t lane_up1(uint32_t v) {  // lane i gets lane i-1 (lane 0 keeps its own)
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x138, 0xF, 0xF, false);
 }
 
-template <int NDIM, int TX, int TY, int TZ>
-__global__ __launch_bounds__(TX* TY* TZ) void k_apparent(
+__device__ __forceinline__ uint32_t pix_key(float v, bool* nan) {
+  if (v != v) {
+    *nan = true;
+    v = INFINITY;
+  }
+  v = canon(v);
+  uint32_t b;
+  __builtin_memcpy(&b, &v, 4);
+  return ord32_bits(b);
+}
+
+// Values derived from one pixel plane: the vertex, the x- and y-edges and the
+// xy-square anchored at the pixel.
+struct Planar {
+  uint32_t v, ex, ey, sxy;
+};
+__device__ __forceinline__ Planar planar(uint32_t f, uint32_t fx, uint32_t fy, uint32_t fxy) {
+  Planar p;
+  p.v = f;
+  p.ex = max(f, fx);
+  p.ey = max(f, fy);
+  p.sxy = max(p.ex, max(fy, fxy));
+  return p;
+}
+__device__ __forceinline__ Rec record(const Planar& a, const Planar& b) {  // a: plane z, b: plane z+1
+  Rec r;
+  r.v[0] = a.v;
+  r.v[1] = a.ex;
+  r.v[2] = a.ey;
+  r.v[3] = a.sxy;
+  r.v[4] = max(a.v, b.v);
+  r.v[5] = max(a.ex, b.ex);
+  r.v[6] = max(a.ey, b.ey);
+  r.v[7] = max(a.sxy, b.sxy);
+  return r;
+}
+
+// Earliest cofacet of the cell of type T: the first direction (ascending
+// kidx) of smallest value; m[a] is the record of the pixel one step down axis a.
+template <int T>
+__device__ __forceinline__ uint32_t ecf_code(const Rec& own, const Rec& mz, const Rec& my, const Rec& mx) {
+  uint32_t best = NONE, code = 7;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    const int a = dir_axis(d);
+    if (T & abit(a)) continue;
+    const int u = T | abit(a);
+    const uint32_t v = d >= 3 ? own.v[u] : (a == 0 ? mz.v[u] : (a == 1 ? my.v[u] : mx.v[u]));
+    if (v < best) {
+      best = v;
+      code = (uint32_t)d;
+    }
+  }
+  return code;
+}
+
+// Latest facet of the cell of type U: the last direction (ascending kidx) of
+// largest value; p[a] is the record of the pixel one step up axis a.
+template <int U>
+__device__ __forceinline__ uint32_t lf_code(const Rec& own, const Rec& pz, const Rec& py, const Rec& px) {
+  uint32_t best = 0, code = 7;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    const int a = dir_axis(d);
+    if (!(U & abit(a))) continue;
+    const int u = U ^ abit(a);
+    const uint32_t v = d < 3 ? own.v[u] : (a == 0 ? pz.v[u] : (a == 1 ? py.v[u] : px.v[u]));
+    if (v >= best) {
+      best = v;
+      code = (uint32_t)d;
+    }
+  }
+  return code;
+}
+
+template <int T = 0>
+__device__ __forceinline__ void codes_all(const Rec& own, const Rec& mz, const Rec& my, const Rec& mx,
+                                          const Rec& pz, const Rec& py, const Rec& px, uint32_t* E, uint32_t* F) {
+  if constexpr (T < 8) {
+    *E |= (T == 7 ? 7u : ecf_code<T>(own, mz, my, mx)) << (3 * T);
+    *F |= (T == 0 ? 7u : lf_code<T>(own, pz, py, px)) << (3 * T);
+    codes_all<T + 1>(own, mz, my, mx, pz, py, px, E, F);
+  }
+}
+
+__device__ __forceinline__ uint32_t code_of(uint32_t word, int t) { return (word >> (3 * t)) & 7u; }
+
+template <int RW>
+struct StencilLds {
+  uint4 recA[RW][64];  // record fields 0, 1, 4, 5 (read by the row above: cells without a y extent)
+  uint4 recB[RW][64];  // record fields 2, 3, 6, 7 (read by the row below)
+  uint2 cw[2][RW][64]; // (earliest-cofacet codes, latest-facet codes), by plane parity
+  uint32_t wcnt[RW];
+  uint32_t woff[RW];
+  unsigned long long wbase;
+};
+
+template <int NDIM, int RW, int ZC>
+__global__ __launch_bounds__(64 * RW) void k_stencil(
     const float* __restrict__ img, const ImgDesc* __restrict__ imgs, const int4* __restrict__ tiles,
     Layout L, uint64_t* __restrict__ surv, uint64_t surv_cap,
     unsigned long long* __restrict__ surv_count, int32_t* __restrict__ vlink, int32_t* __restrict__ tlink,
     uint8_t* __restrict__ eapp, uint32_t* __restrict__ img_status, Status* __restrict__ st) {
-  using T = ApparentTile<NDIM, TX, TY, TZ>;
-  __shared__ float pix[T::PZ * T::PY * T::PX];
-  __shared__ float kv[T::RZ * T::RY * T::RX];
-  __shared__ unsigned int wtot[T::NT / 64];
-  __shared__ unsigned long long bbase;
-  __shared__ unsigned int nan_seen;
-
-  const int tid = threadIdx.x;
+  __shared__ StencilLds<RW> S;
+  constexpr int TOP = NDIM == 3 ? 7 : 3;  // type of the top cell
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
   const int4 tile = tiles[blockIdx.x];
   const int im = tile.x;
   const ImgDesc d = imgs[im];
-  const int z0 = (NDIM == 3) ? tile.y : 0, y0 = tile.z, x0 = tile.w;
-  if (tid == 0) nan_seen = 0;
+  const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
+  const int z0 = tile.y, y0 = tile.z, x0 = tile.w;
+  const int x = x0 - 1 + lane, y = y0 - 1 + row;
+  const bool xin = x >= 0 && x < n2, x1in = x + 1 >= 0 && x + 1 < n2;
+  const bool yin = y >= 0 && y < n1, y1in = y + 1 >= 0 && y + 1 < n1;
+  const bool inner = lane >= 1 && lane <= 62 && row >= 1 && row <= RW - 2 && xin && yin;
+  const uint32_t K1 = (uint32_t)d.K[1], K2 = (uint32_t)d.K[2];
+  const int64_t rowpix = (int64_t)n1 * n2;
+  bool nan = false;
 
-  // ---- stage pixels (tile origin minus one, plus a halo of two after) ----
-  const int pz0 = (NDIM == 3) ? z0 - 1 : 0;
-  for (int i = tid; i < T::PZ * T::PY * T::PX; i += T::NT) {
-    const int px = i % T::PX, py = (i / T::PX) % T::PY, pz = i / (T::PX * T::PY);
-    const int gx = x0 - 1 + px, gy = y0 - 1 + py, gz = pz0 + pz;
-    float v = INFINITY;
-    if (gx >= 0 && gx < d.n[2] && gy >= 0 && gy < d.n[1] && gz >= 0 && gz < d.n[0]) {
-      v = img[pixel_index(d, gz, gy, gx)];
-      if (v != v) {
-        nan_seen = 1;
-        v = INFINITY;
-      }
-      v = canon(v);
+  // pixel keys of plane zz at (x, y), (x, y+1) and their right neighbours
+  auto load_plane = [&](int zz, uint32_t* f, uint32_t* fy) {
+    const bool zin = zz >= 0 && zz < n0;
+    const int64_t base = d.pix_off + (int64_t)zz * rowpix + (int64_t)y * n2 + x;
+    *f = (zin && xin && yin) ? pix_key(img[base], &nan) : NONE;
+    *fy = (zin && xin && y1in) ? pix_key(img[base + n2], &nan) : NONE;
+  };
+  auto planar_of = [&](int zz, uint32_t f, uint32_t fy) {
+    uint32_t fx = lane_down1(f), fxy = lane_down1(fy);
+    if (lane == 63) {  // the right neighbour lies beyond the wavefront
+      const bool zin = zz >= 0 && zz < n0;
+      const int64_t base = d.pix_off + (int64_t)zz * rowpix + (int64_t)y * n2 + x + 1;
+      fx = (zin && x1in && yin) ? pix_key(img[base], &nan) : NONE;
+      fxy = (zin && x1in && y1in) ? pix_key(img[base + n2], &nan) : NONE;
     }
-    pix[i] = v;
+    return planar(f, fx, fy, fxy);
+  };
+
+  // Exchanges the record of plane kk with the rows above and below; returns
+  // the earliest-cofacet and latest-facet codes of the cells at plane kk.
+  auto codes_of_plane = [&](const Rec& R0, const Rec& Rm, const Rec& Rp, uint32_t* E, uint32_t* F) {
+    S.recA[row][lane] = make_uint4(R0.v[0], R0.v[1], R0.v[4], R0.v[5]);
+    S.recB[row][lane] = make_uint4(R0.v[2], R0.v[3], R0.v[6], R0.v[7]);
+    __syncthreads();
+    Rec ym, yp, xm, xp;
+    const uint4 b = row > 0 ? S.recB[row - 1][lane] : make_uint4(NONE, NONE, NONE, NONE);
+    const uint4 a = row < RW - 1 ? S.recA[row + 1][lane] : make_uint4(NONE, NONE, NONE, NONE);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      ym.v[t] = NONE;
+      yp.v[t] = NONE;
+      xm.v[t] = lane_up1(R0.v[t]);
+      xp.v[t] = lane_down1(R0.v[t]);
+    }
+    ym.v[2] = b.x; ym.v[3] = b.y; ym.v[6] = b.z; ym.v[7] = b.w;
+    yp.v[0] = a.x; yp.v[1] = a.y; yp.v[4] = a.z; yp.v[5] = a.w;
+    *E = 0;
+    *F = 0;
+    codes_all(R0, Rm, ym, xm, Rp, yp, xp, E, F);
+  };
+
+  // Classifies the cells anchored at (plane zc, y, x) from the codes of this
+  // pixel (E0, F0), of the pixels one step down each axis (latest-facet words
+  // Fm*) and one step up (earliest-cofacet words Ep*).  Writes the links and
+  // returns the survivor mask; keys[] receives the survivors' keys.
+  auto classify = [&](int zc, const Rec& R, uint32_t E0, uint32_t F0, uint32_t Fmz, uint32_t Fmy, uint32_t Fmx,
+                      uint32_t Epz, uint32_t Epy, uint32_t Epx, uint64_t* keys) -> uint32_t {
+    const int64_t pix = d.pix_off + (int64_t)zc * rowpix + (int64_t)y * n2 + x;
+    const int pc[3] = {zc, y, x};
+    const uint32_t kbase = ((uint32_t)(2 * zc) * K1 + (uint32_t)(2 * y)) * K2 + (uint32_t)(2 * x);
+    uint32_t mask = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (R.v[t] == NONE) continue;  // the cell leaves the image
+      bool paired = false;
+      uint32_t e = 7, f = 7;
+      if (t != 7) {  // as the facet of its earliest cofacet
+        e = code_of(E0, t);
+        if (e != 7) {
+          const int a = dir_axis((int)e);
+          const int u = t | abit(a);
+          const uint32_t lfw = e >= 3 ? F0 : (a == 0 ? Fmz : (a == 1 ? Fmy : Fmx));
+          paired = code_of(lfw, u) == (e >= 3 ? (uint32_t)a : (uint32_t)(5 - a));
+        }
+      }
+      if (!paired && t != 0) {  // as the cofacet of its latest facet
+        f = code_of(F0, t);
+        if (f != 7) {
+          const int b = dir_axis((int)f);
+          const int s = t ^ abit(b);
+          const uint32_t ecw = f < 3 ? E0 : (b == 0 ? Epz : (b == 1 ? Epy : Epx));
+          paired = code_of(ecw, s) == (f < 3 ? (uint32_t)(5 - b) : (uint32_t)b);
+        } else {
+          f = 7;
+        }
+      } else {
+        f = 7;
+      }
+      if (t == 0) {  // vertex: link to the other end of its edge
+        int32_t to = -1;
+        if (paired) {
+          const int a = dir_axis((int)e);
+          const int64_t step = a == 0 ? rowpix : (a == 1 ? (int64_t)n2 : 1);
+          to = (int32_t)(e >= 3 ? pix + step : pix - step);
+        }
+        vlink[pix] = to;
+      }
+      if (t == TOP) {  // top cell: link to the other cofacet of its facet, or the exterior
+        int32_t to = -1;
+        if (paired) {
+          const int b = dir_axis((int)f);
+          const int64_t step = b == 0 ? rowpix : (b == 1 ? (int64_t)n2 : 1);
+          const int nb = b == 0 ? n0 : (b == 1 ? n1 : n2);
+          const bool ext = f < 3 ? pc[b] < 1 : pc[b] + 2 >= nb;
+          to = ext ? -(im + 2) : (int32_t)(f < 3 ? pix - step : pix + step);
+        }
+        tlink[pix] = to;
+      }
+      if (NDIM == 3 && popc3(t) == 1 && eapp) {
+        const int ax = t == 4 ? 0 : (t == 2 ? 1 : 2);
+        eapp[3 * pix + ax] = (paired && e != 7 && (t & abit(dir_axis((int)e))) == 0 && f == 7)
+                                 ? (uint8_t)(2 * dir_axis((int)e) + (e >= 3 ? 1 : 0))
+                                 : (uint8_t)0xFF;
+      }
+      if (!paired) {
+        mask |= 1u << t;
+        const uint32_t kidx = kbase + ((t & 4) ? K1 * K2 : 0u) + ((t & 2) ? K2 : 0u) + (uint32_t)(t & 1);
+        keys[t] = make_skey(L, popc3(t), im, R.v[t], kidx);
+      }
+    }
+    return mask;
+  };
+
+  // Appends the survivors of this step with one atomic per workgroup.
+  auto flush = [&](uint32_t mask, const uint64_t* keys) {
+    const uint32_t cnt = (uint32_t)__popc(mask);
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int bit = 0; bit < 4; ++bit) {
+      const uint64_t bm = __ballot((cnt >> bit) & 1u);
+      pre += __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u)) << bit;
+      tot += (uint32_t)__popcll(bm) << bit;
+    }
+    if (lane == 0) S.wcnt[row] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t run = 0;
+      for (int w = 0; w < RW; ++w) {
+        S.woff[w] = run;
+        run += S.wcnt[w];
+      }
+      S.wbase = run ? atomicAdd(surv_count, (unsigned long long)run) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long pos = S.wbase + S.woff[row] + pre;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (mask & (1u << t)) {
+        if (pos < surv_cap) surv[pos] = keys[t];
+        else raise_flag(st, &st->overflow, OVF_SURVIVORS);
+        ++pos;
+      }
+    }
+  };
+
+  uint64_t keys[8];
+  if constexpr (NDIM == 2) {
+    uint32_t f, fy;
+    load_plane(0, &f, &fy);
+    const Planar p0 = planar_of(0, f, fy);
+    const Planar none = {NONE, NONE, NONE, NONE};
+    const Rec R0 = record(p0, none);
+    Rec Rn;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) Rn.v[t] = NONE;
+    uint32_t E, F;
+    codes_of_plane(R0, Rn, Rn, &E, &F);
+    S.cw[0][row][lane] = make_uint2(E, F);
+    __syncthreads();
+    const uint32_t Fmy = row > 0 ? S.cw[0][row - 1][lane].y : NO_CODES;
+    const uint32_t Epy = row < RW - 1 ? S.cw[0][row + 1][lane].x : NO_CODES;
+    const uint32_t Fmx = lane_up1(F), Epx = lane_down1(E);
+    uint32_t mask = 0;
+    if (inner) mask = classify(0, R0, E, F, NO_CODES, Fmy, Fmx, NO_CODES, Epy, Epx, keys);
+    flush(mask, keys);
+  } else {
+    const int zend = z0 + ZC < n0 ? z0 + ZC : n0;
+    // rolling state: planar values of plane kk+1, records of planes kk-1..kk+1,
+    // codes of planes kk-2 (latest-facet word) and kk-1, and the prefetched plane
+    uint32_t f, fy, nf, nfy;
+    load_plane(z0 - 2, &f, &fy);
+    Planar pcur = planar_of(z0 - 2, f, fy);
+    load_plane(z0 - 1, &nf, &nfy);
+    Rec Rm, R0, Rp;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      Rm.v[t] = NONE;
+      R0.v[t] = NONE;
+      Rp.v[t] = NONE;
+    }
+    uint32_t Ec = NO_CODES, Fc = NO_CODES, Fcm = NO_CODES;
+    for (int kk = z0 - 3; kk <= zend; ++kk) {
+      // plane kk+2 was prefetched; start the load of plane kk+3
+      f = nf;
+      fy = nfy;
+      load_plane(kk + 3, &nf, &nfy);
+      const Planar pnext = planar_of(kk + 2, f, fy);
+      Rm = R0;
+      R0 = Rp;
+      Rp = record(pcur, pnext);  // record of plane kk+1
+      pcur = pnext;
+      if (kk < z0 - 1) continue;
+      uint32_t E, F;
+      codes_of_plane(R0, Rm, Rp, &E, &F);  // codes of plane kk
+      S.cw[kk & 1][row][lane] = make_uint2(E, F);
+      uint32_t mask = 0;
+      const int zc = kk - 1;
+      if (zc >= z0) {
+        // neighbours of plane zc: their codes were stored in the previous step,
+        // before this step's barrier
+        const uint32_t Fmy = row > 0 ? S.cw[zc & 1][row - 1][lane].y : NO_CODES;
+        const uint32_t Epy = row < RW - 1 ? S.cw[zc & 1][row + 1][lane].x : NO_CODES;
+        const uint32_t Fmx = lane_up1(Fc), Epx = lane_down1(Ec);
+        if (inner) mask = classify(zc, Rm, Ec, Fc, Fcm, Fmy, Fmx, E, Epy, Epx, keys);
+      }
+      Fcm = Fc;
+      Ec = E;
+      Fc = F;
+      flush(mask, keys);  // also the barrier before the next step's record exchange
+    }
   }
-  __syncthreads();
-  if (tid == 0 && nan_seen) {
+  if (__ballot(nan) && lane == 0) {
     atomicOr(&img_status[im], 1u);
     atomicOr(&st->nan_input, 1u);
   }
+}
 
-  // ---- values of all cells within Khalimsky distance 2 of the tile ----
-  const int bz = (NDIM == 3) ? 2 * z0 - 2 : 0, by = 2 * y0 - 2, bx = 2 * x0 - 2;
-  for (int i = tid; i < T::RZ * T::RY * T::RX; i += T::NT) {
-    const int lx = i % T::RX, ly = (i / T::RX) % T::RY, lz = i / (T::RX * T::RY);
-    const int kx = bx + lx, ky = by + ly, kz = bz + lz;
-    float v = 0.0f;
-    if (kx >= 0 && kx < d.K[2] && ky >= 0 && ky < d.K[1] && kz >= 0 && kz < d.K[0]) {
-      const int qx = (kx >> 1) - (x0 - 1), qy = (ky >> 1) - (y0 - 1), qz = (kz >> 1) - pz0;
-      v = -INFINITY;
-      for (int dz = 0; dz <= (kz & 1); ++dz)
-        for (int dy = 0; dy <= (ky & 1); ++dy)
-          for (int dx = 0; dx <= (kx & 1); ++dx)
-            v = fmaxf(v, pix[((qz + dz) * T::PY + qy + dy) * T::PX + qx + dx]);
-    }
-    kv[i] = v;
-  }
-  __syncthreads();
+template <int NDIM, int RW, int ZC>
+void launch_stencil_t(int ntiles, const float* img, const ImgDesc* imgs, const int4* tiles, Layout L,
+                      uint64_t* surv, uint64_t surv_cap, unsigned long long* surv_count, int32_t* vlink,
+                      int32_t* tlink, uint8_t* eapp, uint32_t* img_status, Status* st, hipStream_t stream) {
+  k_stencil<NDIM, RW, ZC><<<ntiles, 64 * RW, 0, stream>>>(img, imgs, tiles, L, surv, surv_cap, surv_count, vlink,
+                                                          tlink, eapp, img_status, st);
+}
 
-  // ---- classify the cells anchored at this thread's pixel ----
-  constexpr int NCELL = 1 << NDIM;
-  const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
-  const int gx = x0 + tx, gy = y0 + ty, gz = z0 + tz;
-  const bool pix_in = gx < d.n[2] && gy < d.n[1] && gz < d.n[0];
-  uint32_t surv_mask = 0;
-  uint64_t keys[NCELL];
-  const int Kd[3] = {d.K[0], d.K[1], d.K[2]};
-  const int base[3] = {bz, by, bx};
-  auto lidx = [&](const int k[3]) { return ((k[0] - base[0]) * T::RY + (k[1] - base[1])) * T::RX + (k[2] - base[2]); };
-  auto kid = [&](const int k[3]) {
-    return ((uint32_t)k[0] * (uint32_t)Kd[1] + (uint32_t)k[1]) * (uint32_t)Kd[2] + (uint32_t)k[2];
-  };
+// Tile shapes: RW wavefronts (RW-2 interior rows of 62 pixels) and ZC planes.
+struct TileVariant {
+  int rw, zc;
+};
+constexpr TileVariant TILES2[3] = {{16, 1}, {8, 1}, {4, 1}};
+constexpr TileVariant TILES3[3] = {{16, 32}, {16, 16}, {8, 32}};
 
-#pragma unroll
-  for (int cs = 0; cs < NCELL; ++cs) {
-    const int dx = cs & 1, dy = (cs >> 1) & 1, dz = (NDIM == 3) ? (cs >> 2) & 1 : 0;
-    int k[3] = {2 * gz + dz, 2 * gy + dy, 2 * gx + dx};
-    if (!pix_in || k[0] >= Kd[0] || k[1] >= Kd[1] || k[2] >= Kd[2]) continue;
-    const int dim = dx + dy + dz;
-    const float vc = kv[lidx(k)];
-    const uint32_t kc = kid(k);
-    bool paired = false;
+void launch_apparent(int ndim, int variant, int ntiles, const float* img, const ImgDesc* imgs, const int4* tiles,
+                     Layout L, uint64_t* surv, uint64_t surv_cap, unsigned long long* surv_count,
+                     int32_t* vlink, int32_t* tlink, uint8_t* eapp, uint32_t* img_status, Status* st,
+                     hipStream_t stream) {
+  if (ntiles <= 0) return;
+#define CR_STENCIL(N, R, Z) \
+  launch_stencil_t<N, R, Z>(ntiles, img, imgs, tiles, L, surv, surv_cap, surv_count, vlink, tlink, eapp, img_status, st, stream)
+  if (ndim == 2) {
+    if (variant == 1) CR_STENCIL(2, 8, 1);
+    else if (variant == 2) CR_STENCIL(2, 4, 1);
+    else CR_STENCIL(2, 16, 1);
+  } else {
+    if (variant == 1) CR_STENCIL(3, 16, 16);
+    else if (variant == 2) CR_STENCIL(3, 8, 32);
+    else CR_STENCIL(3, 16, 32);
+  }
+#undef CR_STENCIL
+}
 
-    // (a) as the facet of an apparent pair: earliest cofacet t, then is k the latest facet of t?
-    if (dim < NDIM) {
-      int ta = -1, ts = 0;
-      float tv = 0.0f;
-      uint32_t tk = 0;
-      for (int a = 0; a < 3; ++a) {
-        if (k[a] & 1) continue;
-        for (int s = -1; s <= 1; s += 2) {
-          int t[3] = {k[0], k[1], k[2]};
-          t[a] += s;
-          if (t[a] < 0 || t[a] >= Kd[a]) continue;
-          const float v = kv[lidx(t)];
-          const uint32_t kk = kid(t);
-          if (ta < 0 || key_less(v, kk, tv, tk)) {
-            ta = a; ts = s; tv = v; tk = kk;
-          }
-        }
-      }
-      bool latest = false;
-      if (ta >= 0) {
-        int t[3] = {k[0], k[1], k[2]};
-        t[ta] += ts;
-        latest = true;
-        for (int b = 0; b < 3 && latest; ++b) {
-          if (!(t[b] & 1)) continue;
-          for (int s = -1; s <= 1; s += 2) {
-            int f[3] = {t[0], t[1], t[2]};
-            f[b] += s;
-            if (f[0] == k[0] && f[1] == k[1] && f[2] == k[2]) continue;
-            if (key_less(vc, kc, kv[lidx(f)], kid(f))) {
-              latest = false;
-              break;
-            }
-          }
-        }
-      }
-      if (NDIM == 3 && dim == 1 && eapp) {
-        // apparent-partner code of an edge for the degree-1 reduction:
-        // 2 * axis + (direction > 0) of its partner square, 0xFF if none
-        const int oa = (k[0] & 1) ? 0 : ((k[1] & 1) ? 1 : 2);
-        eapp[3 * pixel_index(d, k[0] >> 1, k[1] >> 1, k[2] >> 1) + oa] =
-            latest ? (uint8_t)(2 * ta + (ts > 0 ? 1 : 0)) : (uint8_t)0xFF;
-      }
-      if (latest) {
-        paired = true;
-        if (dim == 0) {  // vertex: link to the other endpoint of its edge
-          int o[3] = {k[0], k[1], k[2]};
-          o[ta] += 2 * ts;
-          vlink[pixel_index(d, k[0] >> 1, k[1] >> 1, k[2] >> 1)] =
-              (int32_t)pixel_index(d, o[0] >> 1, o[1] >> 1, o[2] >> 1);
-        }
-      }
-    }
-    // (b) as the cofacet of an apparent pair: latest facet s, then is k the earliest cofacet of s?
-    if (!paired && dim >= 1) {
-      int sa = -1, ss = 0;
-      float sv = 0.0f;
-      uint32_t sk = 0;
-      for (int a = 0; a < 3; ++a) {
-        if (!(k[a] & 1)) continue;
-        for (int s = -1; s <= 1; s += 2) {
-          int f[3] = {k[0], k[1], k[2]};
-          f[a] += s;
-          const float v = kv[lidx(f)];
-          const uint32_t kk = kid(f);
-          if (sa < 0 || key_less(sv, sk, v, kk)) {
-            sa = a; ss = s; sv = v; sk = kk;
-          }
-        }
-      }
-      int f[3] = {k[0], k[1], k[2]};
-      f[sa] += ss;
-      bool earliest = true;
-      for (int b = 0; b < 3 && earliest; ++b) {
-        if (f[b] & 1) continue;
-        for (int s = -1; s <= 1; s += 2) {
-          int g[3] = {f[0], f[1], f[2]};
-          g[b] += s;
-          if (g[b] < 0 || g[b] >= Kd[b]) continue;
-          if (g[0] == k[0] && g[1] == k[1] && g[2] == k[2]) continue;
-          if (key_less(kv[lidx(g)], kid(g), vc, kc)) {
-            earliest = false;
-            break;
-          }
-        }
-      }
-      if (earliest) {
-        paired = true;
-        if (dim == NDIM) {  // top cell: link to the other cofacet of its facet, or the exterior
-          int o[3] = {k[0], k[1], k[2]};
-          o[sa] += 2 * ss;
-          int32_t to;
-          if (o[sa] < 0 || o[sa] >= Kd[sa]) to = -(im + 2);
-          else to = (int32_t)pixel_index(d, o[0] >> 1, o[1] >> 1, o[2] >> 1);
-          tlink[pixel_index(d, k[0] >> 1, k[1] >> 1, k[2] >> 1)] = to;
-        }
-      }
-    }
-    if (!paired) {
-      surv_mask |= 1u << cs;
-      uint32_t bits;
-      __builtin_memcpy(&bits, &vc, 4);
-      keys[cs] = make_skey(L, dim, im, ord32_bits(bits), kc);
-      if (dim == 0) vlink[pixel_index(d, k[0] >> 1, k[1] >> 1, k[2] >> 1)] = -1;
-      if (dim == NDIM) tlink[pixel_index(d, k[0] >> 1, k[1] >> 1, k[2] >> 1)] = -1;
-    }
-  }
-
-  // ---- append this workgroup's survivors with one atomic ----
-  const uint32_t mine = __popc(surv_mask);
-  const int lane = __lane_id(), wave = tid >> 6;
-  uint32_t incl = mine;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t up = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += up;
-  }
-  if (lane == 63) wtot[wave] = incl;
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t run = 0;
-    for (int w = 0; w < T::NT / 64; ++w) {
-      const uint32_t t = wtot[w];
-      wtot[w] = run;
-      run += t;
-    }
-    bbase = run ? atomicAdd(surv_count, (unsigned long long)run) : 0ull;
-  }
-  __syncthreads();
-  unsigned long long pos = bbase + wtot[wave] + incl - mine;
-#pragma unroll
-  for (int cs = 0; cs < NCELL; ++cs) {
-    if (surv_mask & (1u << cs)) {
-      if (pos < surv_cap) surv[pos] = keys[cs];
-      else raise_flag(st, &st->overflow, OVF_SURVIVORS);
-      ++pos;
-    }
-  }
+// Extents (z, y, x) of the interior of stencil tile `variant` for ndim; false if there is no such variant.
+bool stencil_tile(int ndim, int variant, int ext[3]) {
+  if (variant < 0 || variant >= 3 || (ndim != 2 && ndim != 3)) return false;
+  const TileVariant v = ndim == 2 ? TILES2[variant] : TILES3[variant];
+  ext[0] = v.zc;
+  ext[1] = v.rw - 2;
+  ext[2] = 62;
+  return true;
 }
 
 // Segment sizes of the sorted survivors: dim_count[d] = number of keys whose
@@ -282,40 +458,7 @@ __global__ void k_dim_bounds(const uint64_t* __restrict__ keys, const unsigned l
   if (t < 4) dim_count[t] = first[t + 1] - first[t];
 }
 
-// ---- host launcher ----------------------------------------------------------
-void launch_apparent(int ndim, int variant, int ntiles, const float* img, const ImgDesc* imgs, const int4* tiles,
-                     Layout L, uint64_t* surv, uint64_t surv_cap, unsigned long long* surv_count,
-                     int32_t* vlink, int32_t* tlink, uint8_t* eapp, uint32_t* img_status, Status* st,
-                     hipStream_t stream) {
-  if (ntiles <= 0) return;
-#define CR_APPARENT(N, X, Y, Z)                                                                     \
-  k_apparent<N, X, Y, Z><<<ntiles, X * Y * Z, 0, stream>>>(img, imgs, tiles, L, surv, surv_cap, surv_count, \
-                                                         vlink, tlink, eapp, img_status, st)
-  // tile shapes (x, y, z extents) indexed by variant; they must match stencil_tile()
-  if (ndim == 2) {
-    if (variant == 1) CR_APPARENT(2, 64, 4, 1);
-    else if (variant == 2) CR_APPARENT(2, 16, 16, 1);
-    else CR_APPARENT(2, 32, 8, 1);
-  } else {
-    if (variant == 1) CR_APPARENT(3, 32, 4, 2);
-    else if (variant == 2) CR_APPARENT(3, 8, 8, 4);
-    else CR_APPARENT(3, 16, 4, 4);
-  }
-#undef CR_APPARENT
-}
-
-// Extents (z, y, x) of stencil tile `variant` for ndim; returns false if there is no such variant.
-bool stencil_tile(int ndim, int variant, int ext[3]) {
-  static const int t2[3][3] = {{1, 8, 32}, {1, 4, 64}, {1, 16, 16}};
-  static const int t3[3][3] = {{4, 4, 16}, {2, 4, 32}, {4, 8, 8}};
-  if (variant < 0 || variant >= 3 || (ndim != 2 && ndim != 3)) return false;
-  const int* t = ndim == 2 ? t2[variant] : t3[variant];
-  ext[0] = t[0];
-  ext[1] = t[1];
-  ext[2] = t[2];
-  return true;
-}
-
+// ---- host launchers ----------------------------------------------------------
 void launch_dim_bounds(const uint64_t* keys, const unsigned long long* n_ptr, uint64_t cap, Layout L,
                        unsigned long long* dim_count, hipStream_t s) {
   k_dim_bounds<<<1, 64, 0, s>>>(keys, n_ptr, cap, L, dim_count);
