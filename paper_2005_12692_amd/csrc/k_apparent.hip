@@ -223,67 +223,43 @@ __global__ __launch_bounds__(64 * RW) void k_stencil(
   auto classify = [&](int zc, const Rec& R, uint32_t E0, uint32_t F0, uint32_t Fmz, uint32_t Fmy, uint32_t Fmx,
                       uint32_t Epz, uint32_t Epy, uint32_t Epx, uint64_t* keys) -> uint32_t {
     const int64_t pix = d.pix_off + (int64_t)zc * rowpix + (int64_t)y * n2 + x;
-    const int pc[3] = {zc, y, x};
     const uint32_t kbase = ((uint32_t)(2 * zc) * K1 + (uint32_t)(2 * y)) * K2 + (uint32_t)(2 * x);
     uint32_t mask = 0;
+    // branch-free: every quantity is computed for every cell type and selected
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      if (R.v[t] == NONE) continue;  // the cell leaves the image
-      bool paired = false;
-      uint32_t e = 7, f = 7;
-      if (t != 7) {  // as the facet of its earliest cofacet
-        e = code_of(E0, t);
-        if (e != 7) {
-          const int a = dir_axis((int)e);
-          const int u = t | abit(a);
-          const uint32_t lfw = e >= 3 ? F0 : (a == 0 ? Fmz : (a == 1 ? Fmy : Fmx));
-          paired = code_of(lfw, u) == (e >= 3 ? (uint32_t)a : (uint32_t)(5 - a));
-        }
-      }
-      if (!paired && t != 0) {  // as the cofacet of its latest facet
-        f = code_of(F0, t);
-        if (f != 7) {
-          const int b = dir_axis((int)f);
-          const int s = t ^ abit(b);
-          const uint32_t ecw = f < 3 ? E0 : (b == 0 ? Epz : (b == 1 ? Epy : Epx));
-          paired = code_of(ecw, s) == (f < 3 ? (uint32_t)(5 - b) : (uint32_t)b);
-        } else {
-          f = 7;
-        }
-      } else {
-        f = 7;
-      }
+      const bool exists = R.v[t] != NONE;
+      // as the facet of its earliest cofacet (code e, along axis a)
+      const uint32_t e = t == 7 ? 7u : code_of(E0, t);
+      const uint32_t a = e < 3 ? e : (e < 6 ? 5 - e : 0u);
+      const uint32_t u = (uint32_t)t | (4u >> a);
+      const uint32_t lfw = e >= 3 ? F0 : (a == 0 ? Fmz : (a == 1 ? Fmy : Fmx));
+      const bool pf = e != 7 && ((lfw >> (3 * u)) & 7u) == (e >= 3 ? a : 5 - a);
+      // as the cofacet of its latest facet (code f, along axis b)
+      const uint32_t f = t == 0 ? 7u : code_of(F0, t);
+      const uint32_t b = f < 3 ? f : (f < 6 ? 5 - f : 0u);
+      const uint32_t sv = (uint32_t)t ^ (4u >> b);
+      const uint32_t ecw = f < 3 ? E0 : (b == 0 ? Epz : (b == 1 ? Epy : Epx));
+      const bool pc = f != 7 && ((ecw >> (3 * sv)) & 7u) == (f < 3 ? 5 - b : b);
+      const bool paired = pf || pc;
       if (t == 0) {  // vertex: link to the other end of its edge
-        int32_t to = -1;
-        if (paired) {
-          const int a = dir_axis((int)e);
-          const int64_t step = a == 0 ? rowpix : (a == 1 ? (int64_t)n2 : 1);
-          to = (int32_t)(e >= 3 ? pix + step : pix - step);
-        }
-        vlink[pix] = to;
+        const int64_t step = a == 0 ? rowpix : (a == 1 ? (int64_t)n2 : 1);
+        vlink[pix] = pf ? (int32_t)(e >= 3 ? pix + step : pix - step) : -1;
       }
-      if (t == TOP) {  // top cell: link to the other cofacet of its facet, or the exterior
-        int32_t to = -1;
-        if (paired) {
-          const int b = dir_axis((int)f);
-          const int64_t step = b == 0 ? rowpix : (b == 1 ? (int64_t)n2 : 1);
-          const int nb = b == 0 ? n0 : (b == 1 ? n1 : n2);
-          const bool ext = f < 3 ? pc[b] < 1 : pc[b] + 2 >= nb;
-          to = ext ? -(im + 2) : (int32_t)(f < 3 ? pix - step : pix + step);
-        }
-        tlink[pix] = to;
+      if (t == TOP && exists) {  // top cell: link to the other cofacet of its facet, or the exterior
+        const int64_t step = b == 0 ? rowpix : (b == 1 ? (int64_t)n2 : 1);
+        const int nb = b == 0 ? n0 : (b == 1 ? n1 : n2);
+        const int pb = b == 0 ? zc : (b == 1 ? y : x);
+        const bool ext = f < 3 ? pb < 1 : pb + 2 >= nb;
+        tlink[pix] = pc ? (ext ? -(im + 2) : (int32_t)(f < 3 ? pix - step : pix + step)) : -1;
       }
-      if (NDIM == 3 && popc3(t) == 1 && eapp) {
-        const int ax = t == 4 ? 0 : (t == 2 ? 1 : 2);
-        eapp[3 * pix + ax] = (paired && e != 7 && (t & abit(dir_axis((int)e))) == 0 && f == 7)
-                                 ? (uint8_t)(2 * dir_axis((int)e) + (e >= 3 ? 1 : 0))
-                                 : (uint8_t)0xFF;
+      if (NDIM == 3 && popc3(t) == 1) {
+        if (eapp && exists)
+          eapp[3 * pix + (t == 4 ? 0 : (t == 2 ? 1 : 2))] = pf ? (uint8_t)(2 * a + (e >= 3 ? 1u : 0u)) : (uint8_t)0xFF;
       }
-      if (!paired) {
-        mask |= 1u << t;
-        const uint32_t kidx = kbase + ((t & 4) ? K1 * K2 : 0u) + ((t & 2) ? K2 : 0u) + (uint32_t)(t & 1);
-        keys[t] = make_skey(L, popc3(t), im, R.v[t], kidx);
-      }
+      const uint32_t kidx = kbase + ((t & 4) ? K1 * K2 : 0u) + ((t & 2) ? K2 : 0u) + (uint32_t)(t & 1);
+      keys[t] = make_skey(L, popc3(t), im, R.v[t], kidx);
+      mask |= (exists && !paired) ? (1u << t) : 0u;
     }
     return mask;
   };
