@@ -176,7 +176,8 @@ typedef struct cr_tuning {
   int32_t tile;         /* stencil tile shape, 0 .. cr_tile_variants(ndim)-1 (see cr_tile_shape) */
   int32_t grid;         /* workgroups of the grid-stride kernels (union-find, output), 64 .. 65536 */
   int32_t long_len;     /* degree-1 reduction of a volume: a stored column longer than this
-                           continues one per wavefront instead of one per thread */
+                           continues one per wavefront instead of one per thread (values
+                           above 16, the keys a thread holds in registers, act as 16) */
   int32_t yield_iters;  /* ... a column reduced one per thread moves to a wavefront after this
                            many additions (>= 1) */
   int32_t wave_short;   /* ... a list of at most this many short columns is run one per wavefront */
@@ -196,7 +197,8 @@ cr_status cr_tile_shape(int ndim, int variant, int32_t extents[3]);
 /* Autotuner: runs the batched call on the caller's batch (same arguments and
  * output buffers as cr_persistence_batched) for candidate parameter sets --
  * one parameter at a time: tile shape, grid, then for volumes with maxdim >= 1
- * the reduction thresholds -- each as one warm-up call plus `repeats` calls
+ * the front-list capacity and the reduction thresholds -- each as one warm-up
+ * call plus `repeats` calls
  * timed with HIP events on `stream`, keeps the fastest, makes it the context's
  * setting for ndim and copies it to *chosen (may be NULL).  Synchronises;
  * returns the first error of a candidate run (the previous setting is then

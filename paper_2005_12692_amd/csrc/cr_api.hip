@@ -19,7 +19,8 @@ void launch_apparent(int ndim, int variant, int ntiles, const float* img, const 
 void launch_dim_bounds(const uint64_t* keys, const unsigned long long* n_ptr, uint64_t cap, Layout L,
                        unsigned long long* dim_count, hipStream_t s);
 uint64_t* launch_sort(uint64_t* keys, uint64_t* tmp, const unsigned long long* n_ptr, uint64_t cap, int bits,
-                      uint32_t* hist, hipStream_t stream);
+                      void* scratch, hipStream_t stream);
+size_t sort_scratch_bytes(uint64_t cap);
 void launch_h0(int grid, const uint64_t* skeys, const unsigned long long* dim_count, const ImgDesc* imgs,
                Layout L, int32_t* vlink, uint64_t* T, uint8_t* neg, const EmitCtx& E, Status* st,
                hipStream_t s);
@@ -37,7 +38,6 @@ void launch_backward(const int64_t* bpix, const int64_t* dpix, const float* gb, 
                      float* grad, int64_t n_pixels, uint32_t* bad, hipStream_t s);
 void launch_check_empty(const unsigned long long* count, Status* st, hipStream_t s);
 bool stencil_tile(int ndim, int variant, int ext[3]);
-constexpr int SORT_HIST_WORDS = 256 * 1024;
 
 }  // namespace cr
 
@@ -73,10 +73,10 @@ cr_tuning default_tuning(int ndim) {
   cr_tuning t;
   t.tile = 0;
   t.grid = 2048;
-  t.long_len = 128;
-  t.yield_iters = 32;
-  t.wave_short = 4096;
-  t.front_cap = 4096;
+  t.long_len = 16;
+  t.yield_iters = 1024;
+  t.wave_short = 65536;
+  t.front_cap = 1024;
   (void)ndim;
   return t;
 }
@@ -93,7 +93,7 @@ struct Problem {
 
 struct Plan {
   size_t status, counters, img_status, img_pairs, imgs, tiles, surv_a, surv_b, hist, vlink, tlink, T, neg,
-      owner, claim, piv, colptr, arena, pbuf, cleared, list[4], eapp, total;
+      owner, claim, piv, colptr, arena, cleared, list[4], eapp, total;
   uint64_t surv_cap, e_cap, arena_cap;
 };
 
@@ -210,7 +210,7 @@ Plan make_plan(const Problem& pb, uint64_t arena_entries) {
   p.tiles = take(sizeof(int4) * pb.tiles.size());
   p.surv_a = take(8 * p.surv_cap);
   p.surv_b = take(8 * p.surv_cap);
-  p.hist = take(4 * (size_t)SORT_HIST_WORDS);
+  p.hist = take(sort_scratch_bytes(p.surv_cap));
   p.vlink = take(4 * pb.P);
   p.tlink = take(4 * pb.P);
   p.T = take(8 * (pb.P + pb.nimg + 64));
@@ -219,7 +219,6 @@ Plan make_plan(const Problem& pb, uint64_t arena_entries) {
   p.piv = take(vol ? 8 * p.e_cap : 0);
   p.colptr = take(vol ? 8 * p.e_cap : 0);
   p.arena = take(vol ? 8 * (p.arena_cap + ARENA_SLACK) : 0);
-  p.pbuf = take(vol ? 8 * PBUF_PER_THREAD * RGRID * 256 : 0);
   p.cleared = take(vol ? p.e_cap : 0);
   p.claim = take(vol ? 4 * 3 * pb.P : 0);
   for (int i = 0; i < 4; ++i) p.list[i] = take(vol ? 4 * p.e_cap : 0);
@@ -368,7 +367,7 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
   launch_apparent(pb.ndim, tu.tile, (int)pb.tiles.size(), image, d_imgs, d_tiles, L, surv, p.surv_cap, &cnt[C_SURV],
                   vlink, tlink, eapp, img_status, st, s);
   mark(ctx, EV_STENCIL, s);
-  uint32_t* hist = at<uint32_t>(ctx, p.hist);
+  void* hist = at<char>(ctx, p.hist);
   uint64_t* skeys = launch_sort(surv, surv_tmp, &cnt[C_SURV], p.surv_cap, 2 + L.ib + 32 + L.kb, hist, s);
   launch_dim_bounds(skeys, &cnt[C_SURV], p.surv_cap, L, &cnt[C_DIM], s);
   mark(ctx, EV_SORT, s);
@@ -406,8 +405,8 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     launch_fill_u32(at<uint32_t>(ctx, p.claim), 0x7FFFFFFFu, 3 * pb.P, s);
     RedCtx R = make_redctx(image, d_imgs, L, skeys, &cnt[C_DIM], cleared, eapp, owner, at<int32_t>(ctx, p.claim),
                            at<uint64_t>(ctx, p.piv), at<uint64_t>(ctx, p.colptr), at<uint64_t>(ctx, p.arena),
-                           p.arena_cap, &cnt[C_ARENA], &cnt[C_WORK], at<uint64_t>(ctx, p.pbuf), st);
-    R.long_len = (uint32_t)tu.long_len;
+                           p.arena_cap, &cnt[C_ARENA], &cnt[C_WORK], st);
+    R.long_len = (uint32_t)std::min(tu.long_len, 16);
     R.yield_iters = (uint32_t)tu.yield_iters;
     R.wave_short = (uint32_t)tu.wave_short;
     R.front_cap = (uint32_t)tu.front_cap;
@@ -936,17 +935,18 @@ cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed
   rc = time_it(best, &best_ms);
   // coordinate descent: one parameter at a time, in the order they matter
   const bool red = ndim == 3 && maxdim >= 1;
-  for (int coord = 0; rc == CR_OK && coord < (red ? 5 : 2); ++coord) {
+  for (int coord = 0; rc == CR_OK && coord < (red ? 6 : 2); ++coord) {
     std::vector<int> vals;
     if (coord == 0) for (int v = 0; v < N_TILE_VARIANTS; ++v) vals.push_back(v);
     if (coord == 1) vals = {512, 1024, 2048, 4096, 8192};
-    if (coord == 2) vals = {32, 64, 128, 256, 512};
-    if (coord == 3) vals = {8, 16, 32, 64};
-    if (coord == 4) vals = {1024, 2048, 4096};
+    if (coord == 2) vals = {512, 1024, 2048, 4096};
+    if (coord == 3) vals = {4, 8, 16};
+    if (coord == 4) vals = {0, 4096, 65536, 1 << 30};
+    if (coord == 5) vals = {16, 128, 1024};
     for (int v : vals) {
       cr_tuning t = best;
-      int* field = coord == 0 ? &t.tile : coord == 1 ? &t.grid : coord == 2 ? &t.long_len
-                 : coord == 3 ? &t.yield_iters : &t.front_cap;
+      int* field = coord == 0 ? &t.tile : coord == 1 ? &t.grid : coord == 2 ? &t.front_cap
+                 : coord == 3 ? &t.long_len : coord == 4 ? &t.wave_short : &t.yield_iters;
       if (*field == v) continue;
       *field = v;
       float ms = 0.0f;

@@ -5,9 +5,6 @@
 namespace cr {
 
 constexpr uint32_t RED_ITER_CAP = 1u << 24;
-constexpr uint32_t FCAP = 64;              // front list capacity
-constexpr uint32_t FBUF = 2 * FCAP + 8;    // front buffer entries (F plus an addend)
-constexpr uint32_t PCAP = 1024;            // private tail buffer entries
 
 struct RedCtx {
   const float* img;
@@ -25,16 +22,15 @@ struct RedCtx {
   uint64_t* arena;         // stored lists: a length word followed by that many ascending keys
   uint64_t arena_cap;
   unsigned long long* arena_top;
-  uint64_t* pbuf;          // private buffers, PBUF_PER_THREAD entries per thread
   Status* st;
   unsigned long long* work;  // column counter of the wave-mode round
-  uint32_t long_len;       // stored columns longer than this continue in wave mode
+  uint32_t long_len;       // stored columns longer than this continue in wave mode (<= 16: thread mode
+                           // holds a column of up to 16 keys in registers)
   uint32_t yield_iters;    // thread mode hands a column to wave mode after this many additions
   uint32_t wave_short;     // a short list of at most this many columns is run in wave mode too
   uint32_t front_cap;      // keys of the wave-mode LDS front list
 };
 constexpr uint64_t NO_OWNER = ~0ull;
-constexpr uint64_t PBUF_PER_THREAD = 2 * FBUF + 2 * PCAP;
 constexpr uint64_t ARENA_SLACK = 64;       // readable entries past the arena end (wave loads of 64 words)
 constexpr uint64_t ARENA_MAX = (1ull << 32) - ARENA_SLACK;  // offsets fit the low half of an owner word
 constexpr uint32_t FRONT_CAP_MIN = 128;    // wave-mode LDS front list capacity bounds
@@ -44,7 +40,7 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
                    const unsigned long long* dim_count, const uint8_t* cleared, const uint8_t* eapp,
                    uint64_t* owner, int32_t* claim,
                    uint64_t* piv, uint64_t* col_ptr, uint64_t* arena, uint64_t arena_cap,
-                   unsigned long long* arena_top, unsigned long long* work, uint64_t* pbuf, Status* st);
+                   unsigned long long* arena_top, unsigned long long* work, Status* st);
 
 // Enqueues rounds [round0, round0 + nrounds) of the reduction.  lists/counts:
 // two ping-pong pairs of column lists (short columns for thread mode, long ones

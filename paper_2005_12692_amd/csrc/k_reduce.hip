@@ -92,112 +92,6 @@ __device__ inline uint64_t arena_alloc(const RedCtx& R, uint64_t len) {
   return off;
 }
 
-// out = a XOR b for ascending lists; returns the length.
-__device__ inline uint32_t xor_lists(const uint64_t* a, uint32_t na, const uint64_t* b, uint32_t nb,
-                                     uint64_t* out) {
-  uint32_t i = 0, j = 0, m = 0;
-  while (i < na && j < nb) {
-    const uint64_t x = a[i], y = b[j];
-    if (x < y) { out[m++] = x; ++i; }
-    else if (y < x) { out[m++] = y; ++j; }
-    else { ++i; ++j; }
-  }
-  while (i < na) out[m++] = a[i++];
-  while (j < nb) out[m++] = b[j++];
-  return m;
-}
-
-// ---- thread mode -----------------------------------------------------------------
-//
-// A working column is kept in two sorted parts: a short front list F (at most
-// FCAP entries plus one addend) that absorbs small additions, and a tail T.
-// The pivot is the larger of the two last entries after cancelling equal ones,
-// so adding a 4-entry boundary to a long column costs O(FCAP), not O(length);
-// F is merged into T only when it overflows.
-struct Work {
-  uint64_t* fbuf[2];
-  uint64_t* tbuf[2];
-  uint64_t* F;
-  uint32_t nf;
-  const uint64_t* T;
-  uint32_t nt;
-  int tsel;  // which private tail buffer T is in, or -1
-  unsigned long long adds, merged;
-  uint32_t maxlen;
-};
-
-// T ^= B into fresh storage (the other private tail buffer, or the arena).
-__device__ inline bool tail_add(const RedCtx& R, Work& W, const uint64_t* b, uint32_t nb) {
-  const uint32_t need = W.nt + nb;
-  uint64_t* out;
-  int sel = -1;
-  if (need <= PCAP) {
-    sel = W.tsel == 0 ? 1 : 0;
-    out = W.tbuf[sel];
-  } else {
-    const uint64_t off = arena_alloc(R, need);
-    if (off == ~0ull) return false;
-    out = R.arena + off;
-  }
-  W.nt = xor_lists(W.T, W.nt, b, nb, out);
-  W.T = out;
-  W.tsel = sel;
-  W.merged += need;
-  return true;
-}
-
-// W ^= B.  Returns false on arena exhaustion.
-__device__ inline bool work_add(const RedCtx& R, Work& W, const uint64_t* b, uint32_t nb) {
-  W.adds += 1;
-  if (nb > FCAP) {
-    if (!tail_add(R, W, b, nb)) return false;
-  } else {
-    uint64_t* out = (W.F == W.fbuf[0]) ? W.fbuf[1] : W.fbuf[0];
-    W.merged += W.nf + nb;
-    W.nf = xor_lists(W.F, W.nf, b, nb, out);
-    W.F = out;
-    if (W.nf > FCAP) {
-      if (!tail_add(R, W, W.F, W.nf)) return false;
-      W.nf = 0;
-    }
-  }
-  if (W.nf + W.nt > W.maxlen) W.maxlen = W.nf + W.nt;
-  return true;
-}
-
-// Cancels equal last entries of F and T; returns false if the column is zero.
-__device__ inline bool work_pivot(Work& W, uint64_t* piv) {
-  while (W.nf && W.nt && W.F[W.nf - 1] == W.T[W.nt - 1]) {
-    --W.nf;
-    --W.nt;
-  }
-  if (!W.nf && !W.nt) return false;
-  if (!W.nf) *piv = W.T[W.nt - 1];
-  else if (!W.nt) *piv = W.F[W.nf - 1];
-  else *piv = W.F[W.nf - 1] > W.T[W.nt - 1] ? W.F[W.nf - 1] : W.T[W.nt - 1];
-  return true;
-}
-
-// Writes F XOR T to the arena as a stored list; afterwards the working column is that list.
-__device__ inline uint64_t work_publish(const RedCtx& R, Work& W) {
-  const uint64_t off = arena_alloc(R, (uint64_t)W.nf + W.nt + 1);
-  if (off == ~0ull) return ~0ull;
-  const uint32_t len = xor_lists(W.F, W.nf, W.T, W.nt, R.arena + off + 1);
-  R.arena[off] = len;
-  W.T = R.arena + off + 1;
-  W.nt = len;
-  W.tsel = -1;
-  W.nf = 0;
-  return off;
-}
-
-__device__ inline void work_load(Work& W, const RedCtx& R, uint64_t off) {
-  W.T = R.arena + off + 1;
-  W.nt = (uint32_t)R.arena[off];
-  W.tsel = -1;
-  W.nf = 0;
-}
-
 constexpr uint64_t YIELDED = ~0ull;      // piv[c] of a column that stored its state without proposing
 
 __device__ inline void push_list(uint32_t* list, unsigned long long* n, uint32_t c) {
@@ -220,76 +114,223 @@ __device__ inline void wave_push(uint32_t* list, unsigned long long* n, bool act
   }
 }
 
-// Stores W as column c and proposes c as the owner of e (or yields if e == YIELDED).
-__device__ inline bool store_and_propose(const RedCtx& R, Work& W, uint32_t c, uint64_t e, int64_t slot) {
-  const uint64_t off = work_publish(R, W);
-  if (off == ~0ull) return false;
-  R.col_ptr[c] = off;
-  R.piv[c] = e;
-  if (e != YIELDED) atomicMin(&R.claim[slot], (int32_t)c);
-  return true;
+template <typename T>
+__device__ __forceinline__ T sel3(int i, T a, T b, T c) { return i == 0 ? a : (i == 1 ? b : c); }
+
+__device__ __forceinline__ uint32_t ord_of(float v) {
+  uint32_t bits;
+  __builtin_memcpy(&bits, &v, 4);
+  return ord32_bits(bits);
+}
+__device__ __forceinline__ float pix_val(const float* img, int64_t p) {
+  const float v = img[p];
+  return (v != v) ? INFINITY : canon(v);
 }
 
-// One round of column c in thread mode: reduce it against the columns done
-// before this round, then store it and propose it as the owner of its pivot.
-// A column whose tail grows past R.long_len keys, or that needs more than
-// R.yield_iters additions, stores its state and moves to the wave-mode list
-// (a single thread merges long lists at one memory latency per key).
-__device__ void reduce_round(const RedCtx& R, uint32_t c, bool first, uint64_t off2, Work& W,
-                             uint32_t* long_next, unsigned long long* n_long_next) {
-  if (first) {  // initial column: the boundary of the square
-    const uint64_t k = R.skeys[off2 + c];
-    const int im = skey_img(R.L, k);
-    const ImgDesc d = R.imgs[im];
-    int sc[3];
-    kidx_coords(d, skey_kidx(R.L, k), sc);
-    W.F = W.fbuf[0];
-    W.nf = (uint32_t)sq_boundary(R, im, d, sc, W.F);
-    W.T = W.tbuf[0];
-    W.nt = 0;
-    W.tsel = 0;
-  } else {
-    W.F = W.fbuf[0];
-    work_load(W, R, R.col_ptr[c]);
+// ---- thread mode: one thread per column, the column in registers -----------------
+//
+// A column of at most TC keys is kept sorted in descending order in registers
+// (w[0] is the pivot).  XOR-inserting a key compares it with every slot and
+// shifts by selects, so nothing is indexed dynamically.  A column that would
+// grow past TC keys, or needs more than yield_iters additions in one round, is
+// stored and continues in wave mode.
+template <int TC>
+struct RegCol {
+  uint64_t w[TC];
+  uint32_t n;
+};
+
+template <int TC>
+__device__ __forceinline__ void rc_pop(RegCol<TC>& C) {
+#pragma unroll
+  for (int i = 0; i + 1 < TC; ++i) C.w[i] = C.w[i + 1];
+  C.w[TC - 1] = 0;
+  --C.n;
+}
+
+// C ^= {k}; when k is absent the column must have a free slot.  Empty slots
+// hold 0, below every key, so they need no bounds test.
+template <int TC>
+__device__ __forceinline__ void rc_xor(RegCol<TC>& C, uint64_t k) {
+  uint32_t gt = 0;
+  bool eq = false;
+#pragma unroll
+  for (int i = 0; i < TC; ++i) {
+    gt += C.w[i] > k ? 1u : 0u;
+    eq = eq || C.w[i] == k;
   }
-  for (uint32_t it = 0; it < RED_ITER_CAP; ++it) {
-    if ((it & 63) == 63 && aborted(R.st)) return;
-    if (it >= R.yield_iters || W.nt > R.long_len) {
-      if (store_and_propose(R, W, c, YIELDED, 0)) push_list(long_next, n_long_next, c);
+  if (eq) {  // remove slot gt: shift the smaller keys up, in place from the top
+#pragma unroll
+    for (int i = 0; i < TC; ++i) {
+      const uint64_t next = i + 1 < TC ? C.w[i + 1 < TC ? i + 1 : i] : 0ull;
+      if ((uint32_t)i >= gt) C.w[i] = next;
+    }
+    --C.n;
+  } else {  // insert at slot gt: shift the smaller keys down, in place from the bottom
+#pragma unroll
+    for (int i = TC - 1; i >= 0; --i) {
+      const uint64_t prev = i > 0 ? C.w[i > 0 ? i - 1 : 0] : 0ull;
+      C.w[i] = (uint32_t)i > gt ? prev : ((uint32_t)i == gt ? k : C.w[i]);
+    }
+    ++C.n;
+  }
+}
+
+// Writes the column to the arena as a stored list (ascending); returns its offset.
+template <int TC>
+__device__ __forceinline__ uint64_t rc_store(const RedCtx& R, const RegCol<TC>& C) {
+  const uint64_t off = arena_alloc(R, (uint64_t)C.n + 1);
+  if (off == ~0ull) return off;
+  R.arena[off] = C.n;
+#pragma unroll
+  for (int i = 0; i < TC; ++i)
+    if ((uint32_t)i < C.n) R.arena[off + C.n - i] = C.w[i];
+  return off;
+}
+
+template <int TC>
+__device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64_t off2, uint32_t* long_next,
+                                 unsigned long long* n_long_next, unsigned long long* adds) {
+  const uint64_t sq = R.skeys[off2 + c];
+  const int im = skey_img(R.L, sq);
+  const ImgDesc d = R.imgs[im];
+  const uint32_t K1 = (uint32_t)d.K[1], K2 = (uint32_t)d.K[2];
+  const int64_t ps0 = (int64_t)d.n[1] * d.n[2], ps1 = d.n[2];
+  const uint32_t ks0 = K1 * K2, ks1 = K2;
+  RegCol<TC> C;
+#pragma unroll
+  for (int i = 0; i < TC; ++i) C.w[i] = 0;
+  if (first) {  // the boundary of the square: its four edges, from its four vertices
+    const uint32_t sk = skey_kidx(R.L, sq);
+    const uint32_t sx = sk % K2, st1 = sk / K2;
+    const uint32_t sy = st1 % K1, sz = st1 / K1;
+    const int a0 = (sz & 1) ? 0 : 1;                 // the two odd axes a0 < a1 of the square
+    const int a1 = (sx & 1) ? 2 : 1;
+    const int64_t p00 = pixel_index(d, (int)(sz >> 1), (int)(sy >> 1), (int)(sx >> 1));
+    const int64_t pa = sel3(a0, ps0, ps1, (int64_t)1), pb = sel3(a1, ps0, ps1, (int64_t)1);
+    const uint32_t ka = sel3(a0, ks0, ks1, 1u), kb = sel3(a1, ks0, ks1, 1u);
+    const float f00 = pix_val(R.img, p00), f10 = pix_val(R.img, p00 + pa);
+    const float f01 = pix_val(R.img, p00 + pb), f11 = pix_val(R.img, p00 + pa + pb);
+    // edges along a1 at a0 = low / high, along a0 at a1 = low / high
+    C.w[0] = make_skey(R.L, 1, im, ord_of(fmaxf(f00, f01)), sk - ka);
+    C.w[1] = make_skey(R.L, 1, im, ord_of(fmaxf(f10, f11)), sk + ka);
+    C.w[2] = make_skey(R.L, 1, im, ord_of(fmaxf(f00, f10)), sk - kb);
+    C.w[3] = make_skey(R.L, 1, im, ord_of(fmaxf(f01, f11)), sk + kb);
+    // descending sorting network on four keys
+    auto cx = [](uint64_t& x, uint64_t& y) {
+      const uint64_t hi = x > y ? x : y, lo = x > y ? y : x;
+      x = hi;
+      y = lo;
+    };
+    cx(C.w[0], C.w[1]);
+    cx(C.w[2], C.w[3]);
+    cx(C.w[0], C.w[2]);
+    cx(C.w[1], C.w[3]);
+    cx(C.w[1], C.w[2]);
+    C.n = 4;
+  } else {
+    const uint64_t off = R.col_ptr[c];
+    const uint32_t len = (uint32_t)R.arena[off];
+    if (len > (uint32_t)TC) {  // too long for registers: straight to wave mode
+      R.piv[c] = YIELDED;
+      push_list(long_next, n_long_next, c);
       return;
     }
-    uint64_t e;
-    if (!work_pivot(W, &e)) {  // a zero column would be a birth of degree 2: those were cleared
+#pragma unroll
+    for (int i = 0; i < TC; ++i)
+      if ((uint32_t)i < len) C.w[i] = R.arena[off + len - i];
+    C.n = len;
+  }
+  auto yield = [&]() {
+    const uint64_t off = rc_store(R, C);
+    if (off == ~0ull) return;
+    R.col_ptr[c] = off;
+    R.piv[c] = YIELDED;
+    push_list(long_next, n_long_next, c);
+  };
+  for (uint32_t it = 0;; ++it) {
+    if (it >= R.yield_iters) {
+      yield();
+      return;
+    }
+    if (C.n == 0) {  // a zero column would be a birth of degree 2: those were cleared
       raise_flag(R.st, &R.st->internal);
       return;
     }
-    const int im = skey_img(R.L, e);
-    const ImgDesc d = R.imgs[im];
-    int ec[3];
-    kidx_coords(d, skey_kidx(R.L, e), ec);
-    uint64_t bnd[4];
-    const int na = apparent_bnd(R, im, d, ec, bnd);
-    if (na > 0) {  // owner: the apparent partner, whose column is its raw boundary
-      if (!work_add(R, W, bnd, (uint32_t)na)) return;
+    const uint64_t e = C.w[0];
+    const uint32_t kidx = skey_kidx(R.L, e);
+    const uint32_t kx = kidx % K2, t1 = kidx / K2;
+    const uint32_t ky = t1 % K1, kz = t1 / K1;
+    if ((e >> (R.L.ib + 32 + R.L.kb)) != 1 || skey_img(R.L, e) != im || kz >= (uint32_t)d.K[0] ||
+        ((kz & 1) + (ky & 1) + (kx & 1)) != 1) {
+      raise_flag(R.st, &R.st->internal);
+      return;
+    }
+    const int ax = (kz & 1) ? 0 : ((ky & 1) ? 1 : 2);
+    const int64_t anchor = pixel_index(d, (int)(kz >> 1), (int)(ky >> 1), (int)(kx >> 1));
+    const int64_t slot = 3 * anchor + ax;
+    const uint8_t code = R.eapp[slot];
+    const uint64_t ow = R.owner[slot];
+    if (code != 0xFF) {  // the apparent partner s of e: its boundary is e and three older edges
+      if (C.n + 2 > (uint32_t)TC) {
+        yield();
+        return;
+      }
+      const int bb = code >> 1;
+      const int sg = (code & 1) ? 1 : -1;
+      const int64_t pax = sel3(ax, ps0, ps1, (int64_t)1), pbb = sel3(bb, ps0, ps1, (int64_t)1);
+      const float v0 = pix_val(R.img, anchor), v1 = pix_val(R.img, anchor + pax);
+      const float w0 = pix_val(R.img, anchor + sg * pbb), w1 = pix_val(R.img, anchor + pax + sg * pbb);
+      const uint32_t kax = sel3(ax, ks0, ks1, 1u);
+      const uint32_t kb = (uint32_t)((int)sel3(bb, ks0, ks1, 1u) * sg);
+      const uint64_t kw = make_skey(R.L, 1, im, ord_of(fmaxf(w0, w1)), kidx + 2 * kb);
+      const uint64_t ka0 = make_skey(R.L, 1, im, ord_of(fmaxf(v0, w0)), kidx - kax + kb);
+      const uint64_t ka1 = make_skey(R.L, 1, im, ord_of(fmaxf(v1, w1)), kidx + kax + kb);
+      if (kw >= e || ka0 >= e || ka1 >= e) {  // e must be the latest facet of s
+        raise_flag(R.st, &R.st->internal);
+        return;
+      }
+      rc_pop(C);
+      rc_xor(C, kw);
+      rc_xor(C, ka0);
+      rc_xor(C, ka1);
+      *adds += 1;
       continue;
     }
-    const int64_t slot = edge_slot(d, ec);
-    const uint64_t ow = R.owner[slot];
     const int32_t o = ow == NO_OWNER ? -1 : (int32_t)(ow >> 32);
-    if (o >= 0 && (uint32_t)o < c) {  // add the column of o
+    if (o >= 0 && (uint32_t)o < c) {  // add the column of o; its top key is e
       const uint64_t* q = R.arena + (uint32_t)ow;
-      if (!work_add(R, W, q + 1, (uint32_t)q[0])) return;
+      const uint32_t m = (uint32_t)q[0] - 1;
+      if (C.n - 1 + m > (uint32_t)TC) {
+        yield();
+        return;
+      }
+      rc_pop(C);
+      for (uint32_t i0 = 0; i0 < m; i0 += 4) {  // four loads in flight, then four inserts
+        uint64_t k[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) k[j] = i0 + j < m ? q[1 + i0 + j] : 0ull;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (i0 + j < m) rc_xor(C, k[j]);
+      }
+      *adds += 1;
       continue;
     }
     if ((uint32_t)o == c) {  // cannot happen: an active column owns nothing
       raise_flag(R.st, &R.st->internal);
       return;
     }
-    store_and_propose(R, W, c, e, slot);
+    const uint64_t off = rc_store(R, C);
+    if (off == ~0ull) return;
+    R.col_ptr[c] = off;
+    R.piv[c] = e;
+    atomicMin(&R.claim[slot], (int32_t)c);
     return;
   }
-  raise_flag(R.st, &R.st->iter_cap);
 }
+
+constexpr int THREAD_CAP = 16;  // keys of a thread-mode column
 
 __global__ void k_fill_count(unsigned long long* c, unsigned long long* work) {
   c[0] = 0;
@@ -299,6 +340,7 @@ __global__ void k_fill_count(unsigned long long* c, unsigned long long* work) {
 
 // Thread-mode round.  Round 0 runs every column that is not cleared; later
 // rounds run the short-column list unless it is short enough for wave mode.
+template <int TC>
 __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __restrict__ list,
                                                    const unsigned long long* __restrict__ n_list, int first,
                                                    uint32_t* __restrict__ long_next,
@@ -307,27 +349,14 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
   const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
   const uint64_t n = first ? R.dim_count[2] : *n_list;
   if (n == 0 || (!first && n <= R.wave_short)) return;
-  const uint64_t gtid = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  Work W;
-  uint64_t* base = R.pbuf + gtid * PBUF_PER_THREAD;
-  W.fbuf[0] = base;
-  W.fbuf[1] = base + FBUF;
-  W.tbuf[0] = base + 2 * FBUF;
-  W.tbuf[1] = base + 2 * FBUF + PCAP;
-  W.adds = 0;
-  W.merged = 0;
-  W.maxlen = 0;
-  for (uint64_t i = gtid; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+  unsigned long long adds = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     if (aborted(R.st)) break;
     const uint32_t c = first ? (uint32_t)i : list[i];
     if (first && R.cleared[c]) continue;
-    reduce_round(R, c, first != 0, off2, W, long_next, n_long_next);
+    reduce_round_reg<TC>(R, c, first != 0, off2, long_next, n_long_next, &adds);
   }
-  if (W.adds) {
-    atomicAdd(&R.st->adds, W.adds);
-    atomicAdd(&R.st->merged, W.merged);
-    atomicMax(&R.st->max_col, W.maxlen);
-  }
+  if (adds) atomicAdd(&R.st->adds, adds);
 }
 
 // ---- wave mode: one wavefront per column -----------------------------------------
@@ -667,17 +696,9 @@ __device__ __forceinline__ void w_pop(WState& W, int where, int lane) {
   else w_tpop(W, lane);
 }
 
-template <typename T>
-__device__ __forceinline__ T sel3(int i, T a, T b, T c) { return i == 0 ? a : (i == 1 ? b : c); }
 __device__ __forceinline__ float rdlane_f(float v, uint32_t i) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)i));
 }
-__device__ __forceinline__ uint32_t ord_of(float v) {
-  uint32_t bits;
-  __builtin_memcpy(&bits, &v, 4);
-  return ord32_bits(bits);
-}
-
 // Reduces column c for one round in wave mode: until its pivot has no owner to
 // its left, then stores it and proposes it for its pivot.
 __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c, uint64_t off2,
@@ -964,7 +985,7 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
                    const unsigned long long* dim_count, const uint8_t* cleared, const uint8_t* eapp,
                    uint64_t* owner, int32_t* claim,
                    uint64_t* piv, uint64_t* col_ptr, uint64_t* arena, uint64_t arena_cap,
-                   unsigned long long* arena_top, unsigned long long* work, uint64_t* pbuf, Status* st) {
+                   unsigned long long* arena_top, unsigned long long* work, Status* st) {
   RedCtx R;
   R.img = img;
   R.imgs = imgs;
@@ -981,12 +1002,11 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.arena_cap = arena_cap;
   R.arena_top = arena_top;
   R.work = work;
-  R.pbuf = pbuf;
   R.st = st;
-  R.long_len = 128;
-  R.yield_iters = 32;
-  R.wave_short = 4096;
-  R.front_cap = 4096;
+  R.long_len = 16;
+  R.yield_iters = 1024;
+  R.wave_short = 65536;
+  R.front_cap = 1024;
   return R;
 }
 
@@ -1001,7 +1021,7 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int per_cu = lds <= 80 * 1024 ? 2 : 1;
+  const int per_cu = (int)(160 * 1024 / lds) < 1 ? 1 : ((int)(160 * 1024 / lds) > 8 ? 8 : (int)(160 * 1024 / lds));
   const int wgrid = ncu * per_cu;
   for (int r = round0; r < round0 + nrounds; ++r) {
     const int cur = r & 1, nxt = (r + 1) & 1;
@@ -1012,7 +1032,7 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
     unsigned long long* ct = counts + 2 * cur;
     unsigned long long* cnx = counts + 2 * nxt;
     k_fill_count<<<1, 1, 0, s>>>(cnx, R.work);
-    k_red_round<<<grid, 256, 0, s>>>(R, lt, ct, first, lists[2 * nxt + 1], cnx + 1);
+    k_red_round<THREAD_CAP><<<grid, 256, 0, s>>>(R, lt, ct, first, lists[2 * nxt + 1], cnx + 1);
     if (!first) k_red_round_wave<<<wgrid, 64 * WPB, lds, s>>>(R, lt, ct, lb, ct + 1);
     k_red_commit<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first, lists[2 * nxt], lists[2 * nxt + 1], cnx);
     k_red_reset<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first);

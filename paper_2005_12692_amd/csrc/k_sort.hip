@@ -1,119 +1,264 @@
 // LSD radix sort of 64-bit keys (key only), 8-bit digits.
 //
 // The number of keys lives in device memory, so the sort can be enqueued before
-// the count is known (and captured in a graph).  The grid is fixed: SORT_G
-// workgroups each own one contiguous chunk of ceil(n / SORT_G) keys.  One pass:
-//   hist    -- per-chunk digit histogram in LDS, written digit-major;
-//   scan    -- one workgroup turns the SORT_G x 256 counts into exclusive offsets;
-//   scatter -- each chunk is walked in rounds of 256 keys in input order; wave64
-//              ballots over the 8 digit bits give every key its rank among the
-//              equal digits of its wavefront, LDS counters chain the wavefronts,
-//              so the pass is stable and the sort is correct.
+// the count is known (and captured in a graph).
+//   hist_all   -- one read of the keys gives the digit histograms of every pass
+//                 (per-block partial counts, reduced by offsets);
+//   offsets    -- per pass, the exclusive start of every digit's bucket;
+// then per digit position, over tiles of 4096 keys:
+//   count      -- per tile and digit, the number of keys;
+//   scan_tiles -- per digit, those counts become the global position of each
+//                 tile's first key of that digit;
+//   scatter    -- each tile is ranked by digit with wavefront ballots (stable:
+//                 wavefront, step, then lane order), sorted by digit in LDS and
+//                 written out in runs of equal digits, so the stores are
+//                 contiguous.
 #include "cr_internal.h"
 
 namespace cr {
 
-constexpr int SORT_G = 1024;
-constexpr int SORT_T = 256;
+constexpr int ST = 256;               // threads of a pass workgroup
+constexpr int SKEYS = 16;             // keys per thread per tile
+constexpr int STILE = ST * SKEYS;     // keys per tile
+constexpr int SWAVES = ST / 64;
+constexpr int HB = 512;               // workgroups of the histogram kernel
+constexpr int SGRID = 1024;           // persistent workgroups of a pass
+constexpr int MAX_PASSES = 8;
 
-__global__ __launch_bounds__(SORT_T) void k_sort_hist(const uint64_t* __restrict__ keys,
-                                                      const unsigned long long* __restrict__ n_ptr,
-                                                      uint64_t cap, int shift, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[256];
-  const int tid = threadIdx.x, b = blockIdx.x;
-  h[tid] = 0;
-  __syncthreads();
-  const uint64_t n = *n_ptr < cap ? *n_ptr : cap;
-  const uint64_t chunk = (n + SORT_G - 1) / SORT_G;
-  const uint64_t lo = (uint64_t)b * chunk;
-  const uint64_t hi = lo + chunk < n ? lo + chunk : n;
-  for (uint64_t i = lo + tid; i < hi; i += SORT_T) atomicAdd(&h[(keys[i] >> shift) & 255], 1u);
-  __syncthreads();
-  hist[tid * SORT_G + b] = h[tid];
+__device__ __forceinline__ uint64_t n_keys(const unsigned long long* n_ptr, uint64_t cap) {
+  return *n_ptr < cap ? *n_ptr : cap;
 }
 
-// Exclusive scan of SORT_G*256 counts, in place, by one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* __restrict__ hist) {
-  constexpr int TOTAL = SORT_G * 256;
-  constexpr int PER = TOTAL / 1024;
-  __shared__ uint32_t part[1024];
-  const int tid = threadIdx.x;
-  uint32_t* seg = hist + (size_t)tid * PER;
-  uint32_t s = 0;
-  for (int i = 0; i < PER; ++i) s += seg[i];
-  part[tid] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t v = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  uint32_t run = part[tid] - s;
-  for (int i = 0; i < PER; ++i) {
-    uint32_t c = seg[i];
-    seg[i] = run;
-    run += c;
-  }
-}
-
-__global__ __launch_bounds__(SORT_T) void k_sort_scatter(const uint64_t* __restrict__ in,
-                                                         uint64_t* __restrict__ out,
-                                                         const unsigned long long* __restrict__ n_ptr,
-                                                         uint64_t cap, int shift, const uint32_t* __restrict__ hist) {
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[SORT_T / 64][256];
+__global__ __launch_bounds__(ST) void k_sort_hist_all(const uint64_t* __restrict__ keys,
+                                                      const unsigned long long* __restrict__ n_ptr, uint64_t cap,
+                                                      int passes, uint32_t* __restrict__ part) {
+  __shared__ uint32_t h[MAX_PASSES][256];
   const int tid = threadIdx.x, b = blockIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  base[tid] = hist[tid * SORT_G + b];
-  const uint64_t n = *n_ptr < cap ? *n_ptr : cap;
-  const uint64_t chunk = (n + SORT_G - 1) / SORT_G;
+  for (int p = 0; p < MAX_PASSES; ++p) h[p][tid] = 0;
+  __syncthreads();
+  const uint64_t n = n_keys(n_ptr, cap);
+  const uint64_t chunk = (n + HB - 1) / HB;
   const uint64_t lo = (uint64_t)b * chunk;
   const uint64_t hi = lo + chunk < n ? lo + chunk : n;
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (uint64_t start = lo; start < hi; start += SORT_T) {
-    const uint64_t i = start + tid;
-    const bool valid = i < hi;
-    const uint64_t key = valid ? in[i] : 0;
-    const uint32_t dig = (uint32_t)(key >> shift) & 255;
-    for (int w = 0; w < SORT_T / 64; ++w) wcnt[w][tid] = 0;
-    __syncthreads();
+  for (uint64_t i = lo + tid; i < hi; i += ST) {
+    const uint64_t k = keys[i];
+    for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255], 1u);
+  }
+  __syncthreads();
+  for (int p = 0; p < passes; ++p) part[((size_t)p * 256 + tid) * HB + b] = h[p][tid];
+}
+
+// offs[p * 256 + d] = number of keys whose digit p is below d.  One workgroup per pass.
+__global__ __launch_bounds__(256) void k_sort_offsets(const uint32_t* __restrict__ part, uint32_t* __restrict__ offs) {
+  __shared__ uint32_t wsum[4];
+  const int p = blockIdx.x, d = threadIdx.x, lane = d & 63, w = d >> 6;
+  const uint32_t* src = part + ((size_t)p * 256 + d) * HB;
+  uint32_t tot = 0;
+  for (int b = 0; b < HB; ++b) tot += src[b];
+  uint32_t incl = tot;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t up = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += up;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int i = 0; i < w; ++i) before += wsum[i];
+  offs[p * 256 + d] = before + incl - tot;
+}
+
+// Ranks the keys of one tile by digit: wavefront w takes keys [w*1024, (w+1)*1024)
+// of the tile, 64 per step; rank[j] = number of earlier keys of the same digit
+// among this wavefront's keys; S.cnt[w][d] ends as the wavefront's count of d.
+struct SortLds {
+  uint64_t sk[STILE];         // the tile, sorted by digit
+  uint32_t cnt[SWAVES][256];  // per-wavefront digit counts, then their exclusive offsets
+  uint32_t tdig[256];         // exclusive start of each digit in the sorted tile
+  uint32_t gpos[256];         // global position of the tile's first key of each digit
+  uint32_t wsum[SWAVES];
+};
+
+__device__ __forceinline__ void rank_tile(SortLds& S, const uint64_t* __restrict__ in, uint64_t t0, uint32_t tcount,
+                                          int shift, uint64_t key[SKEYS], uint32_t rank[SKEYS]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+#pragma unroll
+  for (int j = 0; j < SKEYS; ++j) {
+    const uint32_t li = (uint32_t)(w * (SKEYS * 64) + j * 64 + lane);
+    key[j] = li < tcount ? in[t0 + li] : 0ull;
+  }
+#pragma unroll
+  for (int j = 0; j < SKEYS; ++j) {
+    const uint32_t li = (uint32_t)(w * (SKEYS * 64) + j * 64 + lane);
+    const bool valid = li < tcount;
+    const uint32_t dig = (uint32_t)(key[j] >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
-      const bool on = (dig >> bit) & 1;
+      const bool on = (dig >> bit) & 1u;
       const uint64_t m = __ballot(on);
       peers &= on ? m : ~m;
     }
-    const uint32_t rank = __popcll(peers & lt_mask);
-    if (valid && rank == 0) wcnt[wave][dig] = __popcll(peers);
+    const uint32_t r = (uint32_t)__popcll(peers & lt);
+    const uint32_t base = valid ? S.cnt[w][dig] : 0u;
+    rank[j] = base + r;
+    if (valid && r == 0) S.cnt[w][dig] = base + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Per tile and digit: the number of keys, stored digit-major: counts[d * ntiles + tile].
+__global__ __launch_bounds__(ST) void k_sort_count(const uint64_t* __restrict__ in,
+                                                   const unsigned long long* __restrict__ n_ptr, uint64_t cap,
+                                                   int shift, uint32_t* __restrict__ counts) {
+  __shared__ SortLds S;
+  const int tid = threadIdx.x;
+  const uint64_t n = n_keys(n_ptr, cap);
+  const uint64_t ntiles = (n + STILE - 1) / STILE;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int i = 0; i < SWAVES; ++i) S.cnt[i][tid] = 0;
     __syncthreads();
-    {  // per digit: chain the wavefronts, advance the running base
-      uint32_t run = base[tid];
-      for (int w = 0; w < SORT_T / 64; ++w) {
-        const uint32_t c = wcnt[w][tid];
-        wcnt[w][tid] = run;
-        run += c;
-      }
-      base[tid] = run;
-    }
+    const uint64_t t0 = tile * STILE;
+    const uint32_t tcount = (uint32_t)(n - t0 < (uint64_t)STILE ? n - t0 : (uint64_t)STILE);
+    uint64_t key[SKEYS];
+    uint32_t rank[SKEYS];
+    rank_tile(S, in, t0, tcount, shift, key, rank);
     __syncthreads();
-    if (valid) out[wcnt[wave][dig] + rank] = key;
+    uint32_t tot = 0;
+    for (int i = 0; i < SWAVES; ++i) tot += S.cnt[i][tid];
+    counts[(uint64_t)tid * ntiles + tile] = tot;
     __syncthreads();
   }
+}
+
+// Per digit d (one workgroup each): counts[d * ntiles + t] becomes the global
+// position of tile t's first key of digit d (offs[d] plus the earlier tiles).
+__global__ __launch_bounds__(256) void k_sort_scan_tiles(uint32_t* __restrict__ counts,
+                                                         const unsigned long long* __restrict__ n_ptr, uint64_t cap,
+                                                         const uint32_t* __restrict__ offs) {
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t carry_s;
+  const int d = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint64_t n = n_keys(n_ptr, cap);
+  const uint64_t ntiles = (n + STILE - 1) / STILE;
+  uint32_t* col = counts + (uint64_t)d * ntiles;
+  if (tid == 0) carry_s = offs[d];
+  __syncthreads();
+  constexpr int PER = 8;
+  for (uint64_t base = 0; base < ntiles; base += 256 * PER) {
+    uint32_t v[PER];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const uint64_t i = base + (uint64_t)tid * PER + k;
+      v[k] = i < ntiles ? col[i] : 0u;
+      sum += v[k];
+    }
+    uint32_t incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t up = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += up;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t run = carry_s + incl - sum;
+    for (int i = 0; i < w; ++i) run += wsum[i];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const uint64_t i = base + (uint64_t)tid * PER + k;
+      if (i < ntiles) col[i] = run;
+      run += v[k];
+    }
+    __syncthreads();
+    if (tid == 255) carry_s = run;
+    __syncthreads();
+  }
+}
+
+// One pass: each tile is ranked again, sorted by digit in LDS and written out
+// in runs of equal digits at the positions from k_sort_scan_tiles.
+__global__ __launch_bounds__(ST) void k_sort_scatter(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+                                                     const unsigned long long* __restrict__ n_ptr, uint64_t cap,
+                                                     int shift, const uint32_t* __restrict__ pos) {
+  __shared__ SortLds S;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint64_t n = n_keys(n_ptr, cap);
+  const uint64_t ntiles = (n + STILE - 1) / STILE;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int i = 0; i < SWAVES; ++i) S.cnt[i][tid] = 0;
+    __syncthreads();
+    const uint64_t t0 = tile * STILE;
+    const uint32_t tcount = (uint32_t)(n - t0 < (uint64_t)STILE ? n - t0 : (uint64_t)STILE);
+    uint64_t key[SKEYS];
+    uint32_t rank[SKEYS];
+    rank_tile(S, in, t0, tcount, shift, key, rank);
+    __syncthreads();
+    // per digit: wavefront offsets, tile total, tile-wide exclusive start
+    const int d = tid;
+    uint32_t tot = 0;
+    for (int i = 0; i < SWAVES; ++i) {
+      const uint32_t c = S.cnt[i][d];
+      S.cnt[i][d] = tot;
+      tot += c;
+    }
+    uint32_t incl = tot;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t up = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += up;
+    }
+    if (lane == 63) S.wsum[w] = incl;
+    S.gpos[d] = pos[(uint64_t)d * ntiles + tile];
+    __syncthreads();
+    uint32_t before = 0;
+    for (int i = 0; i < w; ++i) before += S.wsum[i];
+    S.tdig[d] = before + incl - tot;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SKEYS; ++j) {
+      const uint32_t li = (uint32_t)(w * (SKEYS * 64) + j * 64 + lane);
+      if (li < tcount) {
+        const uint32_t dig = (uint32_t)(key[j] >> shift) & 255u;
+        S.sk[S.tdig[dig] + S.cnt[w][dig] + rank[j]] = key[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < SKEYS; ++m) {
+      const uint32_t i = (uint32_t)(tid + m * ST);
+      if (i < tcount) {
+        const uint64_t k = S.sk[i];
+        const uint32_t dig = (uint32_t)(k >> shift) & 255u;
+        out[(uint64_t)S.gpos[dig] + (i - S.tdig[dig])] = k;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Scratch of launch_sort: partial histograms, digit offsets, per-tile counts.
+size_t sort_scratch_bytes(uint64_t cap) {
+  const uint64_t tiles = (cap + STILE - 1) / STILE + 1;
+  return 4ull * MAX_PASSES * 256 * HB + 4ull * MAX_PASSES * 256 + 4ull * tiles * 256 + 256;
 }
 
 // Sorts keys[0..min(*n, cap)) ascending on bits [0, bits); tmp is scratch of the same
 // size.  Returns the buffer (keys or tmp) that holds the result.
 uint64_t* launch_sort(uint64_t* keys, uint64_t* tmp, const unsigned long long* n_ptr, uint64_t cap, int bits,
-                      uint32_t* hist, hipStream_t stream) {
+                      void* scratch, hipStream_t stream) {
   const int passes = (bits + 7) / 8;
+  uint32_t* part = static_cast<uint32_t*>(scratch);
+  uint32_t* offs = part + (size_t)MAX_PASSES * 256 * HB;
+  uint32_t* counts = offs + MAX_PASSES * 256 + 64;
+  const uint64_t max_tiles = (cap + STILE - 1) / STILE;
+  const int grid = (int)(max_tiles < (uint64_t)SGRID ? (max_tiles ? max_tiles : 1) : (uint64_t)SGRID);
+  k_sort_hist_all<<<HB, ST, 0, stream>>>(keys, n_ptr, cap, passes, part);
+  k_sort_offsets<<<passes, 256, 0, stream>>>(part, offs);
   uint64_t* a = keys;
   uint64_t* b = tmp;
   for (int p = 0; p < passes; ++p) {
-    k_sort_hist<<<SORT_G, SORT_T, 0, stream>>>(a, n_ptr, cap, 8 * p, hist);
-    k_sort_scan<<<1, 1024, 0, stream>>>(hist);
-    k_sort_scatter<<<SORT_G, SORT_T, 0, stream>>>(a, b, n_ptr, cap, 8 * p, hist);
+    k_sort_count<<<grid, ST, 0, stream>>>(a, n_ptr, cap, 8 * p, counts);
+    k_sort_scan_tiles<<<256, 256, 0, stream>>>(counts, n_ptr, cap, offs + p * 256);
+    k_sort_scatter<<<grid, ST, 0, stream>>>(a, b, n_ptr, cap, 8 * p, counts);
     uint64_t* t = a;
     a = b;
     b = t;
