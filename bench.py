@@ -50,6 +50,33 @@ def stencil_bytes(shape, survivors_total: int) -> int:
     return 4 * P + 8 * survivors_total + 4 * P + 4 * C
 
 
+def sort_bytes(n_keys: int, bits: int) -> int:
+    """Algorithmic bytes of the sort of the surviving cells: every 8-bit pass
+    reads and writes each 64-bit key once (16 B)."""
+    return 16 * n_keys * ((bits + 7) // 8)
+
+
+def profiled_traffic(kernel_md: str):
+    """HBM bytes per launch measured by the profiler (FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy's counts) as recorded in profiles/<kernel_md>, or None
+    when the kernel's source no longer has the digest the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", kernel_md)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("    "):
+            k, v = line.strip().split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = os.path.join(ROOT, fields.get("source", ""))
+    if "traffic_bytes" not in fields or not os.path.isfile(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("source_sha256"):
+        return None
+    return int(fields["traffic_bytes"])
+
+
 def copy_ceiling(nbytes: int = 1 << 28, reps: int = 5) -> float:
     """GB/s (read + write) of a device-to-device copy of nbytes: the practical
     HBM ceiling the stencil is compared with."""
@@ -227,6 +254,9 @@ def main():
     surv = int(sum(st["survivors"]))
     nbytes = stencil_bytes((n, n, n), surv)
     achieved = nbytes / (stages["stencil"] * 1e-3) / 1e9
+    sort_bits = 2 + 32 + (((2 * n - 1) ** 3) - 1).bit_length()
+    sbytes = sort_bytes(surv, sort_bits)
+    s_achieved = sbytes / (stages["sort_cells"] * 1e-3) / 1e9
     rows = int(d.dim.shape[0])
     line = {
         "metric": "PH cells/s (3D 256^3, degrees 0-2)",
@@ -244,9 +274,17 @@ def main():
         "config": {"workload": "3D 256^3 float32: 200 Gaussian blobs + U[-0.05,0.05) noise, seed 2; "
                                "H0+H1+H2, plain per-volume call",
                    "cells": cells, "pixels": n ** 3},
-        "roofline": {"bound": "hbm", "kernel": "k_apparent (stencil)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes": nbytes},
+        "roofline": {"bound": "hbm", "kernel": "k_stencil (filtration + apparent pairs + compaction)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic("k_stencil_256cube_traffic.md"),
+                     "algorithmic_bytes": nbytes, "ms": stages["stencil"]},
+        "roofline_sort": {"bound": "hbm", "kernel": "cell sort, %d 8-bit passes (count + scan + scatter)"
+                          % ((sort_bits + 7) // 8), "achieved": s_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": s_achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": sbytes,
+                          "ms": stages["sort_cells"]},
+        "latency_bound": {"stage": "degree 1 (boundary reduction)", "ms": stages["degree1"],
+                          "share": stages["degree1"] / ms,
+                          "note": "dependent-load chains of the long columns; no bandwidth roofline applies"},
         "stages_ms": stages,
         "survivors": st["survivors"],
         "rows": rows,
