@@ -181,7 +181,7 @@ typedef struct cr_tuning {
   int32_t yield_iters;  /* ... a column reduced one per thread moves to a wavefront after this
                            many additions (>= 1) */
   int32_t wave_short;   /* ... a list of at most this many short columns is run one per wavefront */
-  int32_t front_cap;    /* ... keys of a wavefront's LDS front list, 128 .. 4096 */
+  int32_t front_cap;    /* ... keys of a wavefront's LDS front list, 128 .. 4032 */
 } cr_tuning;
 
 /* The parameters the context uses for ndim (2 or 3), and a validated setter

@@ -434,6 +434,8 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
   // their buffer is the scratch of this sort.
   *cand_out = launch_sort(cand, skeys, &cnt[C_CAND], p.surv_cap, L.ib + 2 + 2 * L.pb, hist, s);
   mark(ctx, EV_ROWS, s);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(CR_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return CR_OK;
 }
 
@@ -939,7 +941,7 @@ cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed
     std::vector<int> vals;
     if (coord == 0) for (int v = 0; v < N_TILE_VARIANTS; ++v) vals.push_back(v);
     if (coord == 1) vals = {512, 1024, 2048, 4096, 8192};
-    if (coord == 2) vals = {512, 1024, 2048, 4096};
+    if (coord == 2) vals = {512, 1024, 2048, 4032};
     if (coord == 3) vals = {4, 8, 16};
     if (coord == 4) vals = {0, 4096, 65536, 1 << 30};
     if (coord == 5) vals = {16, 128, 1024};

@@ -376,13 +376,15 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
 // merges: PER positions per lane, equal pairs dropped, never split between
 // lanes.  Every step is wave-synchronous: no workgroup barriers.
 constexpr int WPB = 2;                 // wavefronts per workgroup
-constexpr uint32_t XN = 1024;          // addend stage / two merge tiles
-constexpr int PER = 8;                 // merge positions per lane per chunk of a tiled (global) merge
-constexpr uint32_t CHUNK = 64 * PER;   // merge positions per tile chunk (= one tile)
-constexpr int PER_WIDE = 16;           // ... of a long LDS merge
+constexpr int PER = 8;                 // merge positions per lane per step of a merge with the tail
+constexpr uint32_t CHUNK = 64 * PER;   // keys per chunk of the tail ring
+constexpr uint32_t RING = 4;           // chunks of the tail ring (two in use, one arriving, one spare)
+constexpr uint32_t XN = RING * CHUNK;  // the stage: tail ring, or an owner column being added
+constexpr int PER_WIDE = 16;           // merge positions per lane per step of a long LDS merge
 constexpr int PER_NARROW = 2;          // ... of a merge of at most 128 keys
 constexpr uint64_t KEY_INF = ~0ull;    // above every key
-static_assert(2 * CHUNK <= XN, "two merge tiles must fit the stage");
+static_assert((XN & (XN - 1)) == 0, "the tail ring is indexed with a mask");
+static_assert(WPB * 8 * (2 * FRONT_CAP_MAX + XN + 64) <= 160 * 1024, "wave-mode LDS exceeds a workgroup's share");
 
 __host__ __device__ __forceinline__ size_t wave_lds_words(uint32_t front_cap) { return 2 * (size_t)front_cap + XN + 64; }
 
@@ -415,6 +417,12 @@ __device__ __forceinline__ void wsync_global() {
   __builtin_amdgcn_wave_barrier();
 }
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+// Wave-uniform 64-bit value kept in scalar registers (so branches on it are scalar).
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
 __device__ __forceinline__ uint64_t rdlane64(uint64_t v, uint32_t i) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)i);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), (int)i);
@@ -436,9 +444,22 @@ __device__ __forceinline__ uint32_t w_excl_small(uint32_t v, uint32_t* total) {
   return pre;
 }
 
+// A sorted list seen through an index map: a plain LDS array, or a window of
+// the tail ring (key i of the window is ring slot (base + i) mod XN).
+struct Lin {
+  const uint64_t* p;
+  __device__ __forceinline__ uint64_t operator[](uint32_t i) const { return p[i]; }
+};
+struct Ring {
+  const uint64_t* p;
+  uint32_t base;
+  __device__ __forceinline__ uint64_t operator[](uint32_t i) const { return p[(base + i) & (XN - 1)]; }
+};
+
 // Number of A elements among the first d positions of the merge of A and B,
 // ties taken from A first.
-__device__ __forceinline__ uint32_t mp_split(const uint64_t* A, uint32_t na, const uint64_t* B, uint32_t nb, uint32_t d) {
+template <class AA, class BB>
+__device__ __forceinline__ uint32_t mp_split(const AA& A, uint32_t na, const BB& B, uint32_t nb, uint32_t d) {
   uint32_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
   while (lo < hi) {
     const uint32_t m = (lo + hi) >> 1;
@@ -457,8 +478,8 @@ __device__ __forceinline__ uint32_t mp_split(const uint64_t* A, uint32_t na, con
 struct SegResult {
   uint32_t written, ka, kb;
 };
-template <int P>
-__device__ __forceinline__ SegResult w_merge_seg(const uint64_t* A, uint32_t na, const uint64_t* B, uint32_t nb,
+template <int P, class AA, class BB>
+__device__ __forceinline__ SegResult w_merge_seg(const AA& A, uint32_t na, const BB& B, uint32_t nb,
                                                  uint32_t d, uint64_t* out, int lane) {
   const uint32_t dend = (uint32_t)(lane + 1) * P < d ? (uint32_t)(lane + 1) * P : d;
   const uint32_t ie = mp_split(A, na, B, nb, dend);
@@ -514,8 +535,8 @@ __device__ __noinline__ uint32_t w_xor_lds(const uint64_t* A, uint32_t na, const
   uint32_t ia = 0, ib = 0, o = 0;
   while (ia < na || ib < nb) {
     const uint32_t rem = (na - ia) + (nb - ib);
-    const SegResult r =
-        w_merge_seg<P>(A + ia, na - ia, B + ib, nb - ib, rem < 64u * P ? rem : 64u * P, out + o, lane);
+    const SegResult r = w_merge_seg<P>(Lin{A + ia}, na - ia, Lin{B + ib}, nb - ib, rem < 64u * P ? rem : 64u * P,
+                                       out + o, lane);
     o += r.written;
     ia += r.ka;
     ib += r.kb;
@@ -524,29 +545,51 @@ __device__ __noinline__ uint32_t w_xor_lds(const uint64_t* A, uint32_t na, const
   return o;
 }
 
-// out (arena) = A XOR B; each of A and B is in LDS (a_lds / b_lds) or in global
-// memory, in which case it is read through a tile in the stage.
-__device__ __noinline__ uint32_t w_xor_glob(uint64_t* X, const uint64_t* A, uint32_t na, bool a_lds,
-                                            const uint64_t* B, uint32_t nb, bool b_lds, uint64_t* out, int lane) {
+// out (arena) = T XOR F, T in the arena, F in LDS.  T is read through a ring
+// of RING chunks in the stage: the chunks holding the next CHUNK keys are
+// resident, and the chunk after them is loaded into registers during each
+// merge step and stored into the ring when it is needed, so the load latency
+// overlaps the merging.
+__device__ __noinline__ uint32_t w_merge_tail(uint64_t* X, const uint64_t* T, uint32_t nt, const uint64_t* F,
+                                              uint32_t nf, uint64_t* out, int lane) {
+  const uint32_t nch = (nt + CHUNK - 1) / CHUNK;
+  uint64_t pre[PER];
+  auto load_chunk = [&](uint32_t c) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const uint32_t i = c * CHUNK + (uint32_t)(j * 64 + lane);
+      pre[j] = (c < nch && i < nt) ? T[i] : 0ull;
+    }
+  };
+  auto store_chunk = [&](uint32_t c) {
+    uint64_t* slot = X + (c % RING) * CHUNK;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) slot[j * 64 + lane] = pre[j];
+  };
+  load_chunk(0);
+  store_chunk(0);
+  load_chunk(1);
+  store_chunk(1);
+  uint32_t next = 2;  // the chunk in flight in pre[]
+  load_chunk(next);
+  wsync();
   uint32_t ia = 0, ib = 0, o = 0;
-  while (ia < na || ib < nb) {
-    const uint32_t la = na - ia < CHUNK ? na - ia : CHUNK;
-    const uint32_t lb = nb - ib < CHUNK ? nb - ib : CHUNK;
-    const uint64_t* tA = A + ia;
-    const uint64_t* tB = B + ib;
-    if (!a_lds) {
-      for (uint32_t t = lane; t < la; t += 64) X[t] = A[ia + t];
-      tA = X;
-    }
-    if (!b_lds) {
-      for (uint32_t t = lane; t < lb; t += 64) X[CHUNK + t] = B[ib + t];
-      tB = X + CHUNK;
-    }
-    wsync();
-    const SegResult r = w_merge_seg<PER>(tA, la, tB, lb, la + lb < CHUNK ? la + lb : CHUNK, out + o, lane);
+  while (ia < nt || ib < nf) {
+    const uint32_t la = nt - ia < CHUNK ? nt - ia : CHUNK;
+    const uint32_t lb = nf - ib < CHUNK ? nf - ib : CHUNK;
+    const SegResult r = w_merge_seg<PER>(Ring{X, ia}, la, Lin{F + ib}, lb, la + lb < CHUNK ? la + lb : CHUNK, out + o,
+                                         lane);
     o += r.written;
     ia += r.ka;
     ib += r.kb;
+    // the next step reads chunks ia / CHUNK and the one after; the ring slot of
+    // the arriving chunk last held a chunk below ia / CHUNK
+    if (next < nch && next <= ia / CHUNK + 1) {
+      wsync();
+      store_chunk(next);
+      ++next;
+      load_chunk(next);
+    }
     wsync();
   }
   wsync_global();
@@ -557,7 +600,7 @@ __device__ __noinline__ uint32_t w_xor_glob(uint64_t* X, const uint64_t* A, uint
 __device__ __forceinline__ uint64_t w_alloc(const RedCtx& R, uint64_t n, int lane) {
   unsigned long long off = 0;
   if (lane == 0) off = arena_alloc(R, n ? n : 1);
-  return __shfl(off, 0, 64);
+  return rdlane64(off, 0);
 }
 
 __device__ __forceinline__ void w_twin_load(WState& W, int lane) {
@@ -579,20 +622,9 @@ __device__ __forceinline__ bool w_push_front(const RedCtx& R, const WaveBufs& S,
   if (W.nf == 0) return true;
   const uint64_t off = w_alloc(R, (uint64_t)W.nt + W.nf, lane);
   if (off == ~0ull) return false;
-  const uint32_t len = w_xor_glob(S.X, W.T, W.nt, false, fbuf(S, W.cur), W.nf, true, R.arena + off, lane);
+  const uint32_t len = uni(w_merge_tail(S.X, W.T, W.nt, fbuf(S, W.cur), W.nf, R.arena + off, lane));
   W.merged += W.nt + W.nf;
   W.nf = 0;
-  w_set_tail(W, R.arena + off, len, lane);
-  return true;
-}
-
-// T ^= B for a list B in global memory.
-__device__ __forceinline__ bool w_tail_add(const RedCtx& R, const WaveBufs& S, WState& W, const uint64_t* b, uint32_t nb,
-                           int lane) {
-  const uint64_t off = w_alloc(R, (uint64_t)W.nt + nb, lane);
-  if (off == ~0ull) return false;
-  const uint32_t len = w_xor_glob(S.X, W.T, W.nt, false, b, nb, false, R.arena + off, lane);
-  W.merged += W.nt + nb;
   w_set_tail(W, R.arena + off, len, lane);
   return true;
 }
@@ -602,7 +634,7 @@ __device__ __forceinline__ bool w_front_add(const RedCtx& R, const WaveBufs& S, 
                             int lane) {
   if (W.nf + m > S.cap && !w_push_front(R, S, W, lane)) return false;
   W.merged += W.nf + m;
-  W.nf = w_xor_lds<PER_WIDE>(fbuf(S, W.cur), W.nf, X, m, fbuf(S, W.cur ^ 1), lane);
+  W.nf = uni(w_xor_lds<PER_WIDE>(fbuf(S, W.cur), W.nf, X, m, fbuf(S, W.cur ^ 1), lane));
   W.cur ^= 1;
   return true;
 }
@@ -656,7 +688,7 @@ __device__ __forceinline__ void w_p_add(const WaveBufs& S, WState& W, const uint
   if ((uint32_t)lane < W.np) S.ps[lane] = W.p;
   wsync();
   uint64_t* out = fbuf(S, W.cur ^ 1);
-  const uint32_t n = w_xor_lds<PER_NARROW>(S.ps, W.np, X, m, out, lane);
+  const uint32_t n = uni(w_xor_lds<PER_NARROW>(S.ps, W.np, X, m, out, lane));
   W.merged += W.np + m;
   W.p = (uint32_t)lane < n ? out[lane] : 0;
   W.np = n;
@@ -669,7 +701,7 @@ __device__ __forceinline__ void w_p_add(const WaveBufs& S, WState& W, const uint
 __device__ __forceinline__ uint64_t w_pivot(const WaveBufs& S, WState& W, int lane, int* where) {
   for (;;) {
     const uint64_t a = W.np ? rdlane64(W.p, W.np - 1) : 0;
-    const uint64_t b = W.nf ? fbuf(S, W.cur)[W.nf - 1] : 0;
+    const uint64_t b = W.nf ? uni64(fbuf(S, W.cur)[W.nf - 1]) : 0;
     const uint64_t c = W.nt ? rdlane64(W.tw, W.nt - 1 - W.tb) : 0;
     uint64_t m = a > b ? a : b;
     m = m > c ? m : c;
@@ -703,14 +735,20 @@ __device__ __forceinline__ float rdlane_f(float v, uint32_t i) {
 // its left, then stores it and proposes it for its pivot.
 __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c, uint64_t off2,
                                    int lane) {
-  const int im = skey_img(R.L, R.skeys[off2 + c]);  // every edge of the column lies in this image
-  const ImgDesc d = R.imgs[im];
+  const int im = (int)uni((uint32_t)skey_img(R.L, uni64(R.skeys[off2 + c])));  // every edge lies in this image
+  ImgDesc d = R.imgs[im];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    d.n[a] = (int32_t)uni((uint32_t)d.n[a]);
+    d.K[a] = (int32_t)uni((uint32_t)d.K[a]);
+  }
+  d.pix_off = (int64_t)uni64((uint64_t)d.pix_off);
   const uint32_t K1 = (uint32_t)d.K[1], K2 = (uint32_t)d.K[2];
   const int64_t ps0 = (int64_t)d.n[1] * d.n[2], ps1 = d.n[2];
   const uint32_t ks0 = K1 * K2, ks1 = K2;
   {
-    const uint64_t off = R.col_ptr[c];
-    const uint32_t len = (uint32_t)R.arena[off];
+    const uint64_t off = uni64(R.col_ptr[c]);
+    const uint32_t len = uni((uint32_t)R.arena[off]);
     const uint64_t* src = R.arena + off + 1;
     W.np = 0;
     W.cur = 0;
@@ -807,15 +845,18 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
         if (lane >= 1 && (uint32_t)lane <= m) S.X[lane - 1] = head;
         wsync();
         w_p_add(S, W, S.X, m, lane);
-      } else if (m <= XN && m <= S.cap) {
-        // make room first: pushing F into T uses the stage for its tiles
-        if (W.nf + m > S.cap && !w_push_front(R, S, W, lane)) return;
-        if (lane >= 1 && (uint32_t)lane <= m) S.X[lane - 1] = head;
-        for (uint32_t i = 63 + lane; i < m; i += 64) S.X[i] = q[1 + i];
-        wsync();
-        if (!w_front_add(R, S, W, S.X, m, lane)) return;
       } else {
-        if (!w_tail_add(R, S, W, q + 1, m, lane)) return;
+        // into F, in pieces that fit the stage and F; room is made first, since
+        // pushing F into T uses the stage as its ring
+        const uint32_t pmax = XN < S.cap ? XN : S.cap;
+        for (uint32_t base = 0; base < m; base += pmax) {
+          const uint32_t piece = m - base < pmax ? m - base : pmax;
+          if (W.nf + piece > S.cap && !w_push_front(R, S, W, lane)) return;
+          if (base == 0 && lane >= 1 && (uint32_t)lane <= piece) S.X[lane - 1] = head;
+          for (uint32_t i = (base == 0 ? 63u : 0u) + lane; i < piece; i += 64) S.X[i] = q[1 + base + i];
+          wsync();
+          if (!w_front_add(R, S, W, S.X, piece, lane)) return;
+        }
       }
       continue;
     }
@@ -832,7 +873,7 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
       for (uint32_t i = lane; i < W.nf; i += 64) R.arena[off + 1 + i] = fbuf(S, W.cur)[i];
       len = W.nf;
     } else {
-      len = w_xor_glob(S.X, W.T, W.nt, false, fbuf(S, W.cur), W.nf, true, R.arena + off + 1, lane);
+      len = uni(w_merge_tail(S.X, W.T, W.nt, fbuf(S, W.cur), W.nf, R.arena + off + 1, lane));
     }
     if (lane == 0) {
       R.arena[off] = len;
@@ -860,7 +901,7 @@ __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uin
   S.F1 = base + S.cap;
   S.X = base + 2 * (size_t)S.cap;
   S.ps = S.X + XN;
-  const uint64_t nl = *n_l, ns0 = *n_s;
+  const uint64_t nl = uni64(*n_l), ns0 = uni64(*n_s);
   const uint64_t ns = ns0 <= R.wave_short ? ns0 : 0;
   const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
   WState W;
@@ -869,9 +910,9 @@ __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uin
   for (;;) {
     unsigned long long li = 0;
     if (lane == 0) li = atomicAdd(R.work, 1ull);
-    li = __shfl(li, 0, 64);
+    li = rdlane64(li, 0);
     if (li >= nl + ns || aborted(R.st)) break;
-    const uint32_t c = li < nl ? list_l[li] : list_s[li - nl];
+    const uint32_t c = uni(li < nl ? list_l[li] : list_s[li - nl]);
     reduce_column_wave(R, S, W, c, off2, lane);
     wsync();
   }

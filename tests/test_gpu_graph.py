@@ -100,7 +100,7 @@ def test_every_tuning_gives_the_same_bytes(ndim):
 
 def test_set_tuning_rejects_out_of_range():
     default = cr.get_tuning(3)
-    for kw in (dict(tile=99), dict(grid=1), dict(front_cap=64), dict(front_cap=100000), dict(yield_iters=0)):
+    for kw in (dict(tile=99), dict(grid=1), dict(front_cap=64), dict(front_cap=4096), dict(yield_iters=0)):
         with pytest.raises(cr.CRError) as e:
             cr.set_tuning(3, **kw)
         assert e.value.code == cr.CR_ERR_INVALID_ARGUMENT

@@ -165,8 +165,8 @@ WAVE_ENV = ("CR_LONG_LEN", "CR_YIELD_ITERS", "CR_WAVE_SHORT", "CR_FRONT_CAP")
 
 
 @pytest.mark.parametrize("setting", [
-    ("0", "2", "0", "4096"),        # every column to wave mode after two additions
-    ("8", "8", "0", "4096"),
+    ("0", "2", "0", "4032"),        # every column to wave mode after two additions
+    ("8", "8", "0", "4032"),
     ("0", "1", "1000000", "128"),   # whole rounds in wave mode, tiny front list: tail merges
     ("4", "4", "64", "200"),
 ])
