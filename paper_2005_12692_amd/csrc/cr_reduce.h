@@ -29,6 +29,7 @@ struct RedCtx {
   uint32_t yield_iters;    // thread mode hands a column to wave mode after this many additions
   uint32_t wave_short;     // a short list of at most this many columns is run in wave mode too
   uint32_t front_cap;      // keys of the wave-mode LDS front list
+  uint32_t mid_cap;        // the wave-mode middle list is folded into the tail beyond this many keys
 };
 constexpr uint64_t NO_OWNER = ~0ull;
 constexpr uint64_t ARENA_SLACK = 64;       // readable entries past the arena end (wave loads of 64 words)

@@ -361,15 +361,18 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
 
 // ---- wave mode: one wavefront per column -----------------------------------------
 //
-// The working column is the XOR of three sorted lists:
+// The working column is the XOR of four sorted lists, each level absorbing the
+// one before it when that fills (a log-structured merge):
 //   P -- at most 64 keys in registers, lane i holding the i-th smallest; the
 //        three new edges of an apparent addition and short owner columns go here;
 //   F -- the front list in this wavefront's LDS (at most front_cap keys), which
 //        absorbs P when it fills and owner columns of up to XN keys;
-//   T -- the tail in the arena (immutable: a merge into it writes a new list);
-//        its top 64 keys are kept in a register window.
-// The pivot is the largest key present an odd number of times among the tops
-// of the three lists.  An iteration issues its loads together: the apparent
+//   U -- the middle list in the arena, which absorbs F when F fills, and is
+//        folded into T when it would grow past mid_cap keys;
+//   T -- the tail in the arena.
+// Arena lists are immutable (a merge into one writes a new list); the top 64
+// keys of U and of T are kept in register windows.  The pivot is the largest
+// key present an odd number of times among the tops of the four lists.  An iteration issues its loads together: the apparent
 // code of the pivot edge, its owner word, and the ten pixels that the four
 // squares around the edge can have as vertices, so an apparent addition costs
 // one memory latency and an owner addition two.  Merges are merge-path XOR
@@ -398,13 +401,35 @@ struct WaveBufs {
 
 __device__ __forceinline__ uint64_t* fbuf(const WaveBufs& S, uint32_t i) { return i ? S.F1 : S.F0; }
 
+// An arena list with a register window over its top: lane i holds v[b + i]
+// for b + i < n.
+struct Tail {
+  const uint64_t* v;
+  uint64_t w;
+  uint32_t n, b;
+};
+// The wave-mode kernel's RedCtx argument (its first, so at the start of the
+// kernel argument segment) through a pointer that the compiler may not assume
+// unchanged: fields read through it are loaded (scalar loads) where they are
+// used instead of occupying scalar registers for the whole column loop.  For
+// fields that the per-iteration path does not touch; only code called from
+// k_red_round_wave uses it.
+using KargCtx = const __attribute__((address_space(4))) RedCtx;
+__device__ __forceinline__ KargCtx* cold(const RedCtx&) {
+  KargCtx* p = (KargCtx*)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 struct WState {
   uint64_t p;        // this lane's pending key (lane < np)
-  uint64_t tw;       // tail window: lane i holds T[tb + i] for tb + i < nt
-  const uint64_t* T;
-  uint32_t np, nf, nt, tb, cur;
-  unsigned long long adds, merged;
+  Tail U, T;
+  uint32_t np, nf, cur;
+  unsigned long long adds, merged;  // statistics, counted in lane 0 (vector registers)
 };
+__device__ __forceinline__ void w_count(unsigned long long& acc, uint32_t v, int lane) {
+  acc += lane == 0 ? v : 0u;
+}
 
 __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -450,11 +475,13 @@ struct Lin {
   const uint64_t* p;
   __device__ __forceinline__ uint64_t operator[](uint32_t i) const { return p[i]; }
 };
-struct Ring {
+template <uint32_t N>
+struct RingN {
   const uint64_t* p;
   uint32_t base;
-  __device__ __forceinline__ uint64_t operator[](uint32_t i) const { return p[(base + i) & (XN - 1)]; }
+  __device__ __forceinline__ uint64_t operator[](uint32_t i) const { return p[(base + i) & (N - 1)]; }
 };
+using Ring = RingN<XN>;
 
 // Number of A elements among the first d positions of the merge of A and B,
 // ties taken from A first.
@@ -596,36 +623,128 @@ __device__ __noinline__ uint32_t w_merge_tail(uint64_t* X, const uint64_t* T, ui
   return o;
 }
 
+// out (arena) = A XOR B, both in the arena: as w_merge_tail, with the stage
+// split into one ring per input and chunks of half the size.
+__device__ __noinline__ uint32_t w_merge_gg(uint64_t* X, const uint64_t* A, uint32_t na, const uint64_t* B,
+                                            uint32_t nb, uint64_t* out, int lane) {
+  constexpr uint32_t HN = XN / 2;          // words of each ring
+  constexpr uint32_t HCH = HN / RING;      // keys per chunk
+  constexpr int HP = (int)(HCH / 64);      // merge positions per lane per step
+  uint64_t* XA = X;
+  uint64_t* XB = X + HN;
+  const uint32_t nca = (na + HCH - 1) / HCH, ncb = (nb + HCH - 1) / HCH;
+  uint64_t pa[HP], pb[HP];
+  auto load = [&](const uint64_t* src, uint32_t n, uint32_t nch, uint32_t c, uint64_t* pre) {
+#pragma unroll
+    for (int j = 0; j < HP; ++j) {
+      const uint32_t i = c * HCH + (uint32_t)(j * 64 + lane);
+      pre[j] = (c < nch && i < n) ? src[i] : 0ull;
+    }
+  };
+  auto store = [&](uint64_t* ring, uint32_t c, const uint64_t* pre) {
+    uint64_t* slot = ring + (c % RING) * HCH;
+#pragma unroll
+    for (int j = 0; j < HP; ++j) slot[j * 64 + lane] = pre[j];
+  };
+  load(A, na, nca, 0, pa);
+  load(B, nb, ncb, 0, pb);
+  store(XA, 0, pa);
+  store(XB, 0, pb);
+  load(A, na, nca, 1, pa);
+  load(B, nb, ncb, 1, pb);
+  store(XA, 1, pa);
+  store(XB, 1, pb);
+  uint32_t nexta = 2, nextb = 2;  // the chunks in flight in pa[] / pb[]
+  load(A, na, nca, nexta, pa);
+  load(B, nb, ncb, nextb, pb);
+  wsync();
+  uint32_t ia = 0, ib = 0, o = 0;
+  while (ia < na || ib < nb) {
+    const uint32_t la = na - ia < HCH ? na - ia : HCH;
+    const uint32_t lb = nb - ib < HCH ? nb - ib : HCH;
+    const SegResult r = w_merge_seg<HP>(RingN<HN>{XA, ia}, la, RingN<HN>{XB, ib}, lb, la + lb < HCH ? la + lb : HCH,
+                                        out + o, lane);
+    o += r.written;
+    ia += r.ka;
+    ib += r.kb;
+    // each input advances by at most one chunk per step
+    const bool sa = nexta < nca && nexta <= ia / HCH + 1;
+    const bool sb = nextb < ncb && nextb <= ib / HCH + 1;
+    if (sa || sb) {
+      wsync();
+      if (sa) {
+        store(XA, nexta, pa);
+        ++nexta;
+        load(A, na, nca, nexta, pa);
+      }
+      if (sb) {
+        store(XB, nextb, pb);
+        ++nextb;
+        load(B, nb, ncb, nextb, pb);
+      }
+    }
+    wsync();
+  }
+  wsync_global();
+  return o;
+}
+
 // Allocates n arena entries (lane 0) and broadcasts the offset (~0 on overflow).
 __device__ __forceinline__ uint64_t w_alloc(const RedCtx& R, uint64_t n, int lane) {
   unsigned long long off = 0;
-  if (lane == 0) off = arena_alloc(R, n ? n : 1);
+  if (lane == 0) {
+    const auto* C = cold(R);
+    n = n ? n : 1;
+    off = atomicAdd(C->arena_top, (unsigned long long)n);
+    if (off + n > C->arena_cap) {
+      raise_flag(C->st, &C->st->overflow, OVF_ARENA);
+      off = ~0ull;
+    }
+  }
   return rdlane64(off, 0);
 }
 
-__device__ __forceinline__ void w_twin_load(WState& W, int lane) {
-  W.tb = W.nt > 64 ? W.nt - 64 : 0;
-  W.tw = (W.tb + (uint32_t)lane < W.nt) ? W.T[W.tb + lane] : 0;
+__device__ __forceinline__ void tail_window(Tail& t, int lane) {
+  t.b = t.n > 64 ? t.n - 64 : 0;
+  t.w = (t.b + (uint32_t)lane < t.n) ? t.v[t.b + lane] : 0;
 }
-__device__ __forceinline__ void w_set_tail(WState& W, const uint64_t* T, uint32_t nt, int lane) {
-  W.T = T;
-  W.nt = nt;
-  w_twin_load(W, lane);
+__device__ __forceinline__ void tail_set(Tail& t, const uint64_t* v, uint32_t n, int lane) {
+  t.v = v;
+  t.n = n;
+  tail_window(t, lane);
 }
-__device__ __forceinline__ void w_tpop(WState& W, int lane) {
-  --W.nt;
-  if (W.nt > 0 && W.nt == W.tb) w_twin_load(W, lane);
+__device__ __forceinline__ uint64_t tail_top(const Tail& t) { return t.n ? rdlane64(t.w, t.n - 1 - t.b) : 0; }
+__device__ __forceinline__ void tail_pop(Tail& t, int lane) {
+  --t.n;
+  if (t.n > 0 && t.n == t.b) tail_window(t, lane);
 }
 
-// T ^= F (F becomes empty).
+// T ^= U (U becomes empty).
+__device__ __forceinline__ bool w_fold_mid(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
+  if (W.U.n == 0) return true;
+  if (W.T.n == 0) {
+    W.T = W.U;
+  } else {
+    const uint64_t off = w_alloc(R, (uint64_t)W.T.n + W.U.n, lane);
+    if (off == ~0ull) return false;
+    const uint32_t len = uni(w_merge_gg(S.X, W.T.v, W.T.n, W.U.v, W.U.n, R.arena + off, lane));
+    w_count(W.merged, W.T.n + W.U.n, lane);
+    tail_set(W.T, R.arena + off, len, lane);
+  }
+  W.U.n = 0;
+  return true;
+}
+
+// U ^= F (F becomes empty), folding U into T first if U would outgrow mid_cap.
 __device__ __forceinline__ bool w_push_front(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
   if (W.nf == 0) return true;
-  const uint64_t off = w_alloc(R, (uint64_t)W.nt + W.nf, lane);
+  if (W.U.n + W.nf > cold(R)->mid_cap && !w_fold_mid(R, S, W, lane)) return false;
+  const uint64_t off = w_alloc(R, (uint64_t)W.U.n + W.nf, lane);
   if (off == ~0ull) return false;
-  const uint32_t len = uni(w_merge_tail(S.X, W.T, W.nt, fbuf(S, W.cur), W.nf, R.arena + off, lane));
-  W.merged += W.nt + W.nf;
+  const uint32_t len = uni(w_merge_tail(S.X, W.U.v, W.U.n, fbuf(S, W.cur), W.nf, R.arena + off, lane));
+  w_count(W.merged, W.U.n + W.nf, lane);
   W.nf = 0;
-  w_set_tail(W, R.arena + off, len, lane);
+  tail_set(W.U, R.arena + off, len, lane);
   return true;
 }
 
@@ -633,7 +752,7 @@ __device__ __forceinline__ bool w_push_front(const RedCtx& R, const WaveBufs& S,
 __device__ __forceinline__ bool w_front_add(const RedCtx& R, const WaveBufs& S, WState& W, const uint64_t* X, uint32_t m,
                             int lane) {
   if (W.nf + m > S.cap && !w_push_front(R, S, W, lane)) return false;
-  W.merged += W.nf + m;
+  w_count(W.merged, W.nf + m, lane);
   W.nf = uni(w_xor_lds<PER_WIDE>(fbuf(S, W.cur), W.nf, X, m, fbuf(S, W.cur ^ 1), lane));
   W.cur ^= 1;
   return true;
@@ -689,34 +808,34 @@ __device__ __forceinline__ void w_p_add(const WaveBufs& S, WState& W, const uint
   wsync();
   uint64_t* out = fbuf(S, W.cur ^ 1);
   const uint32_t n = uni(w_xor_lds<PER_NARROW>(S.ps, W.np, X, m, out, lane));
-  W.merged += W.np + m;
+  w_count(W.merged, W.np + m, lane);
   W.p = (uint32_t)lane < n ? out[lane] : 0;
   W.np = n;
   wsync();
 }
 
-// Largest key present an odd number of times among the tops of P, F and T,
-// after dropping equal pairs (0 if the column is empty); *where names the list
-// that holds it afterwards (0 = P, 1 = F, 2 = T).
+// Largest key present an odd number of times among the tops of P, F, U and
+// T, after dropping equal pairs (0 if the column is empty); *where names the
+// list that holds it afterwards (0 = P, 1 = F, 2 = U, 3 = T).
 __device__ __forceinline__ uint64_t w_pivot(const WaveBufs& S, WState& W, int lane, int* where) {
   for (;;) {
     const uint64_t a = W.np ? rdlane64(W.p, W.np - 1) : 0;
     const uint64_t b = W.nf ? uni64(fbuf(S, W.cur)[W.nf - 1]) : 0;
-    const uint64_t c = W.nt ? rdlane64(W.tw, W.nt - 1 - W.tb) : 0;
+    const uint64_t u = tail_top(W.U);
+    const uint64_t c = tail_top(W.T);
     uint64_t m = a > b ? a : b;
+    m = m > u ? m : u;
     m = m > c ? m : c;
     if (m == 0) return 0;
-    const int k = (a == m) + (b == m) + (c == m);
-    if (k == 1) {
-      *where = a == m ? 0 : (b == m ? 1 : 2);
-      return m;
-    }
-    // two copies cancel; with three, the one in T remains
-    if (a == m) --W.np;
-    if (b == m) --W.nf;
-    if (k == 2 && c == m) w_tpop(W, lane);
-    if (k == 3) {
-      *where = 2;
+    const bool ha = a == m, hb = b == m, hu = u == m, hc = c == m;
+    // copies cancel in pairs; an odd count leaves the one in the deepest list
+    const int keep = ((int)ha + (int)hb + (int)hu + (int)hc) & 1 ? (hc ? 3 : (hu ? 2 : (hb ? 1 : 0))) : -1;
+    if (ha && keep != 0) --W.np;
+    if (hb && keep != 1) --W.nf;
+    if (hu && keep != 2) tail_pop(W.U, lane);
+    if (hc && keep != 3) tail_pop(W.T, lane);
+    if (keep >= 0) {
+      *where = keep;
       return m;
     }
   }
@@ -725,7 +844,8 @@ __device__ __forceinline__ uint64_t w_pivot(const WaveBufs& S, WState& W, int la
 __device__ __forceinline__ void w_pop(WState& W, int where, int lane) {
   if (where == 0) --W.np;
   else if (where == 1) --W.nf;
-  else w_tpop(W, lane);
+  else if (where == 2) tail_pop(W.U, lane);
+  else tail_pop(W.T, lane);
 }
 
 __device__ __forceinline__ float rdlane_f(float v, uint32_t i) {
@@ -735,8 +855,8 @@ __device__ __forceinline__ float rdlane_f(float v, uint32_t i) {
 // its left, then stores it and proposes it for its pivot.
 __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c, uint64_t off2,
                                    int lane) {
-  const int im = (int)uni((uint32_t)skey_img(R.L, uni64(R.skeys[off2 + c])));  // every edge lies in this image
-  ImgDesc d = R.imgs[im];
+  const int im = (int)uni((uint32_t)skey_img(R.L, uni64(cold(R)->skeys[off2 + c])));  // every edge lies in this image
+  ImgDesc d = cold(R)->imgs[im];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     d.n[a] = (int32_t)uni((uint32_t)d.n[a]);
@@ -747,31 +867,32 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
   const int64_t ps0 = (int64_t)d.n[1] * d.n[2], ps1 = d.n[2];
   const uint32_t ks0 = K1 * K2, ks1 = K2;
   {
-    const uint64_t off = uni64(R.col_ptr[c]);
+    const uint64_t off = uni64(cold(R)->col_ptr[c]);
     const uint32_t len = uni((uint32_t)R.arena[off]);
     const uint64_t* src = R.arena + off + 1;
     W.np = 0;
     W.cur = 0;
+    tail_set(W.U, src, 0, lane);
     if (len <= S.cap) {
       for (uint32_t i = lane; i < len; i += 64) S.F0[i] = src[i];
       W.nf = len;
-      w_set_tail(W, src, 0, lane);
+      tail_set(W.T, src, 0, lane);
     } else {
       W.nf = 0;
-      w_set_tail(W, src, len, lane);
+      tail_set(W.T, src, len, lane);
     }
     wsync();
   }
   for (uint32_t it = 0;; ++it) {
     if (it >= RED_ITER_CAP) {
-      if (lane == 0) raise_flag(R.st, &R.st->iter_cap);
+      if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->iter_cap);
       return;
     }
-    if ((it & 63) == 63 && aborted(R.st)) return;
+    if ((it & 63) == 63 && aborted(cold(R)->st)) return;
     int where = 0;
     const uint64_t e = w_pivot(S, W, lane, &where);
     if (e == 0) {  // a zero column: impossible after clearing
-      if (lane == 0) raise_flag(R.st, &R.st->internal);
+      if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->internal);
       return;
     }
     // the pivot edge: Khalimsky coordinates, axis, anchor pixel
@@ -780,7 +901,7 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
     const uint32_t ky = t1 % K1, kz = t1 / K1;
     if ((e >> (R.L.ib + 32 + R.L.kb)) != 1 || skey_img(R.L, e) != im || kz >= (uint32_t)d.K[0] ||
         ((kz & 1) + (ky & 1) + (kx & 1)) != 1) {  // not an edge of this image: a broken invariant
-      if (lane == 0) raise_flag(R.st, &R.st->internal);
+      if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->internal);
       return;
     }
     const int ax = (kz & 1) ? 0 : ((ky & 1) ? 1 : 2);
@@ -813,7 +934,7 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
     if (lane == 11) ow = R.owner[slot];
     const float pv = (praw != praw) ? INFINITY : canon(praw);
     code = (uint32_t)__builtin_amdgcn_readlane((int)code, 10);
-    W.adds += 1;
+    w_count(W.adds, 1, lane);
     if (code != 0xFF) {
       // apparent partner s: its boundary is e and three older edges
       const int bb = (int)(code >> 1);
@@ -826,7 +947,7 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
       const uint64_t ka0 = make_skey(R.L, 1, im, ord_of(fmaxf(v0, w0)), kidx - kax + kb);
       const uint64_t ka1 = make_skey(R.L, 1, im, ord_of(fmaxf(v1, w1)), kidx + kax + kb);
       if (kw >= e || ka0 >= e || ka1 >= e) {  // e must be the latest facet of s
-        if (lane == 0) raise_flag(R.st, &R.st->internal);
+        if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->internal);
         return;
       }
       w_pop(W, where, lane);
@@ -861,25 +982,31 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
       continue;
     }
     if ((uint32_t)o == c) {
-      if (lane == 0) raise_flag(R.st, &R.st->internal);
+      if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->internal);
       return;
     }
-    // store P ^ F ^ T and propose c for e
+    // store P ^ F ^ U ^ T and propose c for e
     if (!w_flush_p(R, S, W, lane)) return;
-    const uint64_t off = w_alloc(R, (uint64_t)W.nf + W.nt + 1, lane);
+    if (W.U.n && W.T.n && !w_push_front(R, S, W, lane)) return;
+    const Tail& G = W.T.n ? W.T : W.U;  // at most one of them is left with F
+    const Tail& H = W.T.n ? W.U : W.T;
+    const uint64_t off = w_alloc(R, (uint64_t)W.nf + G.n + H.n + 1, lane);
     if (off == ~0ull) return;
     uint32_t len;
-    if (W.nt == 0) {
+    if (H.n) {
+      len = uni(w_merge_gg(S.X, G.v, G.n, H.v, H.n, R.arena + off + 1, lane));
+    } else if (G.n) {
+      len = uni(w_merge_tail(S.X, G.v, G.n, fbuf(S, W.cur), W.nf, R.arena + off + 1, lane));
+    } else {
       for (uint32_t i = lane; i < W.nf; i += 64) R.arena[off + 1 + i] = fbuf(S, W.cur)[i];
       len = W.nf;
-    } else {
-      len = uni(w_merge_tail(S.X, W.T, W.nt, fbuf(S, W.cur), W.nf, R.arena + off + 1, lane));
     }
     if (lane == 0) {
       R.arena[off] = len;
-      R.col_ptr[c] = off;
-      R.piv[c] = e;
-      atomicMin(&R.claim[slot], (int32_t)c);
+      const auto* C = cold(R);
+      C->col_ptr[c] = off;
+      C->piv[c] = e;
+      atomicMin(&C->claim[slot], (int32_t)c);
     }
     return;
   }
@@ -887,6 +1014,8 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
 
 // Wave-mode round over the long-column list (and the short list when it has at
 // most R.wave_short columns); columns are taken from a counter.
+// R must stay the first parameter: the wave-mode helpers read some of its
+// fields from the start of the kernel argument segment.
 __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uint32_t* __restrict__ list_s,
                                                              const unsigned long long* __restrict__ n_s,
                                                              const uint32_t* __restrict__ list_l,
@@ -916,7 +1045,7 @@ __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uin
     reduce_column_wave(R, S, W, c, off2, lane);
     wsync();
   }
-  if (lane == 0 && W.adds) {
+  if (lane == 0 && W.adds) {  // lane 0 holds the counts
     atomicAdd(&R.st->adds, W.adds);
     atomicAdd(&R.st->merged, W.merged);
   }
@@ -1048,6 +1177,7 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.yield_iters = 1024;
   R.wave_short = 65536;
   R.front_cap = 1024;
+  R.mid_cap = 8192;
   return R;
 }
 

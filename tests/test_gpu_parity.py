@@ -161,20 +161,20 @@ def test_deterministic_repeat():
         assert_same(b, a, "repeat")
 
 
-WAVE_ENV = ("CR_LONG_LEN", "CR_YIELD_ITERS", "CR_WAVE_SHORT", "CR_FRONT_CAP")
+WAVE_ENV = ("CR_LONG_LEN", "CR_YIELD_ITERS", "CR_WAVE_SHORT", "CR_FRONT_CAP", "CR_MID_CAP")
 
 
 @pytest.mark.parametrize("setting", [
-    ("0", "2", "0", "4032"),        # every column to wave mode after two additions
-    ("8", "8", "0", "4032"),
-    ("0", "1", "1000000", "128"),   # whole rounds in wave mode, tiny front list: tail merges
-    ("4", "4", "64", "200"),
+    ("0", "2", "0", "4032", "8192"),      # every column to wave mode after two additions
+    ("8", "8", "0", "4032", "8192"),
+    ("0", "1", "1000000", "128", "300"),  # whole rounds in wave mode, tiny front and middle lists
+    ("4", "4", "64", "200", "0"),         # the middle list folded into the tail at every push
 ])
 def test_wave_mode_forced(setting):
     """Volumes whose columns are handed to the wavefront-per-column mode after a
-    few additions, with small front lists so that the tail merges run (the
-    thresholds are lowered through the environment, which the library reads at
-    every call)."""
+    few additions, with small front and middle lists so that the merges into the
+    arena lists run (the thresholds are lowered through the environment, which
+    the library reads at every call)."""
     import os
     rng = np.random.default_rng(5)
     cases = [(synth.blobs3d(16, 1), "blobs 16"), (synth.blobs3d(24, 2), "blobs 24"),
