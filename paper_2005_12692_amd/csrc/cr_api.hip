@@ -417,6 +417,11 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     if (const char* v = getenv("CR_YIELD_ITERS")) R.yield_iters = (uint32_t)strtoul(v, nullptr, 10);
     if (const char* v = getenv("CR_WAVE_SHORT")) R.wave_short = (uint32_t)strtoul(v, nullptr, 10);
     if (const char* v = getenv("CR_MID_CAP")) R.mid_cap = (uint32_t)strtoul(v, nullptr, 10);
+    if (const char* v = getenv("CR_NARROW_MIN")) R.narrow_min = (uint32_t)strtoul(v, nullptr, 10);
+    if (const char* v = getenv("CR_NARROW_CAP")) {
+      const unsigned long f = strtoul(v, nullptr, 10);
+      R.narrow_cap = (uint32_t)(f < FRONT_CAP_MIN ? FRONT_CAP_MIN : (f > FRONT_CAP_NARROW_MAX ? FRONT_CAP_NARROW_MAX : f));
+    }
     if (const char* v = getenv("CR_FRONT_CAP")) {
       const unsigned long f = strtoul(v, nullptr, 10);
       R.front_cap = (uint32_t)(f < FRONT_CAP_MIN ? FRONT_CAP_MIN : (f > FRONT_CAP_MAX ? FRONT_CAP_MAX : f));

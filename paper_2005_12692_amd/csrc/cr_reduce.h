@@ -30,12 +30,15 @@ struct RedCtx {
   uint32_t wave_short;     // a short list of at most this many columns is run in wave mode too
   uint32_t front_cap;      // keys of the wave-mode LDS front list
   uint32_t mid_cap;        // the wave-mode middle list is folded into the tail beyond this many keys
+  uint32_t narrow_min;     // a wave-mode round of at least this many columns runs in the narrow configuration
+  uint32_t narrow_cap;     // keys of the narrow configuration's front list
 };
 constexpr uint64_t NO_OWNER = ~0ull;
 constexpr uint64_t ARENA_SLACK = 64;       // readable entries past the arena end (wave loads of 64 words)
 constexpr uint64_t ARENA_MAX = (1ull << 32) - ARENA_SLACK;  // offsets fit the low half of an owner word
 constexpr uint32_t FRONT_CAP_MIN = 128;    // wave-mode LDS front list capacity bounds
 constexpr uint32_t FRONT_CAP_MAX = 4032;  // two wavefronts' front lists, stage and pending list fit 160 KiB of LDS
+constexpr uint32_t FRONT_CAP_NARROW_MAX = 352;  // narrow configuration: eight two-wave workgroups per CU
 
 RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64_t* skeys,
                    const unsigned long long* dim_count, const uint8_t* cleared, const uint8_t* eapp,

@@ -366,30 +366,44 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
 //   P -- at most 64 keys in registers, lane i holding the i-th smallest; the
 //        three new edges of an apparent addition and short owner columns go here;
 //   F -- the front list in this wavefront's LDS (at most front_cap keys), which
-//        absorbs P when it fills and owner columns of up to XN keys;
+//        absorbs P when it fills and owner columns of up to a stage of keys;
 //   U -- the middle list in the arena, which absorbs F when F fills, and is
 //        folded into T when it would grow past mid_cap keys;
 //   T -- the tail in the arena.
 // Arena lists are immutable (a merge into one writes a new list); the top 64
 // keys of U and of T are kept in register windows.  The pivot is the largest
-// key present an odd number of times among the tops of the four lists.  An iteration issues its loads together: the apparent
-// code of the pivot edge, its owner word, and the ten pixels that the four
-// squares around the edge can have as vertices, so an apparent addition costs
-// one memory latency and an owner addition two.  Merges are merge-path XOR
-// merges: PER positions per lane, equal pairs dropped, never split between
-// lanes.  Every step is wave-synchronous: no workgroup barriers.
+// key present an odd number of times among the tops of the four lists.  An
+// iteration issues its loads together: the apparent code of the pivot edge,
+// its owner word, and the ten pixels that the four squares around the edge can
+// have as vertices, so an apparent addition costs one memory latency and an
+// owner addition two.  Merges are merge-path XOR merges: a fixed number of
+// positions per lane, equal pairs dropped, never split between lanes.  Every
+// step is wave-synchronous: no workgroup barriers.
+//
+// Two configurations: the wide one (large stage and front list, few
+// wavefronts per CU) for rounds with few, long columns, and the narrow one
+// (small LDS footprint, four wavefronts per SIMD to hide memory latency) for
+// rounds with many columns.
 constexpr int WPB = 2;                 // wavefronts per workgroup
-constexpr int PER = 8;                 // merge positions per lane per step of a merge with the tail
-constexpr uint32_t CHUNK = 64 * PER;   // keys per chunk of the tail ring
-constexpr uint32_t RING = 4;           // chunks of the tail ring (two in use, one arriving, one spare)
-constexpr uint32_t XN = RING * CHUNK;  // the stage: tail ring, or an owner column being added
 constexpr int PER_WIDE = 16;           // merge positions per lane per step of a long LDS merge
 constexpr int PER_NARROW = 2;          // ... of a merge of at most 128 keys
 constexpr uint64_t KEY_INF = ~0ull;    // above every key
-static_assert((XN & (XN - 1)) == 0, "the tail ring is indexed with a mask");
-static_assert(WPB * 8 * (2 * FRONT_CAP_MAX + XN + 64) <= 160 * 1024, "wave-mode LDS exceeds a workgroup's share");
+template <int PER_>
+struct WaveCfg {
+  static constexpr int PER = PER_;              // merge positions per lane per step of a merge with an arena list
+  static constexpr uint32_t CHUNK = 64 * PER;   // keys per chunk of the ring
+  static constexpr uint32_t RING = 4;           // chunks of the ring (two in use, one arriving, one spare)
+  static constexpr uint32_t XN = RING * CHUNK;  // the stage: the ring, or an owner column being added
+  static_assert((XN & (XN - 1)) == 0, "the ring is indexed with a mask");
+};
+using WideCfg = WaveCfg<8>;
+using NarrowCfg = WaveCfg<2>;
+static_assert(WPB * 8 * (2 * FRONT_CAP_MAX + WideCfg::XN + 64) <= 160 * 1024, "wave-mode LDS exceeds a workgroup's share");
+static_assert(WPB * 8 * (2 * FRONT_CAP_NARROW_MAX + NarrowCfg::XN + 64) * 8 <= 160 * 1024,
+              "narrow wave mode: eight workgroups per CU");
 
-__host__ __device__ __forceinline__ size_t wave_lds_words(uint32_t front_cap) { return 2 * (size_t)front_cap + XN + 64; }
+template <class C>
+__host__ __device__ __forceinline__ size_t wave_lds_words(uint32_t front_cap) { return 2 * (size_t)front_cap + C::XN + 64; }
 
 struct WaveBufs {
   uint64_t* F0;      // the two front buffers (the front list and its merge target)
@@ -454,6 +468,12 @@ __device__ __forceinline__ uint64_t rdlane64(uint64_t v, uint32_t i) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+__device__ __forceinline__ uint64_t wballot(bool c) { return __builtin_amdgcn_ballot_w64(c); }
+// Number of set bits of m below this lane.
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Exclusive prefix over the wave of a count below 2^BITS per lane, from one
 // ballot per bit; sets *total.
 template <int BITS>
@@ -461,8 +481,8 @@ __device__ __forceinline__ uint32_t w_excl_small(uint32_t v, uint32_t* total) {
   uint32_t pre = 0, tot = 0;
 #pragma unroll
   for (int bit = 0; bit < BITS; ++bit) {
-    const uint64_t bm = __ballot((v >> bit) & 1u);
-    pre += __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u)) << bit;
+    const uint64_t bm = wballot(((v >> bit) & 1u) != 0);
+    pre += mbcnt64(bm) << bit;
     tot += (uint32_t)__popcll(bm) << bit;
   }
   *total = tot;
@@ -470,7 +490,7 @@ __device__ __forceinline__ uint32_t w_excl_small(uint32_t v, uint32_t* total) {
 }
 
 // A sorted list seen through an index map: a plain LDS array, or a window of
-// the tail ring (key i of the window is ring slot (base + i) mod XN).
+// a ring of N slots (key i of the window is ring slot (base + i) mod N).
 struct Lin {
   const uint64_t* p;
   __device__ __forceinline__ uint64_t operator[](uint32_t i) const { return p[i]; }
@@ -481,7 +501,6 @@ struct RingN {
   uint32_t base;
   __device__ __forceinline__ uint64_t operator[](uint32_t i) const { return p[(base + i) & (N - 1)]; }
 };
-using Ring = RingN<XN>;
 
 // Number of A elements among the first d positions of the merge of A and B,
 // ties taken from A first.
@@ -577,8 +596,11 @@ __device__ __noinline__ uint32_t w_xor_lds(const uint64_t* A, uint32_t na, const
 // resident, and the chunk after them is loaded into registers during each
 // merge step and stored into the ring when it is needed, so the load latency
 // overlaps the merging.
+template <class C>
 __device__ __noinline__ uint32_t w_merge_tail(uint64_t* X, const uint64_t* T, uint32_t nt, const uint64_t* F,
                                               uint32_t nf, uint64_t* out, int lane) {
+  constexpr int PER = C::PER;
+  constexpr uint32_t CHUNK = C::CHUNK, RING = C::RING;
   const uint32_t nch = (nt + CHUNK - 1) / CHUNK;
   uint64_t pre[PER];
   auto load_chunk = [&](uint32_t c) {
@@ -604,7 +626,7 @@ __device__ __noinline__ uint32_t w_merge_tail(uint64_t* X, const uint64_t* T, ui
   while (ia < nt || ib < nf) {
     const uint32_t la = nt - ia < CHUNK ? nt - ia : CHUNK;
     const uint32_t lb = nf - ib < CHUNK ? nf - ib : CHUNK;
-    const SegResult r = w_merge_seg<PER>(Ring{X, ia}, la, Lin{F + ib}, lb, la + lb < CHUNK ? la + lb : CHUNK, out + o,
+    const SegResult r = w_merge_seg<PER>(RingN<C::XN>{X, ia}, la, Lin{F + ib}, lb, la + lb < CHUNK ? la + lb : CHUNK, out + o,
                                          lane);
     o += r.written;
     ia += r.ka;
@@ -625,9 +647,11 @@ __device__ __noinline__ uint32_t w_merge_tail(uint64_t* X, const uint64_t* T, ui
 
 // out (arena) = A XOR B, both in the arena: as w_merge_tail, with the stage
 // split into one ring per input and chunks of half the size.
+template <class C>
 __device__ __noinline__ uint32_t w_merge_gg(uint64_t* X, const uint64_t* A, uint32_t na, const uint64_t* B,
                                             uint32_t nb, uint64_t* out, int lane) {
-  constexpr uint32_t HN = XN / 2;          // words of each ring
+  constexpr uint32_t RING = C::RING;
+  constexpr uint32_t HN = C::XN / 2;       // words of each ring
   constexpr uint32_t HCH = HN / RING;      // keys per chunk
   constexpr int HP = (int)(HCH / 64);      // merge positions per lane per step
   uint64_t* XA = X;
@@ -720,6 +744,7 @@ __device__ __forceinline__ void tail_pop(Tail& t, int lane) {
 }
 
 // T ^= U (U becomes empty).
+template <class C>
 __device__ __forceinline__ bool w_fold_mid(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
   if (W.U.n == 0) return true;
   if (W.T.n == 0) {
@@ -727,7 +752,7 @@ __device__ __forceinline__ bool w_fold_mid(const RedCtx& R, const WaveBufs& S, W
   } else {
     const uint64_t off = w_alloc(R, (uint64_t)W.T.n + W.U.n, lane);
     if (off == ~0ull) return false;
-    const uint32_t len = uni(w_merge_gg(S.X, W.T.v, W.T.n, W.U.v, W.U.n, R.arena + off, lane));
+    const uint32_t len = uni(w_merge_gg<C>(S.X, W.T.v, W.T.n, W.U.v, W.U.n, R.arena + off, lane));
     w_count(W.merged, W.T.n + W.U.n, lane);
     tail_set(W.T, R.arena + off, len, lane);
   }
@@ -736,12 +761,13 @@ __device__ __forceinline__ bool w_fold_mid(const RedCtx& R, const WaveBufs& S, W
 }
 
 // U ^= F (F becomes empty), folding U into T first if U would outgrow mid_cap.
+template <class C>
 __device__ __forceinline__ bool w_push_front(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
   if (W.nf == 0) return true;
-  if (W.U.n + W.nf > cold(R)->mid_cap && !w_fold_mid(R, S, W, lane)) return false;
+  if (W.U.n + W.nf > cold(R)->mid_cap && !w_fold_mid<C>(R, S, W, lane)) return false;
   const uint64_t off = w_alloc(R, (uint64_t)W.U.n + W.nf, lane);
   if (off == ~0ull) return false;
-  const uint32_t len = uni(w_merge_tail(S.X, W.U.v, W.U.n, fbuf(S, W.cur), W.nf, R.arena + off, lane));
+  const uint32_t len = uni(w_merge_tail<C>(S.X, W.U.v, W.U.n, fbuf(S, W.cur), W.nf, R.arena + off, lane));
   w_count(W.merged, W.U.n + W.nf, lane);
   W.nf = 0;
   tail_set(W.U, R.arena + off, len, lane);
@@ -749,9 +775,10 @@ __device__ __forceinline__ bool w_push_front(const RedCtx& R, const WaveBufs& S,
 }
 
 // F ^= X[0..m) (X in LDS), pushing F into T first if the result might not fit.
+template <class C>
 __device__ __forceinline__ bool w_front_add(const RedCtx& R, const WaveBufs& S, WState& W, const uint64_t* X, uint32_t m,
                             int lane) {
-  if (W.nf + m > S.cap && !w_push_front(R, S, W, lane)) return false;
+  if (W.nf + m > S.cap && !w_push_front<C>(R, S, W, lane)) return false;
   w_count(W.merged, W.nf + m, lane);
   W.nf = uni(w_xor_lds<PER_WIDE>(fbuf(S, W.cur), W.nf, X, m, fbuf(S, W.cur ^ 1), lane));
   W.cur ^= 1;
@@ -759,46 +786,37 @@ __device__ __forceinline__ bool w_front_add(const RedCtx& R, const WaveBufs& S, 
 }
 
 // F ^= P (P becomes empty).
+template <class C>
 __device__ __forceinline__ bool w_flush_p(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
   if (W.np == 0) return true;
   if ((uint32_t)lane < W.np) S.ps[lane] = W.p;
   wsync();
   const uint32_t np = W.np;
   W.np = 0;
-  return w_front_add(R, S, W, S.ps, np, lane);
+  return w_front_add<C>(R, S, W, S.ps, np, lane);
 }
 
-// Whole-wavefront lane shifts (DPP): lane i receives lane i+1 (down) or lane
-// i-1 (up); the end lane keeps its own value.
-__device__ __forceinline__ uint64_t wave_down1(uint64_t v) {
-  const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
-  const uint32_t l = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xF, 0xF, false);
-  const uint32_t h = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xF, 0xF, false);
-  return ((uint64_t)h << 32) | l;
-}
-__device__ __forceinline__ uint64_t wave_up1(uint64_t v) {
-  const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
-  const uint32_t l = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xF, 0xF, false);
-  const uint32_t h = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xF, 0xF, false);
-  return ((uint64_t)h << 32) | l;
-}
-
-// XOR-inserts one wave-uniform key into P (flushing P first if it is full).
-__device__ __forceinline__ bool w_insert(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t b, int lane) {
-  const uint64_t hit = __ballot((uint32_t)lane < W.np && W.p == b);
-  if (hit) {
-    const int pos = __ffsll((unsigned long long)hit) - 1;
-    const uint64_t q = wave_down1(W.p);
-    if (lane >= pos) W.p = q;
-    --W.np;
-    return true;
-  }
-  if (W.np == 64 && !w_flush_p(R, S, W, lane)) return false;
-  const int pos = __popcll(__ballot((uint32_t)lane < W.np && W.p < b));
-  const uint64_t q = wave_up1(W.p);
-  if (lane > pos) W.p = q;
-  if (lane == pos) W.p = b;
-  ++W.np;
+// P ^= {k0, k1, k2} for three distinct wave-uniform keys (flushing P first if
+// it might overflow): each kept key and each new key goes to its rank through
+// the LDS pending slot, with no branches on the data.
+template <class C>
+__device__ __forceinline__ bool w_insert3(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t k0, uint64_t k1,
+                                          uint64_t k2, int lane) {
+  if (W.np > 61 && !w_flush_p<C>(R, S, W, lane)) return false;
+  const bool in = (uint32_t)lane < W.np;
+  const uint64_t h0 = wballot(in && W.p == k0), h1 = wballot(in && W.p == k1), h2 = wballot(in && W.p == k2);
+  const uint64_t km = wballot(in) & ~(h0 | h1 | h2);  // lanes whose key stays
+  const bool n0 = h0 == 0, n1 = h1 == 0, n2 = h2 == 0;  // keys that are new
+  // ranks of the new keys among kept and new keys
+  const uint32_t r0 = (uint32_t)__popcll(km & wballot(W.p < k0)) + (n1 && k1 < k0) + (n2 && k2 < k0);
+  const uint32_t r1 = (uint32_t)__popcll(km & wballot(W.p < k1)) + (n0 && k0 < k1) + (n2 && k2 < k1);
+  const uint32_t r2 = (uint32_t)__popcll(km & wballot(W.p < k2)) + (n0 && k0 < k2) + (n1 && k1 < k2);
+  if ((km >> lane) & 1) S.ps[mbcnt64(km) + (n0 && k0 < W.p) + (n1 && k1 < W.p) + (n2 && k2 < W.p)] = W.p;
+  if (lane < 3 && sel3(lane, n0, n1, n2)) S.ps[sel3(lane, r0, r1, r2)] = sel3(lane, k0, k1, k2);
+  wsync();
+  W.np = (uint32_t)__popcll(km) + n0 + n1 + n2;
+  W.p = (uint32_t)lane < W.np ? S.ps[lane] : 0;
+  wsync();
   return true;
 }
 
@@ -853,6 +871,7 @@ __device__ __forceinline__ float rdlane_f(float v, uint32_t i) {
 }
 // Reduces column c for one round in wave mode: until its pivot has no owner to
 // its left, then stores it and proposes it for its pivot.
+template <class C>
 __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c, uint64_t off2,
                                    int lane) {
   const int im = (int)uni((uint32_t)skey_img(R.L, uni64(cold(R)->skeys[off2 + c])));  // every edge lies in this image
@@ -951,7 +970,7 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
         return;
       }
       w_pop(W, where, lane);
-      if (!w_insert(R, S, W, kw, lane) || !w_insert(R, S, W, ka0, lane) || !w_insert(R, S, W, ka1, lane)) return;
+      if (!w_insert3<C>(R, S, W, kw, ka0, ka1, lane)) return;
       continue;
     }
     ow = rdlane64(ow, 11);
@@ -969,14 +988,14 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
       } else {
         // into F, in pieces that fit the stage and F; room is made first, since
         // pushing F into T uses the stage as its ring
-        const uint32_t pmax = XN < S.cap ? XN : S.cap;
+        const uint32_t pmax = C::XN < S.cap ? C::XN : S.cap;
         for (uint32_t base = 0; base < m; base += pmax) {
           const uint32_t piece = m - base < pmax ? m - base : pmax;
-          if (W.nf + piece > S.cap && !w_push_front(R, S, W, lane)) return;
+          if (W.nf + piece > S.cap && !w_push_front<C>(R, S, W, lane)) return;
           if (base == 0 && lane >= 1 && (uint32_t)lane <= piece) S.X[lane - 1] = head;
           for (uint32_t i = (base == 0 ? 63u : 0u) + lane; i < piece; i += 64) S.X[i] = q[1 + base + i];
           wsync();
-          if (!w_front_add(R, S, W, S.X, piece, lane)) return;
+          if (!w_front_add<C>(R, S, W, S.X, piece, lane)) return;
         }
       }
       continue;
@@ -986,27 +1005,27 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
       return;
     }
     // store P ^ F ^ U ^ T and propose c for e
-    if (!w_flush_p(R, S, W, lane)) return;
-    if (W.U.n && W.T.n && !w_push_front(R, S, W, lane)) return;
+    if (!w_flush_p<C>(R, S, W, lane)) return;
+    if (W.U.n && W.T.n && !w_push_front<C>(R, S, W, lane)) return;
     const Tail& G = W.T.n ? W.T : W.U;  // at most one of them is left with F
     const Tail& H = W.T.n ? W.U : W.T;
     const uint64_t off = w_alloc(R, (uint64_t)W.nf + G.n + H.n + 1, lane);
     if (off == ~0ull) return;
     uint32_t len;
     if (H.n) {
-      len = uni(w_merge_gg(S.X, G.v, G.n, H.v, H.n, R.arena + off + 1, lane));
+      len = uni(w_merge_gg<C>(S.X, G.v, G.n, H.v, H.n, R.arena + off + 1, lane));
     } else if (G.n) {
-      len = uni(w_merge_tail(S.X, G.v, G.n, fbuf(S, W.cur), W.nf, R.arena + off + 1, lane));
+      len = uni(w_merge_tail<C>(S.X, G.v, G.n, fbuf(S, W.cur), W.nf, R.arena + off + 1, lane));
     } else {
       for (uint32_t i = lane; i < W.nf; i += 64) R.arena[off + 1 + i] = fbuf(S, W.cur)[i];
       len = W.nf;
     }
     if (lane == 0) {
       R.arena[off] = len;
-      const auto* C = cold(R);
-      C->col_ptr[c] = off;
-      C->piv[c] = e;
-      atomicMin(&C->claim[slot], (int32_t)c);
+      const auto* K = cold(R);
+      K->col_ptr[c] = off;
+      K->piv[c] = e;
+      atomicMin(&K->claim[slot], (int32_t)c);
     }
     return;
   }
@@ -1016,22 +1035,27 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
 // most R.wave_short columns); columns are taken from a counter.
 // R must stay the first parameter: the wave-mode helpers read some of its
 // fields from the start of the kernel argument segment.
+// The narrow configuration runs a round of at least R.narrow_min columns, the
+// wide one a round of fewer (both are launched; the other returns at once).
+template <class C>
 __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uint32_t* __restrict__ list_s,
                                                              const unsigned long long* __restrict__ n_s,
                                                              const uint32_t* __restrict__ list_l,
-                                                             const unsigned long long* __restrict__ n_l) {
+                                                             const unsigned long long* __restrict__ n_l,
+                                                             uint32_t front_cap) {
   extern __shared__ __align__(16) uint64_t lds_words[];
   if (aborted(R.st)) return;
+  const uint64_t nl = uni64(*n_l), ns0 = uni64(*n_s);
+  const uint64_t ns = ns0 <= R.wave_short ? ns0 : 0;
+  if ((nl + ns >= R.narrow_min) != (C::XN == NarrowCfg::XN)) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint64_t* base = lds_words + (size_t)wv * wave_lds_words(R.front_cap);
+  uint64_t* base = lds_words + (size_t)wv * wave_lds_words<C>(front_cap);
   WaveBufs S;
-  S.cap = R.front_cap;
+  S.cap = front_cap;
   S.F0 = base;
   S.F1 = base + S.cap;
   S.X = base + 2 * (size_t)S.cap;
-  S.ps = S.X + XN;
-  const uint64_t nl = uni64(*n_l), ns0 = uni64(*n_s);
-  const uint64_t ns = ns0 <= R.wave_short ? ns0 : 0;
+  S.ps = S.X + C::XN;
   const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
   WState W;
   W.adds = 0;
@@ -1042,7 +1066,7 @@ __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uin
     li = rdlane64(li, 0);
     if (li >= nl + ns || aborted(R.st)) break;
     const uint32_t c = uni(li < nl ? list_l[li] : list_s[li - nl]);
-    reduce_column_wave(R, S, W, c, off2, lane);
+    reduce_column_wave<C>(R, S, W, c, off2, lane);
     wsync();
   }
   if (lane == 0 && W.adds) {  // lane 0 holds the counts
@@ -1178,22 +1202,34 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.wave_short = 65536;
   R.front_cap = 1024;
   R.mid_cap = 8192;
+  R.narrow_min = 8192;
+  R.narrow_cap = 256;
   return R;
+}
+
+// Dynamic LDS bytes of a wave-mode workgroup, and the grid: as many
+// workgroups as fit the CUs at once (at most eight per CU).
+template <class C>
+static size_t wave_setup(uint32_t front_cap, int ncu, int* grid) {
+  const size_t lds = WPB * 8 * wave_lds_words<C>(front_cap);
+  static size_t lds_set = 0;
+  if (lds_set < lds) {
+    (void)hipFuncSetAttribute((const void*)k_red_round_wave<C>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    lds_set = lds;
+  }
+  const int fit = (int)(160 * 1024 / lds);
+  *grid = ncu * (fit < 1 ? 1 : (fit > 8 ? 8 : fit));
+  return lds;
 }
 
 void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round0,
                       int nrounds, hipStream_t s) {
-  const size_t lds = WPB * 8 * wave_lds_words(R.front_cap);
-  static size_t lds_set = 0;
-  if (lds_set < lds) {
-    (void)hipFuncSetAttribute((const void*)k_red_round_wave, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    lds_set = lds;
-  }
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int per_cu = (int)(160 * 1024 / lds) < 1 ? 1 : ((int)(160 * 1024 / lds) > 8 ? 8 : (int)(160 * 1024 / lds));
-  const int wgrid = ncu * per_cu;
+  int wgrid = 0, ngrid = 0;
+  const size_t lds = wave_setup<WideCfg>(R.front_cap, ncu, &wgrid);
+  const size_t nlds = wave_setup<NarrowCfg>(R.narrow_cap, ncu, &ngrid);
   for (int r = round0; r < round0 + nrounds; ++r) {
     const int cur = r & 1, nxt = (r + 1) & 1;
     const int first = r == 0;
@@ -1204,7 +1240,10 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
     unsigned long long* cnx = counts + 2 * nxt;
     k_fill_count<<<1, 1, 0, s>>>(cnx, R.work);
     k_red_round<THREAD_CAP><<<grid, 256, 0, s>>>(R, lt, ct, first, lists[2 * nxt + 1], cnx + 1);
-    if (!first) k_red_round_wave<<<wgrid, 64 * WPB, lds, s>>>(R, lt, ct, lb, ct + 1);
+    if (!first) {
+      k_red_round_wave<NarrowCfg><<<ngrid, 64 * WPB, nlds, s>>>(R, lt, ct, lb, ct + 1, R.narrow_cap);
+      k_red_round_wave<WideCfg><<<wgrid, 64 * WPB, lds, s>>>(R, lt, ct, lb, ct + 1, R.front_cap);
+    }
     k_red_commit<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first, lists[2 * nxt], lists[2 * nxt + 1], cnx);
     k_red_reset<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first);
   }

@@ -161,14 +161,19 @@ def test_deterministic_repeat():
         assert_same(b, a, "repeat")
 
 
-WAVE_ENV = ("CR_LONG_LEN", "CR_YIELD_ITERS", "CR_WAVE_SHORT", "CR_FRONT_CAP", "CR_MID_CAP")
+WAVE_ENV = ("CR_LONG_LEN", "CR_YIELD_ITERS", "CR_WAVE_SHORT", "CR_FRONT_CAP", "CR_MID_CAP", "CR_NARROW_MIN",
+            "CR_NARROW_CAP")
 
 
 @pytest.mark.parametrize("setting", [
-    ("0", "2", "0", "4032", "8192"),      # every column to wave mode after two additions
-    ("8", "8", "0", "4032", "8192"),
-    ("0", "1", "1000000", "128", "300"),  # whole rounds in wave mode, tiny front and middle lists
-    ("4", "4", "64", "200", "0"),         # the middle list folded into the tail at every push
+    # every column to wave mode after two additions; narrow configuration with a tiny front list
+    ("0", "2", "0", "4032", "8192", "0", "128"),
+    ("8", "8", "0", "4032", "8192", "1000000000", "256"),  # wide configuration only
+    # whole rounds in wave mode, tiny front and middle lists
+    ("0", "1", "1000000", "128", "300", "1000000000", "352"),
+    ("0", "1", "1000000", "128", "300", "0", "352"),
+    # the middle list folded into the tail at every push; both configurations
+    ("4", "4", "64", "200", "0", "64", "200"),
 ])
 def test_wave_mode_forced(setting):
     """Volumes whose columns are handed to the wavefront-per-column mode after a
