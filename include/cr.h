@@ -177,7 +177,7 @@ typedef struct cr_tuning {
   int32_t grid;         /* workgroups of the grid-stride kernels (union-find, output), 64 .. 65536 */
   int32_t long_len;     /* degree-1 reduction of a volume: a stored column longer than this
                            continues one per wavefront instead of one per thread (values
-                           above 16, the keys a thread holds in registers, act as 16) */
+                           above 32, the keys a thread holds in registers, act as 32) */
   int32_t yield_iters;  /* ... a column reduced one per thread moves to a wavefront after this
                            many additions (>= 1) */
   int32_t wave_short;   /* ... a list of at most this many short columns is run one per wavefront */

@@ -73,9 +73,9 @@ cr_tuning default_tuning(int ndim) {
   cr_tuning t;
   t.tile = 0;
   t.grid = 2048;
-  t.long_len = 16;
+  t.long_len = 32;
   t.yield_iters = 1024;
-  t.wave_short = 65536;
+  t.wave_short = 4096;
   t.front_cap = 1024;
   (void)ndim;
   return t;
@@ -406,7 +406,7 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     RedCtx R = make_redctx(image, d_imgs, L, skeys, &cnt[C_DIM], cleared, eapp, owner, at<int32_t>(ctx, p.claim),
                            at<uint64_t>(ctx, p.piv), at<uint64_t>(ctx, p.colptr), at<uint64_t>(ctx, p.arena),
                            p.arena_cap, &cnt[C_ARENA], &cnt[C_WORK], st);
-    R.long_len = (uint32_t)std::min(tu.long_len, 16);
+    R.long_len = (uint32_t)std::min(tu.long_len, 32);
     R.yield_iters = (uint32_t)tu.yield_iters;
     R.wave_short = (uint32_t)tu.wave_short;
     R.front_cap = (uint32_t)tu.front_cap;
@@ -948,7 +948,7 @@ cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed
     if (coord == 0) for (int v = 0; v < N_TILE_VARIANTS; ++v) vals.push_back(v);
     if (coord == 1) vals = {512, 1024, 2048, 4096, 8192};
     if (coord == 2) vals = {512, 1024, 2048, 4032};
-    if (coord == 3) vals = {4, 8, 16};
+    if (coord == 3) vals = {8, 16, 32};
     if (coord == 4) vals = {0, 4096, 65536, 1 << 30};
     if (coord == 5) vals = {16, 128, 1024};
     for (int v : vals) {

@@ -24,8 +24,8 @@ struct RedCtx {
   unsigned long long* arena_top;
   Status* st;
   unsigned long long* work;  // column counter of the wave-mode round
-  uint32_t long_len;       // stored columns longer than this continue in wave mode (<= 16: thread mode
-                           // holds a column of up to 16 keys in registers)
+  uint32_t long_len;       // stored columns longer than this continue in wave mode (<= 32: after the
+                           // first round thread mode holds a column of up to 32 keys in registers)
   uint32_t yield_iters;    // thread mode hands a column to wave mode after this many additions
   uint32_t wave_short;     // a short list of at most this many columns is run in wave mode too
   uint32_t front_cap;      // keys of the wave-mode LDS front list

@@ -133,7 +133,8 @@ __device__ __forceinline__ float pix_val(const float* img, int64_t p) {
 // (w[0] is the pivot).  XOR-inserting a key compares it with every slot and
 // shifts by selects, so nothing is indexed dynamically.  A column that would
 // grow past TC keys, or needs more than yield_iters additions in one round, is
-// stored and continues in wave mode.
+// stored and continues in wave mode -- except that in the first round, which
+// runs with a smaller TC, a column that outgrows it continues in thread mode.
 template <int TC>
 struct RegCol {
   uint64_t w[TC];
@@ -152,28 +153,24 @@ __device__ __forceinline__ void rc_pop(RegCol<TC>& C) {
 // hold 0, below every key, so they need no bounds test.
 template <int TC>
 __device__ __forceinline__ void rc_xor(RegCol<TC>& C, uint64_t k) {
-  uint32_t gt = 0;
   bool eq = false;
 #pragma unroll
+  for (int i = 0; i < TC; ++i) eq = eq || C.w[i] == k;
+  // one pass, in place, from the top: slot i keeps its key while that is above
+  // k; below, it takes the next key (k removed), or k at the first such slot
+  // and the previous key after it (k inserted)
+  uint64_t prev = 0;
+  bool prev_above = true;
+#pragma unroll
   for (int i = 0; i < TC; ++i) {
-    gt += C.w[i] > k ? 1u : 0u;
-    eq = eq || C.w[i] == k;
+    const uint64_t cur = C.w[i];
+    const uint64_t next = i + 1 < TC ? C.w[i + 1 < TC ? i + 1 : i] : 0ull;
+    const bool above = cur > k;
+    C.w[i] = above ? cur : (eq ? next : (prev_above ? k : prev));
+    prev = cur;
+    prev_above = above;
   }
-  if (eq) {  // remove slot gt: shift the smaller keys up, in place from the top
-#pragma unroll
-    for (int i = 0; i < TC; ++i) {
-      const uint64_t next = i + 1 < TC ? C.w[i + 1 < TC ? i + 1 : i] : 0ull;
-      if ((uint32_t)i >= gt) C.w[i] = next;
-    }
-    --C.n;
-  } else {  // insert at slot gt: shift the smaller keys down, in place from the bottom
-#pragma unroll
-    for (int i = TC - 1; i >= 0; --i) {
-      const uint64_t prev = i > 0 ? C.w[i > 0 ? i - 1 : 0] : 0ull;
-      C.w[i] = (uint32_t)i > gt ? prev : ((uint32_t)i == gt ? k : C.w[i]);
-    }
-    ++C.n;
-  }
+  C.n = eq ? C.n - 1 : C.n + 1;
 }
 
 // Writes the column to the arena as a stored list (ascending); returns its offset.
@@ -188,8 +185,12 @@ __device__ __forceinline__ uint64_t rc_store(const RedCtx& R, const RegCol<TC>& 
   return off;
 }
 
+constexpr int THREAD_CAP_FIRST = 16;  // keys of a thread-mode column in the first round
+constexpr int THREAD_CAP = 32;        // ... in later rounds
+
 template <int TC>
-__device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64_t off2, uint32_t* long_next,
+__device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64_t off2, uint32_t* short_next,
+                                 unsigned long long* n_short_next, uint32_t* long_next,
                                  unsigned long long* n_long_next, unsigned long long* adds) {
   const uint64_t sq = R.skeys[off2 + c];
   const int im = skey_img(R.L, sq);
@@ -241,16 +242,17 @@ __device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64
       if ((uint32_t)i < len) C.w[i] = R.arena[off + len - i];
     C.n = len;
   }
-  auto yield = [&]() {
+  auto yield = [&](bool full) {  // full: the column outgrew TC
     const uint64_t off = rc_store(R, C);
     if (off == ~0ull) return;
     R.col_ptr[c] = off;
     R.piv[c] = YIELDED;
-    push_list(long_next, n_long_next, c);
+    if (full && TC < THREAD_CAP) push_list(short_next, n_short_next, c);
+    else push_list(long_next, n_long_next, c);
   };
   for (uint32_t it = 0;; ++it) {
     if (it >= R.yield_iters) {
-      yield();
+      yield(false);
       return;
     }
     if (C.n == 0) {  // a zero column would be a birth of degree 2: those were cleared
@@ -273,7 +275,7 @@ __device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64
     const uint64_t ow = R.owner[slot];
     if (code != 0xFF) {  // the apparent partner s of e: its boundary is e and three older edges
       if (C.n + 2 > (uint32_t)TC) {
-        yield();
+        yield(true);
         return;
       }
       const int bb = code >> 1;
@@ -302,7 +304,7 @@ __device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64
       const uint64_t* q = R.arena + (uint32_t)ow;
       const uint32_t m = (uint32_t)q[0] - 1;
       if (C.n - 1 + m > (uint32_t)TC) {
-        yield();
+        yield(true);
         return;
       }
       rc_pop(C);
@@ -330,8 +332,6 @@ __device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64
   }
 }
 
-constexpr int THREAD_CAP = 16;  // keys of a thread-mode column
-
 __global__ void k_fill_count(unsigned long long* c, unsigned long long* work) {
   c[0] = 0;
   c[1] = 0;
@@ -343,6 +343,8 @@ __global__ void k_fill_count(unsigned long long* c, unsigned long long* work) {
 template <int TC>
 __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __restrict__ list,
                                                    const unsigned long long* __restrict__ n_list, int first,
+                                                   uint32_t* __restrict__ short_next,
+                                                   unsigned long long* __restrict__ n_short_next,
                                                    uint32_t* __restrict__ long_next,
                                                    unsigned long long* __restrict__ n_long_next) {
   if (aborted(R.st)) return;
@@ -354,7 +356,7 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
     if (aborted(R.st)) break;
     const uint32_t c = first ? (uint32_t)i : list[i];
     if (first && R.cleared[c]) continue;
-    reduce_round_reg<TC>(R, c, first != 0, off2, long_next, n_long_next, &adds);
+    reduce_round_reg<TC>(R, c, first != 0, off2, short_next, n_short_next, long_next, n_long_next, &adds);
   }
   if (adds) atomicAdd(&R.st->adds, adds);
 }
@@ -892,7 +894,12 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
     W.np = 0;
     W.cur = 0;
     tail_set(W.U, src, 0, lane);
-    if (len <= S.cap) {
+    if (len <= 64) {  // into P
+      W.p = (uint32_t)lane < len ? src[lane] : 0;
+      W.np = len;
+      W.nf = 0;
+      tail_set(W.T, src, 0, lane);
+    } else if (len <= S.cap) {
       for (uint32_t i = lane; i < len; i += 64) S.F0[i] = src[i];
       W.nf = len;
       tail_set(W.T, src, 0, lane);
@@ -1005,6 +1012,19 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
       return;
     }
     // store P ^ F ^ U ^ T and propose c for e
+    if (W.nf == 0 && W.U.n == 0 && W.T.n == 0) {  // the column is P
+      const uint64_t off = w_alloc(R, (uint64_t)W.np + 1, lane);
+      if (off == ~0ull) return;
+      if ((uint32_t)lane < W.np) R.arena[off + 1 + lane] = W.p;
+      if (lane == 0) {
+        R.arena[off] = W.np;
+        const auto* K = cold(R);
+        K->col_ptr[c] = off;
+        K->piv[c] = e;
+        atomicMin(&K->claim[slot], (int32_t)c);
+      }
+      return;
+    }
     if (!w_flush_p<C>(R, S, W, lane)) return;
     if (W.U.n && W.T.n && !w_push_front<C>(R, S, W, lane)) return;
     const Tail& G = W.T.n ? W.T : W.U;  // at most one of them is left with F
@@ -1197,9 +1217,9 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.arena_top = arena_top;
   R.work = work;
   R.st = st;
-  R.long_len = 16;
+  R.long_len = THREAD_CAP;
   R.yield_iters = 1024;
-  R.wave_short = 65536;
+  R.wave_short = 4096;
   R.front_cap = 1024;
   R.mid_cap = 8192;
   R.narrow_min = 8192;
@@ -1239,7 +1259,11 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
     unsigned long long* ct = counts + 2 * cur;
     unsigned long long* cnx = counts + 2 * nxt;
     k_fill_count<<<1, 1, 0, s>>>(cnx, R.work);
-    k_red_round<THREAD_CAP><<<grid, 256, 0, s>>>(R, lt, ct, first, lists[2 * nxt + 1], cnx + 1);
+    if (first)
+      k_red_round<THREAD_CAP_FIRST><<<grid, 256, 0, s>>>(R, lt, ct, first, lists[2 * nxt], cnx, lists[2 * nxt + 1],
+                                                         cnx + 1);
+    else
+      k_red_round<THREAD_CAP><<<grid, 256, 0, s>>>(R, lt, ct, first, lists[2 * nxt], cnx, lists[2 * nxt + 1], cnx + 1);
     if (!first) {
       k_red_round_wave<NarrowCfg><<<ngrid, 64 * WPB, nlds, s>>>(R, lt, ct, lb, ct + 1, R.narrow_cap);
       k_red_round_wave<WideCfg><<<wgrid, 64 * WPB, lds, s>>>(R, lt, ct, lb, ct + 1, R.front_cap);
