@@ -418,6 +418,11 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     if (const char* v = getenv("CR_WAVE_SHORT")) R.wave_short = (uint32_t)strtoul(v, nullptr, 10);
     if (const char* v = getenv("CR_MID_CAP")) R.mid_cap = (uint32_t)strtoul(v, nullptr, 10);
     if (const char* v = getenv("CR_NARROW_MIN")) R.narrow_min = (uint32_t)strtoul(v, nullptr, 10);
+    if (const char* v = getenv("CR_GROUP_MAX")) R.group_max = (uint32_t)strtoul(v, nullptr, 10);
+    if (const char* v = getenv("CR_GROUP_CAP")) {
+      const unsigned long f = strtoul(v, nullptr, 10);
+      R.group_cap = (uint32_t)(f < FRONT_CAP_MIN ? FRONT_CAP_MIN : (f > 4096 ? 4096 : f));
+    }
     if (const char* v = getenv("CR_NARROW_CAP")) {
       const unsigned long f = strtoul(v, nullptr, 10);
       R.narrow_cap = (uint32_t)(f < FRONT_CAP_MIN ? FRONT_CAP_MIN : (f > FRONT_CAP_NARROW_MAX ? FRONT_CAP_NARROW_MAX : f));

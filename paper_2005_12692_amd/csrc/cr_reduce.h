@@ -32,6 +32,8 @@ struct RedCtx {
   uint32_t mid_cap;        // the wave-mode middle list is folded into the tail beyond this many keys
   uint32_t narrow_min;     // a wave-mode round of at least this many columns runs in the narrow configuration
   uint32_t narrow_cap;     // keys of the narrow configuration's front list
+  uint32_t group_max;      // a wave-mode round of at most this many columns runs a workgroup per column
+  uint32_t group_cap;      // keys of the group mode's front list
 };
 constexpr uint64_t NO_OWNER = ~0ull;
 constexpr uint64_t ARENA_SLACK = 64;       // readable entries past the arena end (wave loads of 64 words)

@@ -410,8 +410,10 @@ __host__ __device__ __forceinline__ size_t wave_lds_words(uint32_t front_cap) { 
 struct WaveBufs {
   uint64_t* F0;      // the two front buffers (the front list and its merge target)
   uint64_t* F1;
-  uint64_t* X;
-  uint64_t* ps;
+  uint64_t* X;       // the stage
+  uint64_t* ps;      // 64 words: P staged for a merge
+  uint64_t* hx;      // 64 words: a short owner column staged for a merge into P
+  uint64_t* po;      // 128 words: the output of that merge (null: F's spare buffer)
   uint32_t cap;
 };
 
@@ -826,7 +828,7 @@ __device__ __forceinline__ bool w_insert3(const RedCtx& R, const WaveBufs& S, WS
 __device__ __forceinline__ void w_p_add(const WaveBufs& S, WState& W, const uint64_t* X, uint32_t m, int lane) {
   if ((uint32_t)lane < W.np) S.ps[lane] = W.p;
   wsync();
-  uint64_t* out = fbuf(S, W.cur ^ 1);
+  uint64_t* out = S.po ? S.po : fbuf(S, W.cur ^ 1);
   const uint32_t n = uni(w_xor_lds<PER_NARROW>(S.ps, W.np, X, m, out, lane));
   w_count(W.merged, W.np + m, lane);
   W.p = (uint32_t)lane < n ? out[lane] : 0;
@@ -871,11 +873,47 @@ __device__ __forceinline__ void w_pop(WState& W, int where, int lane) {
 __device__ __forceinline__ float rdlane_f(float v, uint32_t i) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)i));
 }
-// Reduces column c for one round in wave mode: until its pivot has no owner to
-// its left, then stores it and proposes it for its pivot.
+// The steps of a column reduction that differ between one wavefront per
+// column and a workgroup per column.
 template <class C>
-__device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c, uint64_t off2,
+struct WaveOps {
+  static constexpr uint32_t XN = C::XN;
+  static constexpr uint32_t NT = 64;  // threads that share the column
+  __device__ static uint32_t tid(int lane) { return (uint32_t)lane; }
+  __device__ static bool leader(int lane) { return lane == 0; }
+  __device__ static void sync() { wsync(); }
+  __device__ static bool aborted(const RedCtx& R, const WaveBufs&) { return cr::aborted(cold(R)->st); }
+  __device__ static uint64_t alloc(const RedCtx& R, const WaveBufs&, uint64_t n, int lane) { return w_alloc(R, n, lane); }
+  __device__ static bool insert3(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t k0, uint64_t k1, uint64_t k2,
+                                 int lane) {
+    return w_insert3<C>(R, S, W, k0, k1, k2, lane);
+  }
+  __device__ static bool flush_p(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
+    return w_flush_p<C>(R, S, W, lane);
+  }
+  __device__ static bool push_front(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
+    return w_push_front<C>(R, S, W, lane);
+  }
+  __device__ static bool front_add(const RedCtx& R, const WaveBufs& S, WState& W, const uint64_t* X, uint32_t m,
                                    int lane) {
+    return w_front_add<C>(R, S, W, X, m, lane);
+  }
+  __device__ static uint32_t merge_tail(const WaveBufs& S, const uint64_t* T, uint32_t nt, const uint64_t* F,
+                                        uint32_t nf, uint64_t* out, int lane) {
+    return uni(w_merge_tail<C>(S.X, T, nt, F, nf, out, lane));
+  }
+  __device__ static uint32_t merge_gg(const WaveBufs& S, const uint64_t* A, uint32_t na, const uint64_t* B,
+                                      uint32_t nb, uint64_t* out, int lane) {
+    return uni(w_merge_gg<C>(S.X, A, na, B, nb, out, lane));
+  }
+};
+
+// Reduces column c for one round: until its pivot has no owner to its left,
+// then stores it and proposes it for its pivot.  Every wavefront that shares
+// the column runs this with the same data and so takes the same branches.
+template <class O>
+__device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c, uint64_t off2,
+                                              int lane) {
   const int im = (int)uni((uint32_t)skey_img(R.L, uni64(cold(R)->skeys[off2 + c])));  // every edge lies in this image
   ImgDesc d = cold(R)->imgs[im];
 #pragma unroll
@@ -900,21 +938,21 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
       W.nf = 0;
       tail_set(W.T, src, 0, lane);
     } else if (len <= S.cap) {
-      for (uint32_t i = lane; i < len; i += 64) S.F0[i] = src[i];
+      for (uint32_t i = O::tid(lane); i < len; i += O::NT) S.F0[i] = src[i];
       W.nf = len;
       tail_set(W.T, src, 0, lane);
     } else {
       W.nf = 0;
       tail_set(W.T, src, len, lane);
     }
-    wsync();
+    O::sync();
   }
   for (uint32_t it = 0;; ++it) {
     if (it >= RED_ITER_CAP) {
       if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->iter_cap);
       return;
     }
-    if ((it & 63) == 63 && aborted(cold(R)->st)) return;
+    if ((it & 63) == 63 && O::aborted(R, S)) return;
     int where = 0;
     const uint64_t e = w_pivot(S, W, lane, &where);
     if (e == 0) {  // a zero column: impossible after clearing
@@ -977,7 +1015,7 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
         return;
       }
       w_pop(W, where, lane);
-      if (!w_insert3<C>(R, S, W, kw, ka0, ka1, lane)) return;
+      if (!O::insert3(R, S, W, kw, ka0, ka1, lane)) return;
       continue;
     }
     ow = rdlane64(ow, 11);
@@ -989,20 +1027,19 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
       const uint32_t m = len - 1;     // keys below e
       w_pop(W, where, lane);
       if (m + W.np <= 64 && m <= 63) {  // the loaded head holds keys 0..62
-        if (lane >= 1 && (uint32_t)lane <= m) S.X[lane - 1] = head;
+        if (lane >= 1 && (uint32_t)lane <= m) S.hx[lane - 1] = head;
         wsync();
-        w_p_add(S, W, S.X, m, lane);
+        w_p_add(S, W, S.hx, m, lane);
       } else {
         // into F, in pieces that fit the stage and F; room is made first, since
-        // pushing F into T uses the stage as its ring
-        const uint32_t pmax = C::XN < S.cap ? C::XN : S.cap;
+        // pushing F into the arena lists uses the stage as its ring
+        const uint32_t pmax = O::XN < S.cap ? O::XN : S.cap;
         for (uint32_t base = 0; base < m; base += pmax) {
           const uint32_t piece = m - base < pmax ? m - base : pmax;
-          if (W.nf + piece > S.cap && !w_push_front<C>(R, S, W, lane)) return;
-          if (base == 0 && lane >= 1 && (uint32_t)lane <= piece) S.X[lane - 1] = head;
-          for (uint32_t i = (base == 0 ? 63u : 0u) + lane; i < piece; i += 64) S.X[i] = q[1 + base + i];
-          wsync();
-          if (!w_front_add<C>(R, S, W, S.X, piece, lane)) return;
+          if (W.nf + piece > S.cap && !O::push_front(R, S, W, lane)) return;
+          for (uint32_t i = O::tid(lane); i < piece; i += O::NT) S.X[i] = q[1 + base + i];
+          O::sync();
+          if (!O::front_add(R, S, W, S.X, piece, lane)) return;
         }
       }
       continue;
@@ -1013,10 +1050,10 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
     }
     // store P ^ F ^ U ^ T and propose c for e
     if (W.nf == 0 && W.U.n == 0 && W.T.n == 0) {  // the column is P
-      const uint64_t off = w_alloc(R, (uint64_t)W.np + 1, lane);
+      const uint64_t off = O::alloc(R, S, (uint64_t)W.np + 1, lane);
       if (off == ~0ull) return;
-      if ((uint32_t)lane < W.np) R.arena[off + 1 + lane] = W.p;
-      if (lane == 0) {
+      if (O::tid(lane) < W.np) R.arena[off + 1 + lane] = W.p;
+      if (O::leader(lane)) {
         R.arena[off] = W.np;
         const auto* K = cold(R);
         K->col_ptr[c] = off;
@@ -1025,22 +1062,22 @@ __device__ __forceinline__ void reduce_column_wave(const RedCtx& R, const WaveBu
       }
       return;
     }
-    if (!w_flush_p<C>(R, S, W, lane)) return;
-    if (W.U.n && W.T.n && !w_push_front<C>(R, S, W, lane)) return;
+    if (!O::flush_p(R, S, W, lane)) return;
+    if (W.U.n && W.T.n && !O::push_front(R, S, W, lane)) return;
     const Tail& G = W.T.n ? W.T : W.U;  // at most one of them is left with F
     const Tail& H = W.T.n ? W.U : W.T;
-    const uint64_t off = w_alloc(R, (uint64_t)W.nf + G.n + H.n + 1, lane);
+    const uint64_t off = O::alloc(R, S, (uint64_t)W.nf + G.n + H.n + 1, lane);
     if (off == ~0ull) return;
     uint32_t len;
     if (H.n) {
-      len = uni(w_merge_gg<C>(S.X, G.v, G.n, H.v, H.n, R.arena + off + 1, lane));
+      len = O::merge_gg(S, G.v, G.n, H.v, H.n, R.arena + off + 1, lane);
     } else if (G.n) {
-      len = uni(w_merge_tail<C>(S.X, G.v, G.n, fbuf(S, W.cur), W.nf, R.arena + off + 1, lane));
+      len = O::merge_tail(S, G.v, G.n, fbuf(S, W.cur), W.nf, R.arena + off + 1, lane);
     } else {
-      for (uint32_t i = lane; i < W.nf; i += 64) R.arena[off + 1 + i] = fbuf(S, W.cur)[i];
+      for (uint32_t i = O::tid(lane); i < W.nf; i += O::NT) R.arena[off + 1 + i] = fbuf(S, W.cur)[i];
       len = W.nf;
     }
-    if (lane == 0) {
+    if (O::leader(lane)) {
       R.arena[off] = len;
       const auto* K = cold(R);
       K->col_ptr[c] = off;
@@ -1067,7 +1104,7 @@ __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uin
   if (aborted(R.st)) return;
   const uint64_t nl = uni64(*n_l), ns0 = uni64(*n_s);
   const uint64_t ns = ns0 <= R.wave_short ? ns0 : 0;
-  if ((nl + ns >= R.narrow_min) != (C::XN == NarrowCfg::XN)) return;
+  if (nl + ns <= R.group_max || (nl + ns >= R.narrow_min) != (C::XN == NarrowCfg::XN)) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint64_t* base = lds_words + (size_t)wv * wave_lds_words<C>(front_cap);
   WaveBufs S;
@@ -1076,6 +1113,8 @@ __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uin
   S.F1 = base + S.cap;
   S.X = base + 2 * (size_t)S.cap;
   S.ps = S.X + C::XN;
+  S.hx = S.X;
+  S.po = nullptr;
   const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
   WState W;
   W.adds = 0;
@@ -1086,10 +1125,386 @@ __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uin
     li = rdlane64(li, 0);
     if (li >= nl + ns || aborted(R.st)) break;
     const uint32_t c = uni(li < nl ? list_l[li] : list_s[li - nl]);
-    reduce_column_wave<C>(R, S, W, c, off2, lane);
+    reduce_column<WaveOps<C>>(R, S, W, c, off2, lane);
     wsync();
   }
   if (lane == 0 && W.adds) {  // lane 0 holds the counts
+    atomicAdd(&R.st->adds, W.adds);
+    atomicAdd(&R.st->merged, W.merged);
+  }
+}
+
+// ---- group mode: one workgroup of NW wavefronts per column ---------------------------
+//
+// For rounds with few columns.  Every wavefront runs reduce_column with the
+// same data, so each holds the same P, windows and counts; the merges of F, U
+// and T -- the bulk of a long column's work -- are split between the
+// wavefronts: a merge advances in steps of NW * 64 * P positions, each
+// wavefront taking a contiguous part of the step (lane splits by merge path
+// over the whole lists, restricted to what the step can reach), and the
+// wavefronts' output counts are combined through LDS before writing.  Arena
+// inputs stream through rings of four chunks of one step's size (the chunks
+// before, at and after the step's start resident, the next one loading into
+// registers).  Arena allocation, the column counter and the abort test are
+// done once and broadcast, so that no wavefront can take another branch.
+constexpr int GNW = 8;              // wavefronts per group
+constexpr int GP_LDS = 4;           // merge positions per lane per step: LDS lists
+constexpr int GP_TAIL = 4;          // ... an arena list with an LDS list
+constexpr int GP_GG = 2;            // ... two arena lists
+constexpr uint32_t GXN = 4 * GNW * 64 * GP_TAIL;  // stage words: one ring of four chunks (two rings for GP_GG)
+static_assert(2 * 4 * GNW * 64 * GP_GG == GXN, "the two rings of an arena-arena merge fill the stage");
+constexpr uint32_t GPRIV = 64 + 64 + 128;  // words per wavefront: ps, hx, po
+struct GroupShared {
+  uint32_t cnt[GNW];   // output counts of the wavefronts in a merge step
+  uint32_t end_a, end_b;
+  unsigned long long bc;  // broadcast word
+};
+__host__ __device__ __forceinline__ size_t group_lds_bytes(uint32_t cap) {
+  return 8 * (2 * (size_t)cap + GXN + (size_t)GNW * GPRIV) + sizeof(GroupShared);
+}
+constexpr uint32_t FRONT_CAP_GROUP_MAX = 4096;
+static_assert(8 * (2 * FRONT_CAP_GROUP_MAX + GXN + GNW * GPRIV) + sizeof(GroupShared) <= 160 * 1024,
+              "group mode LDS exceeds a workgroup's share");
+
+__device__ __forceinline__ GroupShared* gshared(const WaveBufs& S) {
+  return reinterpret_cast<GroupShared*>(S.X + GXN + GNW * GPRIV);
+}
+__device__ __forceinline__ uint32_t gtid(int lane) { return (threadIdx.x & ~63u) + (uint32_t)lane; }
+
+// Thread 0's value of v, in every thread of the workgroup.
+__device__ __forceinline__ uint64_t g_bcast(GroupShared* G, uint64_t v) {
+  __syncthreads();
+  if (threadIdx.x == 0) G->bc = v;
+  __syncthreads();
+  const uint64_t r = uni64(G->bc);
+  __syncthreads();
+  return r;
+}
+
+// Merge-path split at position d, knowing that the split at d0 <= d took ia0
+// keys of A: the search only reads A in [ia0, ia0 + d - d0) and B within one
+// step of its own start.
+template <class AA, class BB>
+__device__ __forceinline__ uint32_t g_split(const AA& A, uint32_t na, const BB& B, uint32_t nb, uint32_t d,
+                                            uint32_t d0, uint32_t ia0) {
+  uint32_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+  lo = lo > ia0 ? lo : ia0;
+  hi = hi < ia0 + (d - d0) ? hi : ia0 + (d - d0);
+  while (lo < hi) {
+    const uint32_t m = (lo + hi) >> 1;
+    if (A[m] <= B[d - m - 1]) lo = m + 1;
+    else hi = m;
+  }
+  return lo;
+}
+
+// A sorted arena list streamed through a ring of four chunks of CH keys; the
+// workgroup loads chunk c with P keys per thread.
+template <int P>
+struct GRing {
+  static constexpr uint32_t CH = GNW * 64 * P;
+  uint64_t* slots;
+  const uint64_t* src;
+  uint32_t n, nch, next;
+  uint64_t pre[P];
+  __device__ __forceinline__ uint64_t operator[](uint32_t i) const { return slots[i & (4 * CH - 1)]; }
+  __device__ __forceinline__ void load(uint32_t c) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const uint32_t i = c * CH + (uint32_t)j * (GNW * 64) + threadIdx.x;
+      pre[j] = (c < nch && i < n) ? src[i] : 0ull;
+    }
+  }
+  __device__ __forceinline__ void store(uint32_t c) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) slots[(c % 4) * CH + (uint32_t)j * (GNW * 64) + threadIdx.x] = pre[j];
+  }
+  __device__ __forceinline__ void init(uint64_t* sl, const uint64_t* s, uint32_t len) {
+    slots = sl;
+    src = s;
+    n = len;
+    nch = (len + CH - 1) / CH;
+    load(0);
+    store(0);
+    load(1);
+    store(1);
+    next = 2;
+    load(2);
+  }
+  // Makes the chunks up to the one after the chunk of key i resident (the
+  // slot it takes held a chunk at least three below).
+  __device__ __forceinline__ void advance(uint32_t i) {
+    if (next < nch && next <= i / CH + 1) {
+      store(next);
+      ++next;
+      load(next);
+    }
+  }
+};
+struct GLds {
+  const uint64_t* p;
+  __device__ __forceinline__ uint64_t operator[](uint32_t i) const { return p[i]; }
+};
+
+// out = A XOR B by the whole workgroup, in steps of GNW * 64 * P positions;
+// pre(ia, ib) runs at the start of each step (the keys of A and B consumed so
+// far) to make what the step reads resident.  Returns the number written
+// (the same in every thread).
+template <int P, class AA, class BB, class Pre>
+__device__ __forceinline__ uint32_t g_merge(const AA& A, uint32_t na, const BB& B, uint32_t nb, uint64_t* out,
+                                            GroupShared* G, int lane, Pre pre) {
+  constexpr uint32_t D = GNW * 64 * P;
+  const uint32_t wv = threadIdx.x >> 6;
+  const uint32_t total = na + nb;
+  uint32_t d0 = 0, ia0 = 0, ib0 = 0, o = 0;
+  while (d0 < total) {
+    pre(ia0, ib0);
+    __syncthreads();
+    const uint32_t d1 = total - d0 < D ? total : d0 + D;
+    const uint32_t mine = d0 + (wv * 64 + (uint32_t)lane + 1) * P;
+    const uint32_t dend = mine < d1 ? mine : d1;
+    const uint32_t ie = g_split(A, na, B, nb, dend, d0, ia0);
+    uint32_t je = dend - ie;
+    if (ie > 0 && je < nb && A[ie - 1] == B[je]) ++je;
+    uint32_t is = __shfl_up(ie, 1, 64), js = __shfl_up(je, 1, 64);
+    if (lane == 0) {
+      if (wv == 0) {
+        is = ia0;
+        js = ib0;
+      } else {  // where the previous wavefront's last lane ends
+        const uint32_t ws = d0 + wv * 64 * P;
+        const uint32_t ds = ws < d1 ? ws : d1;
+        is = g_split(A, na, B, nb, ds, d0, ia0);
+        js = ds - is;
+        if (is > 0 && js < nb && A[is - 1] == B[js]) ++js;
+      }
+    }
+    uint32_t i = is, j = js;
+    uint64_t a = i < ie ? A[i] : KEY_INF;
+    uint64_t b = j < je ? B[j] : KEY_INF;
+    uint64_t buf[P + 1];
+    uint32_t keep = 0;
+#pragma unroll
+    for (int t = 0; t <= P; ++t) {
+      buf[t] = 0;
+      if (a < b) {
+        buf[t] = a;
+        keep |= 1u << t;
+        ++i;
+        a = i < ie ? A[i] : KEY_INF;
+      } else if (b < a) {
+        buf[t] = b;
+        keep |= 1u << t;
+        ++j;
+        b = j < je ? B[j] : KEY_INF;
+      } else if (a != KEY_INF) {
+        ++i;
+        ++j;
+        a = i < ie ? A[i] : KEY_INF;
+        b = j < je ? B[j] : KEY_INF;
+      }
+    }
+    uint32_t wtot;
+    uint32_t pos = w_excl_small<(P < 8 ? 3 : (P < 16 ? 4 : 5))>((uint32_t)__popc(keep), &wtot);
+    if (lane == 0) G->cnt[wv] = wtot;
+    if (wv == GNW - 1 && lane == 63) {
+      G->end_a = ie;
+      G->end_b = je;
+    }
+    __syncthreads();
+    uint32_t before = 0, sum = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < (uint32_t)GNW; ++w) {
+      const uint32_t cw = G->cnt[w];
+      before += w < wv ? cw : 0u;
+      sum += cw;
+    }
+    pos += o + before;
+#pragma unroll
+    for (int t = 0; t <= P; ++t)
+      if (keep & (1u << t)) out[pos++] = buf[t];
+    o += sum;
+    ia0 = G->end_a;
+    ib0 = G->end_b;
+    d0 = d1;
+  }
+  __syncthreads();
+  return uni(o);
+}
+
+__device__ __forceinline__ uint64_t g_alloc(const RedCtx& R, const WaveBufs& S, uint64_t n) {
+  unsigned long long off = 0;
+  if (threadIdx.x == 0) {
+    const auto* K = cold(R);
+    n = n ? n : 1;
+    off = atomicAdd(K->arena_top, (unsigned long long)n);
+    if (off + n > K->arena_cap) {
+      raise_flag(K->st, &K->st->overflow, OVF_ARENA);
+      off = ~0ull;
+    }
+  }
+  return g_bcast(gshared(S), off);
+}
+
+__device__ __noinline__ uint32_t g_merge_lds(const WaveBufs& S, const uint64_t* A, uint32_t na, const uint64_t* B,
+                                                uint32_t nb, uint64_t* out, int lane) {
+  return g_merge<GP_LDS>(GLds{A}, na, GLds{B}, nb, out, gshared(S), lane, [](uint32_t, uint32_t) {});
+}
+__device__ __noinline__ uint32_t g_merge_tail(const WaveBufs& S, const uint64_t* T, uint32_t nt, const uint64_t* F,
+                                                 uint32_t nf, uint64_t* out, int lane) {
+  GRing<GP_TAIL> ra;
+  ra.init(S.X, T, nt);
+  return g_merge<GP_TAIL>(ra, nt, GLds{F}, nf, out, gshared(S), lane,
+                          [&](uint32_t ia, uint32_t) { ra.advance(ia); });
+}
+__device__ __noinline__ uint32_t g_merge_gg(const WaveBufs& S, const uint64_t* A, uint32_t na, const uint64_t* B,
+                                               uint32_t nb, uint64_t* out, int lane) {
+  GRing<GP_GG> ra, rb;
+  ra.init(S.X, A, na);
+  rb.init(S.X + GXN / 2, B, nb);
+  return g_merge<GP_GG>(ra, na, rb, nb, out, gshared(S), lane, [&](uint32_t ia, uint32_t ib) {
+    ra.advance(ia);
+    rb.advance(ib);
+  });
+}
+
+// T ^= U (U becomes empty).
+__device__ __forceinline__ bool g_fold_mid(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
+  if (W.U.n == 0) return true;
+  if (W.T.n == 0) {
+    W.T = W.U;
+  } else {
+    const uint64_t off = g_alloc(R, S, (uint64_t)W.T.n + W.U.n);
+    if (off == ~0ull) return false;
+    const uint32_t len = g_merge_gg(S, W.T.v, W.T.n, W.U.v, W.U.n, R.arena + off, lane);
+    w_count(W.merged, W.T.n + W.U.n, lane);
+    tail_set(W.T, R.arena + off, len, lane);
+  }
+  W.U.n = 0;
+  return true;
+}
+
+// U ^= F (F becomes empty), folding U into T first if U would outgrow mid_cap.
+__device__ __forceinline__ bool g_push_front(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
+  if (W.nf == 0) return true;
+  if (W.U.n + W.nf > cold(R)->mid_cap && !g_fold_mid(R, S, W, lane)) return false;
+  const uint64_t off = g_alloc(R, S, (uint64_t)W.U.n + W.nf);
+  if (off == ~0ull) return false;
+  const uint32_t len = g_merge_tail(S, W.U.v, W.U.n, fbuf(S, W.cur), W.nf, R.arena + off, lane);
+  w_count(W.merged, W.U.n + W.nf, lane);
+  W.nf = 0;
+  tail_set(W.U, R.arena + off, len, lane);
+  return true;
+}
+
+// F ^= X[0..m) (X in LDS), pushing F into U first if the result might not fit.
+__device__ __forceinline__ bool g_front_add(const RedCtx& R, const WaveBufs& S, WState& W, const uint64_t* X,
+                                            uint32_t m, int lane) {
+  if (W.nf + m > S.cap && !g_push_front(R, S, W, lane)) return false;
+  w_count(W.merged, W.nf + m, lane);
+  W.nf = g_merge_lds(S, fbuf(S, W.cur), W.nf, X, m, fbuf(S, W.cur ^ 1), lane);
+  W.cur ^= 1;
+  return true;
+}
+
+// F ^= P (P becomes empty); the first wavefront's copy of P is merged.
+__device__ __forceinline__ bool g_flush_p(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
+  if (W.np == 0) return true;
+  if ((uint32_t)lane < W.np) S.ps[lane] = W.p;
+  const uint32_t np = W.np;
+  W.np = 0;
+  return g_front_add(R, S, W, S.ps - (threadIdx.x >> 6) * GPRIV, np, lane);
+}
+
+__device__ __forceinline__ bool g_insert3(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t k0, uint64_t k1,
+                                          uint64_t k2, int lane) {
+  if (W.np > 61 && !g_flush_p(R, S, W, lane)) return false;
+  const bool in = (uint32_t)lane < W.np;
+  const uint64_t h0 = wballot(in && W.p == k0), h1 = wballot(in && W.p == k1), h2 = wballot(in && W.p == k2);
+  const uint64_t km = wballot(in) & ~(h0 | h1 | h2);
+  const bool n0 = h0 == 0, n1 = h1 == 0, n2 = h2 == 0;
+  const uint32_t r0 = (uint32_t)__popcll(km & wballot(W.p < k0)) + (n1 && k1 < k0) + (n2 && k2 < k0);
+  const uint32_t r1 = (uint32_t)__popcll(km & wballot(W.p < k1)) + (n0 && k0 < k1) + (n2 && k2 < k1);
+  const uint32_t r2 = (uint32_t)__popcll(km & wballot(W.p < k2)) + (n0 && k0 < k2) + (n1 && k1 < k2);
+  if ((km >> lane) & 1) S.ps[mbcnt64(km) + (n0 && k0 < W.p) + (n1 && k1 < W.p) + (n2 && k2 < W.p)] = W.p;
+  if (lane < 3 && sel3(lane, n0, n1, n2)) S.ps[sel3(lane, r0, r1, r2)] = sel3(lane, k0, k1, k2);
+  wsync();
+  W.np = (uint32_t)__popcll(km) + n0 + n1 + n2;
+  W.p = (uint32_t)lane < W.np ? S.ps[lane] : 0;
+  wsync();
+  return true;
+}
+
+struct GroupOps {
+  static constexpr uint32_t XN = GXN;
+  static constexpr uint32_t NT = GNW * 64;
+  __device__ static uint32_t tid(int lane) { return gtid(lane); }
+  __device__ static bool leader(int lane) { return gtid(lane) == 0; }
+  __device__ static void sync() { __syncthreads(); }
+  __device__ static bool aborted(const RedCtx& R, const WaveBufs& S) {
+    return g_bcast(gshared(S), threadIdx.x == 0 && cr::aborted(cold(R)->st)) != 0;
+  }
+  __device__ static uint64_t alloc(const RedCtx& R, const WaveBufs& S, uint64_t n, int) { return g_alloc(R, S, n); }
+  __device__ static bool insert3(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t k0, uint64_t k1, uint64_t k2,
+                                 int lane) {
+    return g_insert3(R, S, W, k0, k1, k2, lane);
+  }
+  __device__ static bool flush_p(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
+    return g_flush_p(R, S, W, lane);
+  }
+  __device__ static bool push_front(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
+    return g_push_front(R, S, W, lane);
+  }
+  __device__ static bool front_add(const RedCtx& R, const WaveBufs& S, WState& W, const uint64_t* X, uint32_t m,
+                                   int lane) {
+    return g_front_add(R, S, W, X, m, lane);
+  }
+  __device__ static uint32_t merge_tail(const WaveBufs& S, const uint64_t* T, uint32_t nt, const uint64_t* F,
+                                        uint32_t nf, uint64_t* out, int lane) {
+    return g_merge_tail(S, T, nt, F, nf, out, lane);
+  }
+  __device__ static uint32_t merge_gg(const WaveBufs& S, const uint64_t* A, uint32_t na, const uint64_t* B,
+                                      uint32_t nb, uint64_t* out, int lane) {
+    return g_merge_gg(S, A, na, B, nb, out, lane);
+  }
+};
+
+// Group-mode round over the same lists as the wave-mode round, when they hold
+// at most R.group_max columns (the wave-mode kernels return at once then).
+// R must stay the first parameter (see cold()).
+__global__ __launch_bounds__(64 * GNW) void k_red_round_group(RedCtx R, const uint32_t* __restrict__ list_s,
+                                                             const unsigned long long* __restrict__ n_s,
+                                                             const uint32_t* __restrict__ list_l,
+                                                             const unsigned long long* __restrict__ n_l,
+                                                             uint32_t front_cap) {
+  extern __shared__ __align__(16) uint64_t lds_words[];
+  const uint64_t nl = uni64(*n_l), ns0 = uni64(*n_s);
+  const uint64_t ns = ns0 <= R.wave_short ? ns0 : 0;
+  if (nl + ns == 0 || nl + ns > R.group_max) return;
+  const int lane = threadIdx.x & 63;
+  WaveBufs S;
+  S.cap = front_cap;
+  S.F0 = lds_words;
+  S.F1 = S.F0 + S.cap;
+  S.X = S.F1 + S.cap;
+  S.ps = S.X + GXN + (threadIdx.x >> 6) * GPRIV;
+  S.hx = S.ps + 64;
+  S.po = S.ps + 128;
+  GroupShared* G = gshared(S);
+  const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
+  WState W;
+  W.adds = 0;
+  W.merged = 0;
+  for (;;) {
+    unsigned long long li = ~0ull;
+    if (threadIdx.x == 0 && !aborted(R.st)) li = atomicAdd(R.work, 1ull);
+    li = g_bcast(G, li);
+    if (li >= nl + ns) break;
+    const uint32_t c = uni(li < nl ? list_l[li] : list_s[li - nl]);
+    reduce_column<GroupOps>(R, S, W, c, off2, lane);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && W.adds) {  // every wavefront counted the same; the first reports
     atomicAdd(&R.st->adds, W.adds);
     atomicAdd(&R.st->merged, W.merged);
   }
@@ -1224,6 +1639,8 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.mid_cap = 8192;
   R.narrow_min = 8192;
   R.narrow_cap = 256;
+  R.group_max = 256;
+  R.group_cap = 4096;
   return R;
 }
 
@@ -1250,6 +1667,12 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
   int wgrid = 0, ngrid = 0;
   const size_t lds = wave_setup<WideCfg>(R.front_cap, ncu, &wgrid);
   const size_t nlds = wave_setup<NarrowCfg>(R.narrow_cap, ncu, &ngrid);
+  const size_t glds = group_lds_bytes(R.group_cap);
+  static size_t glds_set = 0;
+  if (glds_set < glds) {
+    (void)hipFuncSetAttribute((const void*)k_red_round_group, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds);
+    glds_set = glds;
+  }
   for (int r = round0; r < round0 + nrounds; ++r) {
     const int cur = r & 1, nxt = (r + 1) & 1;
     const int first = r == 0;
@@ -1267,6 +1690,7 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
     if (!first) {
       k_red_round_wave<NarrowCfg><<<ngrid, 64 * WPB, nlds, s>>>(R, lt, ct, lb, ct + 1, R.narrow_cap);
       k_red_round_wave<WideCfg><<<wgrid, 64 * WPB, lds, s>>>(R, lt, ct, lb, ct + 1, R.front_cap);
+      k_red_round_group<<<ncu, 64 * GNW, glds, s>>>(R, lt, ct, lb, ct + 1, R.group_cap);
     }
     k_red_commit<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first, lists[2 * nxt], lists[2 * nxt + 1], cnx);
     k_red_reset<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first);

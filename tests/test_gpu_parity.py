@@ -162,18 +162,22 @@ def test_deterministic_repeat():
 
 
 WAVE_ENV = ("CR_LONG_LEN", "CR_YIELD_ITERS", "CR_WAVE_SHORT", "CR_FRONT_CAP", "CR_MID_CAP", "CR_NARROW_MIN",
-            "CR_NARROW_CAP")
+            "CR_NARROW_CAP", "CR_GROUP_MAX", "CR_GROUP_CAP")
 
 
 @pytest.mark.parametrize("setting", [
     # every column to wave mode after two additions; narrow configuration with a tiny front list
-    ("0", "2", "0", "4032", "8192", "0", "128"),
-    ("8", "8", "0", "4032", "8192", "1000000000", "256"),  # wide configuration only
+    ("0", "2", "0", "4032", "8192", "0", "128", "0", "4096"),
+    ("8", "8", "0", "4032", "8192", "1000000000", "256", "0", "4096"),  # wide configuration only
     # whole rounds in wave mode, tiny front and middle lists
-    ("0", "1", "1000000", "128", "300", "1000000000", "352"),
-    ("0", "1", "1000000", "128", "300", "0", "352"),
-    # the middle list folded into the tail at every push; both configurations
-    ("4", "4", "64", "200", "0", "64", "200"),
+    ("0", "1", "1000000", "128", "300", "1000000000", "352", "0", "4096"),
+    ("0", "1", "1000000", "128", "300", "0", "352", "0", "4096"),
+    # the middle list folded into the tail at every push; all three configurations
+    ("4", "4", "64", "200", "0", "64", "200", "16", "128"),
+    # a workgroup per column in every wave-mode round: small lists, then the defaults
+    ("0", "1", "1000000", "128", "300", "1000000000", "256", "1000000000", "128"),
+    ("0", "2", "0", "1024", "0", "1000000000", "256", "1000000000", "200"),
+    ("16", "1024", "4096", "1024", "8192", "8192", "256", "1000000000", "4096"),
 ])
 def test_wave_mode_forced(setting):
     """Volumes whose columns are handed to the wavefront-per-column mode after a
