@@ -878,10 +878,7 @@ __device__ __forceinline__ float rdlane_f(float v, uint32_t i) {
 template <class C>
 struct WaveOps {
   static constexpr uint32_t XN = C::XN;
-  static constexpr uint32_t NT = 64;  // threads that share the column
-  __device__ static uint32_t tid(int lane) { return (uint32_t)lane; }
   __device__ static bool leader(int lane) { return lane == 0; }
-  __device__ static void sync() { wsync(); }
   __device__ static bool aborted(const RedCtx& R, const WaveBufs&) { return cr::aborted(cold(R)->st); }
   __device__ static uint64_t alloc(const RedCtx& R, const WaveBufs&, uint64_t n, int lane) { return w_alloc(R, n, lane); }
   __device__ static bool insert3(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t k0, uint64_t k1, uint64_t k2,
@@ -906,11 +903,17 @@ struct WaveOps {
                                       uint32_t nb, uint64_t* out, int lane) {
     return uni(w_merge_gg<C>(S.X, A, na, B, nb, out, lane));
   }
+  __device__ static void copy_in(const WaveBufs&, uint64_t* dst, const uint64_t* src, uint32_t n, int lane) {
+    for (uint32_t i = (uint32_t)lane; i < n; i += 64) dst[i] = src[i];
+    wsync();
+  }
+  __device__ static void copy_out(const WaveBufs&, uint64_t* dst, const uint64_t* src, uint32_t n, int lane) {
+    for (uint32_t i = (uint32_t)lane; i < n; i += 64) dst[i] = src[i];
+  }
 };
 
 // Reduces column c for one round: until its pivot has no owner to its left,
-// then stores it and proposes it for its pivot.  Every wavefront that shares
-// the column runs this with the same data and so takes the same branches.
+// then stores it and proposes it for its pivot.
 template <class O>
 __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c, uint64_t off2,
                                               int lane) {
@@ -938,14 +941,13 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
       W.nf = 0;
       tail_set(W.T, src, 0, lane);
     } else if (len <= S.cap) {
-      for (uint32_t i = O::tid(lane); i < len; i += O::NT) S.F0[i] = src[i];
+      O::copy_in(S, S.F0, src, len, lane);
       W.nf = len;
       tail_set(W.T, src, 0, lane);
     } else {
       W.nf = 0;
       tail_set(W.T, src, len, lane);
     }
-    O::sync();
   }
   for (uint32_t it = 0;; ++it) {
     if (it >= RED_ITER_CAP) {
@@ -1037,8 +1039,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
         for (uint32_t base = 0; base < m; base += pmax) {
           const uint32_t piece = m - base < pmax ? m - base : pmax;
           if (W.nf + piece > S.cap && !O::push_front(R, S, W, lane)) return;
-          for (uint32_t i = O::tid(lane); i < piece; i += O::NT) S.X[i] = q[1 + base + i];
-          O::sync();
+          O::copy_in(S, S.X, q + 1 + base, piece, lane);
           if (!O::front_add(R, S, W, S.X, piece, lane)) return;
         }
       }
@@ -1052,7 +1053,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
     if (W.nf == 0 && W.U.n == 0 && W.T.n == 0) {  // the column is P
       const uint64_t off = O::alloc(R, S, (uint64_t)W.np + 1, lane);
       if (off == ~0ull) return;
-      if (O::tid(lane) < W.np) R.arena[off + 1 + lane] = W.p;
+      if ((uint32_t)lane < W.np) R.arena[off + 1 + lane] = W.p;
       if (O::leader(lane)) {
         R.arena[off] = W.np;
         const auto* K = cold(R);
@@ -1074,7 +1075,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
     } else if (G.n) {
       len = O::merge_tail(S, G.v, G.n, fbuf(S, W.cur), W.nf, R.arena + off + 1, lane);
     } else {
-      for (uint32_t i = O::tid(lane); i < W.nf; i += O::NT) R.arena[off + 1 + i] = fbuf(S, W.cur)[i];
+      O::copy_out(S, R.arena + off + 1, fbuf(S, W.cur), W.nf, lane);
       len = W.nf;
     }
     if (O::leader(lane)) {
@@ -1134,51 +1135,52 @@ __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uin
   }
 }
 
-// ---- group mode: one workgroup of NW wavefronts per column ---------------------------
+// ---- group mode: one workgroup of GNW wavefronts per column ---------------------------
 //
-// For rounds with few columns.  Every wavefront runs reduce_column with the
-// same data, so each holds the same P, windows and counts; the merges of F, U
-// and T -- the bulk of a long column's work -- are split between the
-// wavefronts: a merge advances in steps of NW * 64 * P positions, each
-// wavefront taking a contiguous part of the step (lane splits by merge path
-// over the whole lists, restricted to what the step can reach), and the
-// wavefronts' output counts are combined through LDS before writing.  Arena
-// inputs stream through rings of four chunks of one step's size (the chunks
-// before, at and after the step's start resident, the next one loading into
-// registers).  Arena allocation, the column counter and the abort test are
-// done once and broadcast, so that no wavefront can take another branch.
+// For rounds with few columns.  The first wavefront (the leader) reduces the
+// column as in wave mode and alone holds P, the windows and the counts; the
+// other wavefronts wait at a barrier and join it for the operations that carry
+// the bulk of a long column's work: the merges of F, U and T, and the copies
+// between LDS and the arena.  The leader describes each such operation in LDS
+// and the whole workgroup runs it.  A merge advances in steps of GNW * 64 * P
+// positions, each wavefront taking a contiguous part of the step (lane splits
+// by merge path over the whole lists, restricted to what the step can reach);
+// the wavefronts' output counts are combined through LDS before writing.
+// Arena inputs stream through rings of four chunks of one step's size (the
+// chunks before, at and after the step's start resident, the next one loading
+// into registers).
 constexpr int GNW = 8;              // wavefronts per group
 constexpr int GP_LDS = 4;           // merge positions per lane per step: LDS lists
 constexpr int GP_TAIL = 4;          // ... an arena list with an LDS list
 constexpr int GP_GG = 2;            // ... two arena lists
 constexpr uint32_t GXN = 4 * GNW * 64 * GP_TAIL;  // stage words: one ring of four chunks (two rings for GP_GG)
 static_assert(2 * 4 * GNW * 64 * GP_GG == GXN, "the two rings of an arena-arena merge fill the stage");
-constexpr uint32_t GPRIV = 64 + 64 + 128;  // words per wavefront: ps, hx, po
+constexpr uint32_t GPRIV = 64 + 64 + 128;  // the leader's ps, hx, po
+
+enum GOp : uint32_t { G_END = 0, G_MERGE_LDS, G_MERGE_TAIL, G_MERGE_GG, G_COPY_IN, G_COPY_OUT };
+// An operation for the whole group: LDS operands are word offsets from the
+// start of the group's LDS, arena operands are addresses.
+struct GDesc {
+  uint32_t op, na, nb, pad;
+  uint64_t a, b, out;
+};
 struct GroupShared {
   uint32_t cnt[GNW];   // output counts of the wavefronts in a merge step
   uint32_t end_a, end_b;
-  unsigned long long bc;  // broadcast word
+  GDesc desc;
 };
 __host__ __device__ __forceinline__ size_t group_lds_bytes(uint32_t cap) {
-  return 8 * (2 * (size_t)cap + GXN + (size_t)GNW * GPRIV) + sizeof(GroupShared);
+  return 8 * (2 * (size_t)cap + GXN + GPRIV) + sizeof(GroupShared);
 }
-constexpr uint32_t FRONT_CAP_GROUP_MAX = 4096;
-static_assert(8 * (2 * FRONT_CAP_GROUP_MAX + GXN + GNW * GPRIV) + sizeof(GroupShared) <= 160 * 1024,
+// the largest front list that fits the LDS of a workgroup with the rest
+constexpr uint32_t FRONT_CAP_GROUP_MAX =
+    (uint32_t)(((160 * 1024 - sizeof(GroupShared)) / 8 - GXN - GPRIV) / 2) & ~63u;
+static_assert(FRONT_CAP_GROUP_MAX >= FRONT_CAP_MIN, "group mode LDS leaves no room for the front list");
+static_assert(8 * (2 * FRONT_CAP_GROUP_MAX + GXN + GPRIV) + sizeof(GroupShared) <= 160 * 1024,
               "group mode LDS exceeds a workgroup's share");
 
 __device__ __forceinline__ GroupShared* gshared(const WaveBufs& S) {
-  return reinterpret_cast<GroupShared*>(S.X + GXN + GNW * GPRIV);
-}
-__device__ __forceinline__ uint32_t gtid(int lane) { return (threadIdx.x & ~63u) + (uint32_t)lane; }
-
-// Thread 0's value of v, in every thread of the workgroup.
-__device__ __forceinline__ uint64_t g_bcast(GroupShared* G, uint64_t v) {
-  __syncthreads();
-  if (threadIdx.x == 0) G->bc = v;
-  __syncthreads();
-  const uint64_t r = uni64(G->bc);
-  __syncthreads();
-  return r;
+  return reinterpret_cast<GroupShared*>(S.X + GXN + GPRIV);
 }
 
 // Merge-path split at position d, knowing that the split at d0 <= d took ia0
@@ -1199,7 +1201,7 @@ __device__ __forceinline__ uint32_t g_split(const AA& A, uint32_t na, const BB& 
 }
 
 // A sorted arena list streamed through a ring of four chunks of CH keys; the
-// workgroup loads chunk c with P keys per thread.
+// workgroup loads a chunk with P keys per thread.
 template <int P>
 struct GRing {
   static constexpr uint32_t CH = GNW * 64 * P;
@@ -1248,8 +1250,7 @@ struct GLds {
 
 // out = A XOR B by the whole workgroup, in steps of GNW * 64 * P positions;
 // pre(ia, ib) runs at the start of each step (the keys of A and B consumed so
-// far) to make what the step reads resident.  Returns the number written
-// (the same in every thread).
+// far) to make what the step reads resident.  Returns the number written.
 template <int P, class AA, class BB, class Pre>
 __device__ __forceinline__ uint32_t g_merge(const AA& A, uint32_t na, const BB& B, uint32_t nb, uint64_t* out,
                                             GroupShared* G, int lane, Pre pre) {
@@ -1332,41 +1333,57 @@ __device__ __forceinline__ uint32_t g_merge(const AA& A, uint32_t na, const BB& 
   return uni(o);
 }
 
-__device__ __forceinline__ uint64_t g_alloc(const RedCtx& R, const WaveBufs& S, uint64_t n) {
-  unsigned long long off = 0;
-  if (threadIdx.x == 0) {
-    const auto* K = cold(R);
-    n = n ? n : 1;
-    off = atomicAdd(K->arena_top, (unsigned long long)n);
-    if (off + n > K->arena_cap) {
-      raise_flag(K->st, &K->st->overflow, OVF_ARENA);
-      off = ~0ull;
-    }
+// Runs operation d with the whole workgroup; returns the keys written.
+__device__ __noinline__ uint32_t g_run(const WaveBufs& S, uint32_t op, uint32_t na, uint32_t nb, uint64_t a,
+                                       uint64_t b, uint64_t out, int lane) {
+  GroupShared* G = gshared(S);
+  uint64_t* L = S.F0;  // the start of the group's LDS
+  if (op == G_MERGE_LDS) {
+    return g_merge<GP_LDS>(GLds{L + a}, na, GLds{L + b}, nb, L + out, G, lane, [](uint32_t, uint32_t) {});
   }
-  return g_bcast(gshared(S), off);
+  if (op == G_MERGE_TAIL) {
+    GRing<GP_TAIL> ra;
+    ra.init(S.X, reinterpret_cast<const uint64_t*>(a), na);
+    return g_merge<GP_TAIL>(ra, na, GLds{L + b}, nb, reinterpret_cast<uint64_t*>(out), G, lane,
+                            [&](uint32_t ia, uint32_t) { ra.advance(ia); });
+  }
+  if (op == G_MERGE_GG) {
+    GRing<GP_GG> ra, rb;
+    ra.init(S.X, reinterpret_cast<const uint64_t*>(a), na);
+    rb.init(S.X + GXN / 2, reinterpret_cast<const uint64_t*>(b), nb);
+    return g_merge<GP_GG>(ra, na, rb, nb, reinterpret_cast<uint64_t*>(out), G, lane, [&](uint32_t ia, uint32_t ib) {
+      ra.advance(ia);
+      rb.advance(ib);
+    });
+  }
+  if (op == G_COPY_IN) {
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(a);
+    for (uint32_t i = threadIdx.x; i < na; i += GNW * 64) L[out + i] = src[i];
+  } else {  // G_COPY_OUT
+    uint64_t* dst = reinterpret_cast<uint64_t*>(out);
+    for (uint32_t i = threadIdx.x; i < na; i += GNW * 64) dst[i] = L[a + i];
+  }
+  __syncthreads();
+  return na;
 }
 
-__device__ __noinline__ uint32_t g_merge_lds(const WaveBufs& S, const uint64_t* A, uint32_t na, const uint64_t* B,
-                                                uint32_t nb, uint64_t* out, int lane) {
-  return g_merge<GP_LDS>(GLds{A}, na, GLds{B}, nb, out, gshared(S), lane, [](uint32_t, uint32_t) {});
+// The leader posts an operation and runs it with the other wavefronts.
+__device__ __forceinline__ uint32_t g_issue(const WaveBufs& S, uint32_t op, uint32_t na, uint32_t nb, uint64_t a,
+                                            uint64_t b, uint64_t out, int lane) {
+  GroupShared* G = gshared(S);
+  if (lane == 0) {
+    G->desc.op = op;
+    G->desc.na = na;
+    G->desc.nb = nb;
+    G->desc.a = a;
+    G->desc.b = b;
+    G->desc.out = out;
+  }
+  __syncthreads();
+  return uni(g_run(S, op, na, nb, a, b, out, lane));
 }
-__device__ __noinline__ uint32_t g_merge_tail(const WaveBufs& S, const uint64_t* T, uint32_t nt, const uint64_t* F,
-                                                 uint32_t nf, uint64_t* out, int lane) {
-  GRing<GP_TAIL> ra;
-  ra.init(S.X, T, nt);
-  return g_merge<GP_TAIL>(ra, nt, GLds{F}, nf, out, gshared(S), lane,
-                          [&](uint32_t ia, uint32_t) { ra.advance(ia); });
-}
-__device__ __noinline__ uint32_t g_merge_gg(const WaveBufs& S, const uint64_t* A, uint32_t na, const uint64_t* B,
-                                               uint32_t nb, uint64_t* out, int lane) {
-  GRing<GP_GG> ra, rb;
-  ra.init(S.X, A, na);
-  rb.init(S.X + GXN / 2, B, nb);
-  return g_merge<GP_GG>(ra, na, rb, nb, out, gshared(S), lane, [&](uint32_t ia, uint32_t ib) {
-    ra.advance(ia);
-    rb.advance(ib);
-  });
-}
+__device__ __forceinline__ uint64_t loff(const WaveBufs& S, const uint64_t* p) { return (uint64_t)(p - S.F0); }
+__device__ __forceinline__ uint64_t gaddr(const uint64_t* p) { return (uint64_t)(uintptr_t)p; }
 
 // T ^= U (U becomes empty).
 __device__ __forceinline__ bool g_fold_mid(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
@@ -1374,9 +1391,9 @@ __device__ __forceinline__ bool g_fold_mid(const RedCtx& R, const WaveBufs& S, W
   if (W.T.n == 0) {
     W.T = W.U;
   } else {
-    const uint64_t off = g_alloc(R, S, (uint64_t)W.T.n + W.U.n);
+    const uint64_t off = w_alloc(R, (uint64_t)W.T.n + W.U.n, lane);
     if (off == ~0ull) return false;
-    const uint32_t len = g_merge_gg(S, W.T.v, W.T.n, W.U.v, W.U.n, R.arena + off, lane);
+    const uint32_t len = g_issue(S, G_MERGE_GG, W.T.n, W.U.n, gaddr(W.T.v), gaddr(W.U.v), gaddr(R.arena + off), lane);
     w_count(W.merged, W.T.n + W.U.n, lane);
     tail_set(W.T, R.arena + off, len, lane);
   }
@@ -1388,9 +1405,10 @@ __device__ __forceinline__ bool g_fold_mid(const RedCtx& R, const WaveBufs& S, W
 __device__ __forceinline__ bool g_push_front(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
   if (W.nf == 0) return true;
   if (W.U.n + W.nf > cold(R)->mid_cap && !g_fold_mid(R, S, W, lane)) return false;
-  const uint64_t off = g_alloc(R, S, (uint64_t)W.U.n + W.nf);
+  const uint64_t off = w_alloc(R, (uint64_t)W.U.n + W.nf, lane);
   if (off == ~0ull) return false;
-  const uint32_t len = g_merge_tail(S, W.U.v, W.U.n, fbuf(S, W.cur), W.nf, R.arena + off, lane);
+  const uint32_t len = g_issue(S, G_MERGE_TAIL, W.U.n, W.nf, gaddr(W.U.v), loff(S, fbuf(S, W.cur)),
+                               gaddr(R.arena + off), lane);
   w_count(W.merged, W.U.n + W.nf, lane);
   W.nf = 0;
   tail_set(W.U, R.arena + off, len, lane);
@@ -1402,18 +1420,18 @@ __device__ __forceinline__ bool g_front_add(const RedCtx& R, const WaveBufs& S, 
                                             uint32_t m, int lane) {
   if (W.nf + m > S.cap && !g_push_front(R, S, W, lane)) return false;
   w_count(W.merged, W.nf + m, lane);
-  W.nf = g_merge_lds(S, fbuf(S, W.cur), W.nf, X, m, fbuf(S, W.cur ^ 1), lane);
+  W.nf = g_issue(S, G_MERGE_LDS, W.nf, m, loff(S, fbuf(S, W.cur)), loff(S, X), loff(S, fbuf(S, W.cur ^ 1)), lane);
   W.cur ^= 1;
   return true;
 }
 
-// F ^= P (P becomes empty); the first wavefront's copy of P is merged.
+// F ^= P (P becomes empty).
 __device__ __forceinline__ bool g_flush_p(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
   if (W.np == 0) return true;
   if ((uint32_t)lane < W.np) S.ps[lane] = W.p;
   const uint32_t np = W.np;
   W.np = 0;
-  return g_front_add(R, S, W, S.ps - (threadIdx.x >> 6) * GPRIV, np, lane);
+  return g_front_add(R, S, W, S.ps, np, lane);
 }
 
 __device__ __forceinline__ bool g_insert3(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t k0, uint64_t k1,
@@ -1435,16 +1453,12 @@ __device__ __forceinline__ bool g_insert3(const RedCtx& R, const WaveBufs& S, WS
   return true;
 }
 
+// The leader's side of the column steps.
 struct GroupOps {
   static constexpr uint32_t XN = GXN;
-  static constexpr uint32_t NT = GNW * 64;
-  __device__ static uint32_t tid(int lane) { return gtid(lane); }
-  __device__ static bool leader(int lane) { return gtid(lane) == 0; }
-  __device__ static void sync() { __syncthreads(); }
-  __device__ static bool aborted(const RedCtx& R, const WaveBufs& S) {
-    return g_bcast(gshared(S), threadIdx.x == 0 && cr::aborted(cold(R)->st)) != 0;
-  }
-  __device__ static uint64_t alloc(const RedCtx& R, const WaveBufs& S, uint64_t n, int) { return g_alloc(R, S, n); }
+  __device__ static bool leader(int lane) { return lane == 0; }
+  __device__ static bool aborted(const RedCtx& R, const WaveBufs&) { return cr::aborted(cold(R)->st); }
+  __device__ static uint64_t alloc(const RedCtx& R, const WaveBufs&, uint64_t n, int lane) { return w_alloc(R, n, lane); }
   __device__ static bool insert3(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t k0, uint64_t k1, uint64_t k2,
                                  int lane) {
     return g_insert3(R, S, W, k0, k1, k2, lane);
@@ -1461,11 +1475,17 @@ struct GroupOps {
   }
   __device__ static uint32_t merge_tail(const WaveBufs& S, const uint64_t* T, uint32_t nt, const uint64_t* F,
                                         uint32_t nf, uint64_t* out, int lane) {
-    return g_merge_tail(S, T, nt, F, nf, out, lane);
+    return g_issue(S, G_MERGE_TAIL, nt, nf, gaddr(T), loff(S, F), gaddr(out), lane);
   }
   __device__ static uint32_t merge_gg(const WaveBufs& S, const uint64_t* A, uint32_t na, const uint64_t* B,
                                       uint32_t nb, uint64_t* out, int lane) {
-    return g_merge_gg(S, A, na, B, nb, out, lane);
+    return g_issue(S, G_MERGE_GG, na, nb, gaddr(A), gaddr(B), gaddr(out), lane);
+  }
+  __device__ static void copy_in(const WaveBufs& S, uint64_t* dst, const uint64_t* src, uint32_t n, int lane) {
+    g_issue(S, G_COPY_IN, n, 0, gaddr(src), 0, loff(S, dst), lane);
+  }
+  __device__ static void copy_out(const WaveBufs& S, uint64_t* dst, const uint64_t* src, uint32_t n, int lane) {
+    g_issue(S, G_COPY_OUT, n, 0, loff(S, src), 0, gaddr(dst), lane);
   }
 };
 
@@ -1487,24 +1507,34 @@ __global__ __launch_bounds__(64 * GNW) void k_red_round_group(RedCtx R, const ui
   S.F0 = lds_words;
   S.F1 = S.F0 + S.cap;
   S.X = S.F1 + S.cap;
-  S.ps = S.X + GXN + (threadIdx.x >> 6) * GPRIV;
+  S.ps = S.X + GXN;
   S.hx = S.ps + 64;
   S.po = S.ps + 128;
   GroupShared* G = gshared(S);
+  if (threadIdx.x >= 64) {  // helpers: run what the leader posts until it posts the end
+    for (;;) {
+      __syncthreads();
+      const uint32_t op = uni(G->desc.op);
+      if (op == G_END) return;
+      g_run(S, op, uni(G->desc.na), uni(G->desc.nb), uni64(G->desc.a), uni64(G->desc.b), uni64(G->desc.out), lane);
+    }
+  }
   const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
   WState W;
   W.adds = 0;
   W.merged = 0;
   for (;;) {
-    unsigned long long li = ~0ull;
-    if (threadIdx.x == 0 && !aborted(R.st)) li = atomicAdd(R.work, 1ull);
-    li = g_bcast(G, li);
-    if (li >= nl + ns) break;
+    unsigned long long li = 0;
+    if (lane == 0) li = atomicAdd(R.work, 1ull);
+    li = rdlane64(li, 0);
+    if (li >= nl + ns || aborted(R.st)) break;
     const uint32_t c = uni(li < nl ? list_l[li] : list_s[li - nl]);
     reduce_column<GroupOps>(R, S, W, c, off2, lane);
-    __syncthreads();
+    wsync();
   }
-  if (threadIdx.x == 0 && W.adds) {  // every wavefront counted the same; the first reports
+  if (lane == 0) G->desc.op = G_END;
+  __syncthreads();
+  if (lane == 0 && W.adds) {
     atomicAdd(&R.st->adds, W.adds);
     atomicAdd(&R.st->merged, W.merged);
   }
@@ -1639,8 +1669,8 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.mid_cap = 8192;
   R.narrow_min = 8192;
   R.narrow_cap = 256;
-  R.group_max = 256;
-  R.group_cap = 4096;
+  R.group_max = 1024;
+  R.group_cap = 2048;
   return R;
 }
 
@@ -1667,7 +1697,8 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
   int wgrid = 0, ngrid = 0;
   const size_t lds = wave_setup<WideCfg>(R.front_cap, ncu, &wgrid);
   const size_t nlds = wave_setup<NarrowCfg>(R.narrow_cap, ncu, &ngrid);
-  const size_t glds = group_lds_bytes(R.group_cap);
+  const uint32_t gcap = R.group_cap < FRONT_CAP_GROUP_MAX ? R.group_cap : FRONT_CAP_GROUP_MAX;
+  const size_t glds = group_lds_bytes(gcap);
   static size_t glds_set = 0;
   if (glds_set < glds) {
     (void)hipFuncSetAttribute((const void*)k_red_round_group, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds);
@@ -1690,7 +1721,7 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
     if (!first) {
       k_red_round_wave<NarrowCfg><<<ngrid, 64 * WPB, nlds, s>>>(R, lt, ct, lb, ct + 1, R.narrow_cap);
       k_red_round_wave<WideCfg><<<wgrid, 64 * WPB, lds, s>>>(R, lt, ct, lb, ct + 1, R.front_cap);
-      k_red_round_group<<<ncu, 64 * GNW, glds, s>>>(R, lt, ct, lb, ct + 1, R.group_cap);
+      k_red_round_group<<<ncu, 64 * GNW, glds, s>>>(R, lt, ct, lb, ct + 1, gcap);
     }
     k_red_commit<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first, lists[2 * nxt], lists[2 * nxt + 1], cnx);
     k_red_reset<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first);
