@@ -926,8 +926,23 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
   }
   d.pix_off = (int64_t)uni64((uint64_t)d.pix_off);
   const uint32_t K1 = (uint32_t)d.K[1], K2 = (uint32_t)d.K[2];
-  const int64_t ps0 = (int64_t)d.n[1] * d.n[2], ps1 = d.n[2];
+  // pixel and edge indices within the image fit 32 bits (an image has fewer
+  // than 2^27 pixels: its Khalimsky index fits the key's index field)
+  const uint32_t n0 = (uint32_t)d.n[0], n1 = (uint32_t)d.n[1], n2 = (uint32_t)d.n[2];
+  const uint32_t ps0 = n1 * n2, ps1 = n2;
   const uint32_t ks0 = K1 * K2, ks1 = K2;
+  const float* imgp = cold(R)->img + d.pix_off;
+  const uint8_t* eappp = cold(R)->eapp + 3 * d.pix_off;
+  const uint64_t* ownp = cold(R)->owner + 3 * d.pix_off;
+  const uint64_t kpre = make_skey(R.L, 1, im, 0, 0);  // the dimension and image fields of an edge key
+  // lane roles in the load group: 0 and 1 the edge's endpoints, 2..9 the far
+  // vertices of the four squares around it (lane 2 + 4h + 2s + o: the other
+  // axis h, side s, endpoint o)
+  const uint32_t lq = (uint32_t)lane - 2;
+  const bool lfar = lane >= 2 && lane < 10;
+  const bool lhi = (lq & 4) != 0;
+  const bool lodd = (lq & 1) != 0;
+  const int lsg = (lq & 2) ? 1 : -1;
   {
     const uint64_t off = uni64(cold(R)->col_ptr[c]);
     const uint32_t len = uni((uint32_t)R.arena[off]);
@@ -965,53 +980,42 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
     const uint32_t kidx = skey_kidx(R.L, e);
     const uint32_t kx = kidx % K2, t1 = kidx / K2;
     const uint32_t ky = t1 % K1, kz = t1 / K1;
-    if ((e >> (R.L.ib + 32 + R.L.kb)) != 1 || skey_img(R.L, e) != im || kz >= (uint32_t)d.K[0] ||
+    if ((e >> R.L.kb >> 32) != (kpre >> R.L.kb >> 32) || kz >= (uint32_t)d.K[0] ||
         ((kz & 1) + (ky & 1) + (kx & 1)) != 1) {  // not an edge of this image: a broken invariant
       if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->internal);
       return;
     }
     const int ax = (kz & 1) ? 0 : ((ky & 1) ? 1 : 2);
     const int b0 = ax == 0 ? 1 : 0, b1 = ax == 2 ? 1 : 2;  // the two other axes
-    const int64_t pax = sel3(ax, ps0, ps1, (int64_t)1);
+    const uint32_t cz = kz >> 1, cy = ky >> 1, cx = kx >> 1;
+    const uint32_t pax = sel3(ax, ps0, ps1, 1u);
     const uint32_t kax = sel3(ax, ks0, ks1, 1u);
-    const int64_t anchor = pixel_index(d, (int)(kz >> 1), (int)(ky >> 1), (int)(kx >> 1));
-    const int64_t slot = 3 * anchor + ax;
-    // one group of loads: lanes 0/1 the edge's endpoints, lanes 2..9 the far
-    // vertices of the four squares around it, lane 10 the apparent code, lane 11
-    // the owner word
-    int64_t p = anchor;
-    bool pix_ok = lane < 10;
-    if (lane == 1) {
-      p += pax;
-    } else if (lane >= 2 && lane < 10) {
-      const int q = lane - 2;
-      const int bb = (q >> 2) ? b1 : b0;
-      const int sg = (q & 2) ? 1 : -1;
-      const int vb = (int)(sel3(bb, kz, ky, kx) >> 1) + sg;
-      pix_ok = vb >= 0 && vb < sel3(bb, d.n[0], d.n[1], d.n[2]);
-      p += (q & 1) * pax + sg * sel3(bb, ps0, ps1, (int64_t)1);
-    }
-    // raw loads first, every use after them, so that the three are in flight together
-    float praw = 0.0f;
-    uint32_t code = 0xFF;
-    uint64_t ow = NO_OWNER;
-    if (pix_ok) praw = R.img[p];
-    if (lane == 10) code = R.eapp[slot];
-    if (lane == 11) ow = R.owner[slot];
+    const uint32_t anchor = cz * ps0 + cy * ps1 + cx;
+    const uint32_t slot = 3 * anchor + (uint32_t)ax;
+    // one group of loads: this lane's vertex (lanes past 9, and vertices off
+    // the image, read the anchor), the apparent code and the owner word (the
+    // same address in every lane)
+    const int bb = lhi ? b1 : b0;
+    const uint32_t vb = sel3(bb, cz, cy, cx) + (uint32_t)lsg;  // wraps below 0
+    const bool pix_ok = lane < 2 || (lfar && vb < sel3(bb, n0, n1, n2));
+    const uint32_t pofs = ((lane == 1 || (lfar && lodd)) ? pax : 0u) +
+                          (lfar ? (uint32_t)(lsg * (int32_t)sel3(bb, ps0, ps1, 1u)) : 0u);
+    const float praw = imgp[pix_ok ? anchor + pofs : anchor];
+    const uint32_t code = uni((uint32_t)eappp[slot]);
+    const uint64_t ow = uni64(ownp[slot]);
     const float pv = (praw != praw) ? INFINITY : canon(praw);
-    code = (uint32_t)__builtin_amdgcn_readlane((int)code, 10);
     w_count(W.adds, 1, lane);
     if (code != 0xFF) {
       // apparent partner s: its boundary is e and three older edges
-      const int bb = (int)(code >> 1);
+      const int pb = (int)(code >> 1);
       const int sg = (code & 1) ? 1 : -1;
-      const int q = 2 + ((bb == b1) ? 4 : 0) + (sg > 0 ? 2 : 0);
+      const int q = 2 + ((pb == b1) ? 4 : 0) + (sg > 0 ? 2 : 0);
       const float v0 = rdlane_f(pv, 0), v1 = rdlane_f(pv, 1);
       const float w0 = rdlane_f(pv, (uint32_t)q), w1 = rdlane_f(pv, (uint32_t)q + 1);
-      const uint32_t kb = (uint32_t)((int)sel3(bb, ks0, ks1, 1u) * sg);
-      const uint64_t kw = make_skey(R.L, 1, im, ord_of(fmaxf(w0, w1)), kidx + 2 * kb);
-      const uint64_t ka0 = make_skey(R.L, 1, im, ord_of(fmaxf(v0, w0)), kidx - kax + kb);
-      const uint64_t ka1 = make_skey(R.L, 1, im, ord_of(fmaxf(v1, w1)), kidx + kax + kb);
+      const uint32_t kb = (uint32_t)((int)sel3(pb, ks0, ks1, 1u) * sg);
+      const uint64_t kw = kpre | ((uint64_t)ord_of(fmaxf(w0, w1)) << R.L.kb) | (kidx + 2 * kb);
+      const uint64_t ka0 = kpre | ((uint64_t)ord_of(fmaxf(v0, w0)) << R.L.kb) | (kidx - kax + kb);
+      const uint64_t ka1 = kpre | ((uint64_t)ord_of(fmaxf(v1, w1)) << R.L.kb) | (kidx + kax + kb);
       if (kw >= e || ka0 >= e || ka1 >= e) {  // e must be the latest facet of s
         if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->internal);
         return;
@@ -1020,7 +1024,6 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
       if (!O::insert3(R, S, W, kw, ka0, ka1, lane)) return;
       continue;
     }
-    ow = rdlane64(ow, 11);
     const int32_t o = ow == NO_OWNER ? -1 : (int32_t)(ow >> 32);
     if (o >= 0 && (uint32_t)o < c) {  // add the column of o (its top key is e)
       const uint64_t* q = R.arena + (uint32_t)ow;
@@ -1059,7 +1062,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
         const auto* K = cold(R);
         K->col_ptr[c] = off;
         K->piv[c] = e;
-        atomicMin(&K->claim[slot], (int32_t)c);
+        atomicMin(&K->claim[3 * d.pix_off + slot], (int32_t)c);
       }
       return;
     }
@@ -1083,7 +1086,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
       const auto* K = cold(R);
       K->col_ptr[c] = off;
       K->piv[c] = e;
-      atomicMin(&K->claim[slot], (int32_t)c);
+      atomicMin(&K->claim[3 * d.pix_off + slot], (int32_t)c);
     }
     return;
   }
