@@ -40,7 +40,7 @@ constexpr uint64_t ARENA_SLACK = 64;       // readable entries past the arena en
 constexpr uint64_t ARENA_MAX = (1ull << 32) - ARENA_SLACK;  // offsets fit the low half of an owner word
 constexpr uint32_t FRONT_CAP_MIN = 128;    // wave-mode LDS front list capacity bounds
 constexpr uint32_t FRONT_CAP_MAX = 4032;  // two wavefronts' front lists, stage and pending list fit 160 KiB of LDS
-constexpr uint32_t FRONT_CAP_NARROW_MAX = 352;  // narrow configuration: eight two-wave workgroups per CU
+constexpr uint32_t FRONT_CAP_NARROW_MAX = 320;  // narrow configuration: eight two-wave workgroups per CU
 
 RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64_t* skeys,
                    const unsigned long long* dim_count, const uint8_t* cleared, const uint8_t* eapp,

@@ -365,8 +365,9 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
 //
 // The working column is the XOR of four sorted lists, each level absorbing the
 // one before it when that fills (a log-structured merge):
-//   P -- at most 64 keys in registers, lane i holding the i-th smallest; the
-//        three new edges of an apparent addition and short owner columns go here;
+//   P -- at most 128 keys in registers, lane i holding the i-th and the
+//        (64 + i)-th smallest; the three new edges of an apparent addition and
+//        short owner columns go here;
 //   F -- the front list in this wavefront's LDS (at most front_cap keys), which
 //        absorbs P when it fills and owner columns of up to a stage of keys;
 //   U -- the middle list in the arena, which absorbs F when F fills, and is
@@ -390,6 +391,7 @@ constexpr int WPB = 2;                 // wavefronts per workgroup
 constexpr int PER_WIDE = 16;           // merge positions per lane per step of a long LDS merge
 constexpr int PER_NARROW = 2;          // ... of a merge of at most 128 keys
 constexpr uint64_t KEY_INF = ~0ull;    // above every key
+constexpr uint32_t PCAP = 128;         // keys of P: two per lane
 template <int PER_>
 struct WaveCfg {
   static constexpr int PER = PER_;              // merge positions per lane per step of a merge with an arena list
@@ -400,20 +402,20 @@ struct WaveCfg {
 };
 using WideCfg = WaveCfg<8>;
 using NarrowCfg = WaveCfg<2>;
-static_assert(WPB * 8 * (2 * FRONT_CAP_MAX + WideCfg::XN + 64) <= 160 * 1024, "wave-mode LDS exceeds a workgroup's share");
-static_assert(WPB * 8 * (2 * FRONT_CAP_NARROW_MAX + NarrowCfg::XN + 64) * 8 <= 160 * 1024,
+static_assert(WPB * 8 * (2 * FRONT_CAP_MAX + WideCfg::XN + PCAP) <= 160 * 1024, "wave-mode LDS exceeds a workgroup's share");
+static_assert(WPB * 8 * (2 * FRONT_CAP_NARROW_MAX + NarrowCfg::XN + PCAP) * 8 <= 160 * 1024,
               "narrow wave mode: eight workgroups per CU");
 
 template <class C>
-__host__ __device__ __forceinline__ size_t wave_lds_words(uint32_t front_cap) { return 2 * (size_t)front_cap + C::XN + 64; }
+__host__ __device__ __forceinline__ size_t wave_lds_words(uint32_t front_cap) { return 2 * (size_t)front_cap + C::XN + PCAP; }
 
 struct WaveBufs {
   uint64_t* F0;      // the two front buffers (the front list and its merge target)
   uint64_t* F1;
   uint64_t* X;       // the stage
-  uint64_t* ps;      // 64 words: P staged for a merge
+  uint64_t* ps;      // PCAP words: P staged for a merge
   uint64_t* hx;      // 64 words: a short owner column staged for a merge into P
-  uint64_t* po;      // 128 words: the output of that merge (null: F's spare buffer)
+  uint64_t* po;      // PCAP words: the output of that merge (null: F's spare buffer)
   uint32_t cap;
 };
 
@@ -440,7 +442,7 @@ __device__ __forceinline__ KargCtx* cold(const RedCtx&) {
 }
 
 struct WState {
-  uint64_t p;        // this lane's pending key (lane < np)
+  uint64_t p0, p1;   // P: this lane's keys lane and 64 + lane (below np)
   Tail U, T;
   uint32_t np, nf, cur;
   unsigned long long adds, merged;  // statistics, counted in lane 0 (vector registers)
@@ -476,6 +478,50 @@ __device__ __forceinline__ uint64_t wballot(bool c) { return __builtin_amdgcn_ba
 // Number of set bits of m below this lane.
 __device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// ---- P, the register list: key i in lane i (i < 64) or lane i - 64 of p1 ----
+__device__ __forceinline__ uint64_t p_top(const WState& W) {
+  return W.np == 0 ? 0 : (W.np <= 64 ? rdlane64(W.p0, W.np - 1) : rdlane64(W.p1, W.np - 65));
+}
+// Writes P ascending to dst[0..np).
+__device__ __forceinline__ void p_stage(const WState& W, uint64_t* dst, int lane) {
+  if ((uint32_t)lane < W.np) dst[lane] = W.p0;
+  if ((uint32_t)lane + 64 < W.np) dst[64 + lane] = W.p1;
+}
+// P = src[0..n), n <= PCAP.
+__device__ __forceinline__ void p_load(WState& W, const uint64_t* src, uint32_t n, int lane) {
+  W.p0 = (uint32_t)lane < n ? src[lane] : 0;
+  W.p1 = (uint32_t)lane + 64 < n ? src[64 + lane] : 0;
+  W.np = n;
+}
+// P ^= {k0, k1, k2} for three distinct wave-uniform keys, P holding at most
+// PCAP - 3 keys: each kept key and each new key goes to its rank through the
+// LDS slot ps, with no branches on the data.
+__device__ __forceinline__ void p_insert3(const WaveBufs& S, WState& W, uint64_t k0, uint64_t k1, uint64_t k2,
+                                          int lane) {
+  const bool in0 = (uint32_t)lane < W.np, in1 = (uint32_t)lane + 64 < W.np;
+  const bool h0 = (wballot(in0 && W.p0 == k0) | wballot(in1 && W.p1 == k0)) != 0;
+  const bool h1 = (wballot(in0 && W.p0 == k1) | wballot(in1 && W.p1 == k1)) != 0;
+  const bool h2 = (wballot(in0 && W.p0 == k2) | wballot(in1 && W.p1 == k2)) != 0;
+  const uint64_t km0 = wballot(in0 && W.p0 != k0 && W.p0 != k1 && W.p0 != k2);  // lanes whose key stays
+  const uint64_t km1 = wballot(in1 && W.p1 != k0 && W.p1 != k1 && W.p1 != k2);
+  const bool n0 = !h0, n1 = !h1, n2 = !h2;  // keys that are new
+  auto below = [&](uint64_t k) {  // kept keys below k
+    return (uint32_t)__popcll(km0 & wballot(W.p0 < k)) + (uint32_t)__popcll(km1 & wballot(W.p1 < k));
+  };
+  const uint32_t r0 = below(k0) + (n1 && k1 < k0) + (n2 && k2 < k0);
+  const uint32_t r1 = below(k1) + (n0 && k0 < k1) + (n2 && k2 < k1);
+  const uint32_t r2 = below(k2) + (n0 && k0 < k2) + (n1 && k1 < k2);
+  const uint32_t c0 = (uint32_t)__popcll(km0);
+  if ((km0 >> lane) & 1)
+    S.ps[mbcnt64(km0) + (n0 && k0 < W.p0) + (n1 && k1 < W.p0) + (n2 && k2 < W.p0)] = W.p0;
+  if ((km1 >> lane) & 1)
+    S.ps[c0 + mbcnt64(km1) + (n0 && k0 < W.p1) + (n1 && k1 < W.p1) + (n2 && k2 < W.p1)] = W.p1;
+  if (lane < 3 && sel3(lane, n0, n1, n2)) S.ps[sel3(lane, r0, r1, r2)] = sel3(lane, k0, k1, k2);
+  wsync();
+  p_load(W, S.ps, c0 + (uint32_t)__popcll(km1) + n0 + n1 + n2, lane);
+  wsync();
 }
 
 // Exclusive prefix over the wave of a count below 2^BITS per lane, from one
@@ -793,7 +839,7 @@ __device__ __forceinline__ bool w_front_add(const RedCtx& R, const WaveBufs& S, 
 template <class C>
 __device__ __forceinline__ bool w_flush_p(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
   if (W.np == 0) return true;
-  if ((uint32_t)lane < W.np) S.ps[lane] = W.p;
+  p_stage(W, S.ps, lane);
   wsync();
   const uint32_t np = W.np;
   W.np = 0;
@@ -806,33 +852,20 @@ __device__ __forceinline__ bool w_flush_p(const RedCtx& R, const WaveBufs& S, WS
 template <class C>
 __device__ __forceinline__ bool w_insert3(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t k0, uint64_t k1,
                                           uint64_t k2, int lane) {
-  if (W.np > 61 && !w_flush_p<C>(R, S, W, lane)) return false;
-  const bool in = (uint32_t)lane < W.np;
-  const uint64_t h0 = wballot(in && W.p == k0), h1 = wballot(in && W.p == k1), h2 = wballot(in && W.p == k2);
-  const uint64_t km = wballot(in) & ~(h0 | h1 | h2);  // lanes whose key stays
-  const bool n0 = h0 == 0, n1 = h1 == 0, n2 = h2 == 0;  // keys that are new
-  // ranks of the new keys among kept and new keys
-  const uint32_t r0 = (uint32_t)__popcll(km & wballot(W.p < k0)) + (n1 && k1 < k0) + (n2 && k2 < k0);
-  const uint32_t r1 = (uint32_t)__popcll(km & wballot(W.p < k1)) + (n0 && k0 < k1) + (n2 && k2 < k1);
-  const uint32_t r2 = (uint32_t)__popcll(km & wballot(W.p < k2)) + (n0 && k0 < k2) + (n1 && k1 < k2);
-  if ((km >> lane) & 1) S.ps[mbcnt64(km) + (n0 && k0 < W.p) + (n1 && k1 < W.p) + (n2 && k2 < W.p)] = W.p;
-  if (lane < 3 && sel3(lane, n0, n1, n2)) S.ps[sel3(lane, r0, r1, r2)] = sel3(lane, k0, k1, k2);
-  wsync();
-  W.np = (uint32_t)__popcll(km) + n0 + n1 + n2;
-  W.p = (uint32_t)lane < W.np ? S.ps[lane] : 0;
-  wsync();
+  if (W.np > PCAP - 3 && !w_flush_p<C>(R, S, W, lane)) return false;
+  p_insert3(S, W, k0, k1, k2, lane);
   return true;
 }
 
-// P ^= X[0..m) for a staged list with np + m <= 64; F's spare buffer is the output.
+// P ^= X[0..m) for a staged list with np + m <= PCAP; the output goes through
+// S.po, or F's spare buffer.
 __device__ __forceinline__ void w_p_add(const WaveBufs& S, WState& W, const uint64_t* X, uint32_t m, int lane) {
-  if ((uint32_t)lane < W.np) S.ps[lane] = W.p;
+  p_stage(W, S.ps, lane);
   wsync();
   uint64_t* out = S.po ? S.po : fbuf(S, W.cur ^ 1);
   const uint32_t n = uni(w_xor_lds<PER_NARROW>(S.ps, W.np, X, m, out, lane));
   w_count(W.merged, W.np + m, lane);
-  W.p = (uint32_t)lane < n ? out[lane] : 0;
-  W.np = n;
+  p_load(W, out, n, lane);
   wsync();
 }
 
@@ -841,7 +874,7 @@ __device__ __forceinline__ void w_p_add(const WaveBufs& S, WState& W, const uint
 // list that holds it afterwards (0 = P, 1 = F, 2 = U, 3 = T).
 __device__ __forceinline__ uint64_t w_pivot(const WaveBufs& S, WState& W, int lane, int* where) {
   for (;;) {
-    const uint64_t a = W.np ? rdlane64(W.p, W.np - 1) : 0;
+    const uint64_t a = p_top(W);
     const uint64_t b = W.nf ? uni64(fbuf(S, W.cur)[W.nf - 1]) : 0;
     const uint64_t u = tail_top(W.U);
     const uint64_t c = tail_top(W.T);
@@ -950,9 +983,8 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
     W.np = 0;
     W.cur = 0;
     tail_set(W.U, src, 0, lane);
-    if (len <= 64) {  // into P
-      W.p = (uint32_t)lane < len ? src[lane] : 0;
-      W.np = len;
+    if (len <= PCAP) {  // into P
+      p_load(W, src, len, lane);
       W.nf = 0;
       tail_set(W.T, src, 0, lane);
     } else if (len <= S.cap) {
@@ -1031,7 +1063,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
       const uint32_t len = (uint32_t)rdlane64(head, 0);
       const uint32_t m = len - 1;     // keys below e
       w_pop(W, where, lane);
-      if (m + W.np <= 64 && m <= 63) {  // the loaded head holds keys 0..62
+      if (m + W.np <= PCAP && m <= 63) {  // the loaded head holds keys 0..62
         if (lane >= 1 && (uint32_t)lane <= m) S.hx[lane - 1] = head;
         wsync();
         w_p_add(S, W, S.hx, m, lane);
@@ -1056,7 +1088,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
     if (W.nf == 0 && W.U.n == 0 && W.T.n == 0) {  // the column is P
       const uint64_t off = O::alloc(R, S, (uint64_t)W.np + 1, lane);
       if (off == ~0ull) return;
-      if ((uint32_t)lane < W.np) R.arena[off + 1 + lane] = W.p;
+      p_stage(W, R.arena + off + 1, lane);
       if (O::leader(lane)) {
         R.arena[off] = W.np;
         const auto* K = cold(R);
@@ -1158,7 +1190,7 @@ constexpr int GP_TAIL = 4;          // ... an arena list with an LDS list
 constexpr int GP_GG = 2;            // ... two arena lists
 constexpr uint32_t GXN = 4 * GNW * 64 * GP_TAIL;  // stage words: one ring of four chunks (two rings for GP_GG)
 static_assert(2 * 4 * GNW * 64 * GP_GG == GXN, "the two rings of an arena-arena merge fill the stage");
-constexpr uint32_t GPRIV = 64 + 64 + 128;  // the leader's ps, hx, po
+constexpr uint32_t GPRIV = PCAP + 64 + PCAP;  // the leader's ps, hx, po
 
 enum GOp : uint32_t { G_END = 0, G_MERGE_LDS, G_MERGE_TAIL, G_MERGE_GG, G_COPY_IN, G_COPY_OUT };
 // An operation for the whole group: LDS operands are word offsets from the
@@ -1431,7 +1463,7 @@ __device__ __forceinline__ bool g_front_add(const RedCtx& R, const WaveBufs& S, 
 // F ^= P (P becomes empty).
 __device__ __forceinline__ bool g_flush_p(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
   if (W.np == 0) return true;
-  if ((uint32_t)lane < W.np) S.ps[lane] = W.p;
+  p_stage(W, S.ps, lane);
   const uint32_t np = W.np;
   W.np = 0;
   return g_front_add(R, S, W, S.ps, np, lane);
@@ -1439,20 +1471,8 @@ __device__ __forceinline__ bool g_flush_p(const RedCtx& R, const WaveBufs& S, WS
 
 __device__ __forceinline__ bool g_insert3(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t k0, uint64_t k1,
                                           uint64_t k2, int lane) {
-  if (W.np > 61 && !g_flush_p(R, S, W, lane)) return false;
-  const bool in = (uint32_t)lane < W.np;
-  const uint64_t h0 = wballot(in && W.p == k0), h1 = wballot(in && W.p == k1), h2 = wballot(in && W.p == k2);
-  const uint64_t km = wballot(in) & ~(h0 | h1 | h2);
-  const bool n0 = h0 == 0, n1 = h1 == 0, n2 = h2 == 0;
-  const uint32_t r0 = (uint32_t)__popcll(km & wballot(W.p < k0)) + (n1 && k1 < k0) + (n2 && k2 < k0);
-  const uint32_t r1 = (uint32_t)__popcll(km & wballot(W.p < k1)) + (n0 && k0 < k1) + (n2 && k2 < k1);
-  const uint32_t r2 = (uint32_t)__popcll(km & wballot(W.p < k2)) + (n0 && k0 < k2) + (n1 && k1 < k2);
-  if ((km >> lane) & 1) S.ps[mbcnt64(km) + (n0 && k0 < W.p) + (n1 && k1 < W.p) + (n2 && k2 < W.p)] = W.p;
-  if (lane < 3 && sel3(lane, n0, n1, n2)) S.ps[sel3(lane, r0, r1, r2)] = sel3(lane, k0, k1, k2);
-  wsync();
-  W.np = (uint32_t)__popcll(km) + n0 + n1 + n2;
-  W.p = (uint32_t)lane < W.np ? S.ps[lane] : 0;
-  wsync();
+  if (W.np > PCAP - 3 && !g_flush_p(R, S, W, lane)) return false;
+  p_insert3(S, W, k0, k1, k2, lane);
   return true;
 }
 
@@ -1511,8 +1531,8 @@ __global__ __launch_bounds__(64 * GNW) void k_red_round_group(RedCtx R, const ui
   S.F1 = S.F0 + S.cap;
   S.X = S.F1 + S.cap;
   S.ps = S.X + GXN;
-  S.hx = S.ps + 64;
-  S.po = S.ps + 128;
+  S.hx = S.ps + PCAP;
+  S.po = S.hx + 64;
   GroupShared* G = gshared(S);
   if (threadIdx.x >= 64) {  // helpers: run what the leader posts until it posts the end
     for (;;) {

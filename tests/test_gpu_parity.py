@@ -170,8 +170,8 @@ WAVE_ENV = ("CR_LONG_LEN", "CR_YIELD_ITERS", "CR_WAVE_SHORT", "CR_FRONT_CAP", "C
     ("0", "2", "0", "4032", "8192", "0", "128", "0", "4096"),
     ("8", "8", "0", "4032", "8192", "1000000000", "256", "0", "4096"),  # wide configuration only
     # whole rounds in wave mode, tiny front and middle lists
-    ("0", "1", "1000000", "128", "300", "1000000000", "352", "0", "4096"),
-    ("0", "1", "1000000", "128", "300", "0", "352", "0", "4096"),
+    ("0", "1", "1000000", "128", "300", "1000000000", "320", "0", "4096"),
+    ("0", "1", "1000000", "128", "300", "0", "320", "0", "4096"),
     # the middle list folded into the tail at every push; all three configurations
     ("4", "4", "64", "200", "0", "64", "200", "16", "128"),
     # a workgroup per column in every wave-mode round: small lists, then the defaults
