@@ -11,7 +11,8 @@ Also reported (one JSON line):
   roofline     -- the stencil kernel (filtration + apparent pairs + survivor
                   compaction, the HBM-streaming pass) against the 8 TB/s HBM peak;
                   its duration is the mean of HIP events recorded around it on the
-                  call's stream during the timed steps;
+                  call's stream during the timed steps; "issue" gives its profiled
+                  VALU instructions per launch against the single-issue ceiling;
   cpu_baseline -- the CPU oracle timed on a bounded sample of the workload;
   stages       -- mean per-stage times over the timed steps;
   batched      -- 512 2D images of sides 28..512 (half uniform noise, half
@@ -36,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4  # G wavefront VALU instructions per second, single issue
 
 
 def stencil_bytes(shape, survivors_total: int) -> int:
@@ -56,10 +58,10 @@ def sort_bytes(n_keys: int, bits: int) -> int:
     return 16 * n_keys * ((bits + 7) // 8)
 
 
-def profiled_traffic(kernel_md: str):
-    """HBM bytes per launch measured by the profiler (FETCH_SIZE + WRITE_SIZE,
-    scaled by a plain copy's counts) as recorded in profiles/<kernel_md>, or None
-    when the kernel's source no longer has the digest the counters were taken on."""
+def profiled_fields(kernel_md: str):
+    """Per-launch counter values recorded in profiles/<kernel_md> (HBM bytes from
+    FETCH_SIZE + WRITE_SIZE scaled by a plain copy's counts, instruction counts),
+    or None when the kernel's source no longer has the digest they were taken on."""
     import hashlib
     path = os.path.join(ROOT, "profiles", kernel_md)
     if not os.path.exists(path):
@@ -70,11 +72,30 @@ def profiled_traffic(kernel_md: str):
             k, v = line.strip().split(":", 1)
             fields[k.strip()] = v.strip()
     src = os.path.join(ROOT, fields.get("source", ""))
-    if "traffic_bytes" not in fields or not os.path.isfile(src):
+    if not os.path.isfile(src):
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("source_sha256"):
         return None
-    return int(fields["traffic_bytes"])
+    return fields
+
+
+def profiled_traffic(kernel_md: str):
+    f = profiled_fields(kernel_md)
+    return int(f["traffic_bytes"]) if f and "traffic_bytes" in f else None
+
+
+def issue_rate(kernel_md: str, ms: float):
+    """The kernel's vector instruction issue rate (profiled VALU wavefront
+    instructions per launch over the measured duration) against the chip's
+    single-issue ceiling: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64
+    instruction = 614.4 G/s."""
+    f = profiled_fields(kernel_md)
+    if not f or "valu_insts" not in f:
+        return None
+    n = int(f["valu_insts"])
+    achieved = n / (ms * 1e-3) / 1e9
+    return {"valu_insts": n, "achieved": achieved, "peak": VALU_PEAK_GINST, "unit": "G wave-instr/s",
+            "frac": achieved / VALU_PEAK_GINST}
 
 
 def copy_ceiling(nbytes: int = 1 << 28, reps: int = 5) -> float:
@@ -277,7 +298,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_stencil (filtration + apparent pairs + compaction)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic("k_stencil_256cube_traffic.md"),
-                     "algorithmic_bytes": nbytes, "ms": stages["stencil"]},
+                     "algorithmic_bytes": nbytes, "ms": stages["stencil"],
+                     "issue": issue_rate("k_stencil_256cube_traffic.md", stages["stencil"])},
         "roofline_sort": {"bound": "hbm", "kernel": "cell sort, %d 8-bit passes (count + scan + scatter)"
                           % ((sort_bits + 7) // 8), "achieved": s_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": s_achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": sbytes,
