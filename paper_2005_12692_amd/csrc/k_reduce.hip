@@ -835,6 +835,33 @@ __device__ __forceinline__ bool w_front_add(const RedCtx& R, const WaveBufs& S, 
   return true;
 }
 
+// Adds a sorted arena list Q[0..m) (an owner column) to the column: into F,
+// streamed through the stage, or, for a list of more than half of F's
+// capacity, into U (which becomes Q itself when it is empty: arena lists are
+// immutable).
+template <class C>
+__device__ __forceinline__ bool w_owner_add(const RedCtx& R, const WaveBufs& S, WState& W, const uint64_t* Q,
+                                            uint32_t m, int lane) {
+  if (2 * m > S.cap) {
+    if (W.U.n + m > cold(R)->mid_cap && !w_fold_mid<C>(R, S, W, lane)) return false;
+    if (W.U.n == 0) {
+      tail_set(W.U, Q, m, lane);
+      return true;
+    }
+    const uint64_t off = w_alloc(R, (uint64_t)W.U.n + m, lane);
+    if (off == ~0ull) return false;
+    const uint32_t len = uni(w_merge_gg<C>(S.X, W.U.v, W.U.n, Q, m, R.arena + off, lane));
+    w_count(W.merged, W.U.n + m, lane);
+    tail_set(W.U, R.arena + off, len, lane);
+    return true;
+  }
+  if (W.nf + m > S.cap && !w_push_front<C>(R, S, W, lane)) return false;
+  w_count(W.merged, W.nf + m, lane);
+  W.nf = uni(w_merge_tail<C>(S.X, Q, m, fbuf(S, W.cur), W.nf, fbuf(S, W.cur ^ 1), lane));
+  W.cur ^= 1;
+  return true;
+}
+
 // F ^= P (P becomes empty).
 template <class C>
 __device__ __forceinline__ bool w_flush_p(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
@@ -939,6 +966,10 @@ struct WaveOps {
   __device__ static void copy_in(const WaveBufs&, uint64_t* dst, const uint64_t* src, uint32_t n, int lane) {
     for (uint32_t i = (uint32_t)lane; i < n; i += 64) dst[i] = src[i];
     wsync();
+  }
+  __device__ static bool owner_add(const RedCtx& R, const WaveBufs& S, WState& W, const uint64_t* Q, uint32_t m,
+                                   int lane) {
+    return w_owner_add<C>(R, S, W, Q, m, lane);
   }
   __device__ static void copy_out(const WaveBufs&, uint64_t* dst, const uint64_t* src, uint32_t n, int lane) {
     for (uint32_t i = (uint32_t)lane; i < n; i += 64) dst[i] = src[i];
@@ -1067,16 +1098,8 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
         if (lane >= 1 && (uint32_t)lane <= m) S.hx[lane - 1] = head;
         wsync();
         w_p_add(S, W, S.hx, m, lane);
-      } else {
-        // into F, in pieces that fit the stage and F; room is made first, since
-        // pushing F into the arena lists uses the stage as its ring
-        const uint32_t pmax = O::XN < S.cap ? O::XN : S.cap;
-        for (uint32_t base = 0; base < m; base += pmax) {
-          const uint32_t piece = m - base < pmax ? m - base : pmax;
-          if (W.nf + piece > S.cap && !O::push_front(R, S, W, lane)) return;
-          O::copy_in(S, S.X, q + 1 + base, piece, lane);
-          if (!O::front_add(R, S, W, S.X, piece, lane)) return;
-        }
+      } else if (!O::owner_add(R, S, W, q + 1, m, lane)) {
+        return;
       }
       continue;
     }
@@ -1192,7 +1215,7 @@ constexpr uint32_t GXN = 4 * GNW * 64 * GP_TAIL;  // stage words: one ring of fo
 static_assert(2 * 4 * GNW * 64 * GP_GG == GXN, "the two rings of an arena-arena merge fill the stage");
 constexpr uint32_t GPRIV = PCAP + 64 + PCAP;  // the leader's ps, hx, po
 
-enum GOp : uint32_t { G_END = 0, G_MERGE_LDS, G_MERGE_TAIL, G_MERGE_GG, G_COPY_IN, G_COPY_OUT };
+enum GOp : uint32_t { G_END = 0, G_MERGE_LDS, G_MERGE_TAIL, G_MERGE_TAIL_LDS, G_MERGE_GG, G_COPY_IN, G_COPY_OUT };
 // An operation for the whole group: LDS operands are word offsets from the
 // start of the group's LDS, arena operands are addresses.
 struct GDesc {
@@ -1376,10 +1399,11 @@ __device__ __noinline__ uint32_t g_run(const WaveBufs& S, uint32_t op, uint32_t 
   if (op == G_MERGE_LDS) {
     return g_merge<GP_LDS>(GLds{L + a}, na, GLds{L + b}, nb, L + out, G, lane, [](uint32_t, uint32_t) {});
   }
-  if (op == G_MERGE_TAIL) {
+  if (op == G_MERGE_TAIL || op == G_MERGE_TAIL_LDS) {  // the output in the arena, or in LDS
     GRing<GP_TAIL> ra;
     ra.init(S.X, reinterpret_cast<const uint64_t*>(a), na);
-    return g_merge<GP_TAIL>(ra, na, GLds{L + b}, nb, reinterpret_cast<uint64_t*>(out), G, lane,
+    return g_merge<GP_TAIL>(ra, na, GLds{L + b}, nb,
+                            op == G_MERGE_TAIL ? reinterpret_cast<uint64_t*>(out) : L + out, G, lane,
                             [&](uint32_t ia, uint32_t) { ra.advance(ia); });
   }
   if (op == G_MERGE_GG) {
@@ -1460,6 +1484,29 @@ __device__ __forceinline__ bool g_front_add(const RedCtx& R, const WaveBufs& S, 
   return true;
 }
 
+// Adds a sorted arena list Q[0..m) (an owner column): as w_owner_add.
+__device__ __forceinline__ bool g_owner_add(const RedCtx& R, const WaveBufs& S, WState& W, const uint64_t* Q,
+                                            uint32_t m, int lane) {
+  if (2 * m > S.cap) {
+    if (W.U.n + m > cold(R)->mid_cap && !g_fold_mid(R, S, W, lane)) return false;
+    if (W.U.n == 0) {
+      tail_set(W.U, Q, m, lane);
+      return true;
+    }
+    const uint64_t off = w_alloc(R, (uint64_t)W.U.n + m, lane);
+    if (off == ~0ull) return false;
+    const uint32_t len = g_issue(S, G_MERGE_GG, W.U.n, m, gaddr(W.U.v), gaddr(Q), gaddr(R.arena + off), lane);
+    w_count(W.merged, W.U.n + m, lane);
+    tail_set(W.U, R.arena + off, len, lane);
+    return true;
+  }
+  if (W.nf + m > S.cap && !g_push_front(R, S, W, lane)) return false;
+  w_count(W.merged, W.nf + m, lane);
+  W.nf = g_issue(S, G_MERGE_TAIL_LDS, m, W.nf, gaddr(Q), loff(S, fbuf(S, W.cur)), loff(S, fbuf(S, W.cur ^ 1)), lane);
+  W.cur ^= 1;
+  return true;
+}
+
 // F ^= P (P becomes empty).
 __device__ __forceinline__ bool g_flush_p(const RedCtx& R, const WaveBufs& S, WState& W, int lane) {
   if (W.np == 0) return true;
@@ -1509,6 +1556,10 @@ struct GroupOps {
   }
   __device__ static void copy_out(const WaveBufs& S, uint64_t* dst, const uint64_t* src, uint32_t n, int lane) {
     g_issue(S, G_COPY_OUT, n, 0, loff(S, src), 0, gaddr(dst), lane);
+  }
+  __device__ static bool owner_add(const RedCtx& R, const WaveBufs& S, WState& W, const uint64_t* Q, uint32_t m,
+                                   int lane) {
+    return g_owner_add(R, S, W, Q, m, lane);
   }
 };
 
