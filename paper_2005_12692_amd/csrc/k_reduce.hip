@@ -369,9 +369,11 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
 //        (64 + i)-th smallest; the three new edges of an apparent addition and
 //        short owner columns go here;
 //   F -- the front list in this wavefront's LDS (at most front_cap keys), which
-//        absorbs P when it fills and owner columns of up to a stage of keys;
-//   U -- the middle list in the arena, which absorbs F when F fills, and is
-//        folded into T when it would grow past mid_cap keys;
+//        absorbs P when it fills and owner columns too long for P (merged
+//        straight from the arena);
+//   U -- the middle list in the arena, which absorbs F when F fills and owner
+//        columns longer than half of F, and is folded into T when it would
+//        grow past mid_cap keys;
 //   T -- the tail in the arena.
 // Arena lists are immutable (a merge into one writes a new list); the top 64
 // keys of U and of T are kept in register windows.  The pivot is the largest
@@ -388,8 +390,8 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
 // (small LDS footprint, four wavefronts per SIMD to hide memory latency) for
 // rounds with many columns.
 constexpr int WPB = 2;                 // wavefronts per workgroup
-constexpr int PER_WIDE = 16;           // merge positions per lane per step of a long LDS merge
-constexpr int PER_NARROW = 2;          // ... of a merge of at most 128 keys
+constexpr int PER_WIDE = 16;           // merge positions per lane per step of a merge into F
+constexpr int PER_NARROW = 2;          // ... of a merge into P
 constexpr uint64_t KEY_INF = ~0ull;    // above every key
 constexpr uint32_t PCAP = 128;         // keys of P: two per lane
 template <int PER_>
@@ -397,7 +399,7 @@ struct WaveCfg {
   static constexpr int PER = PER_;              // merge positions per lane per step of a merge with an arena list
   static constexpr uint32_t CHUNK = 64 * PER;   // keys per chunk of the ring
   static constexpr uint32_t RING = 4;           // chunks of the ring (two in use, one arriving, one spare)
-  static constexpr uint32_t XN = RING * CHUNK;  // the stage: the ring, or an owner column being added
+  static constexpr uint32_t XN = RING * CHUNK;  // the stage: the ring of a merge with an arena list
   static_assert((XN & (XN - 1)) == 0, "the ring is indexed with a mask");
 };
 using WideCfg = WaveCfg<8>;
@@ -937,7 +939,6 @@ __device__ __forceinline__ float rdlane_f(float v, uint32_t i) {
 // column and a workgroup per column.
 template <class C>
 struct WaveOps {
-  static constexpr uint32_t XN = C::XN;
   __device__ static bool leader(int lane) { return lane == 0; }
   __device__ static bool aborted(const RedCtx& R, const WaveBufs&) { return cr::aborted(cold(R)->st); }
   __device__ static uint64_t alloc(const RedCtx& R, const WaveBufs&, uint64_t n, int lane) { return w_alloc(R, n, lane); }
@@ -1525,7 +1526,6 @@ __device__ __forceinline__ bool g_insert3(const RedCtx& R, const WaveBufs& S, WS
 
 // The leader's side of the column steps.
 struct GroupOps {
-  static constexpr uint32_t XN = GXN;
   __device__ static bool leader(int lane) { return lane == 0; }
   __device__ static bool aborted(const RedCtx& R, const WaveBufs&) { return cr::aborted(cold(R)->st); }
   __device__ static uint64_t alloc(const RedCtx& R, const WaveBufs&, uint64_t n, int lane) { return w_alloc(R, n, lane); }
