@@ -320,7 +320,8 @@ def main():
                      "cold": {"ms": cold["stencil"], "achieved": c_achieved, "frac": c_achieved / HBM_PEAK_GBS}},
         "roofline_sort": {"bound": "hbm", "kernel": "cell sort, %d 8-bit passes (count + scan + scatter)"
                           % ((sort_bits + 7) // 8), "achieved": s_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": s_achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": sbytes,
+                          "frac": s_achieved / HBM_PEAK_GBS, "traffic": profiled_traffic("k_sort_256cube_traffic.md"),
+                          "algorithmic_bytes": sbytes,
                           "ms": stages["sort_cells"],
                           "cold": {"ms": cold["sort_cells"], "achieved": cs_achieved,
                                    "frac": cs_achieved / HBM_PEAK_GBS}},
