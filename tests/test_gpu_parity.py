@@ -198,3 +198,43 @@ def test_wave_mode_forced(setting):
     finally:
         for k in WAVE_ENV:
             os.environ.pop(k, None)
+
+
+_MODE_VOLUMES = {}
+
+
+def _mode_volumes():
+    """Larger volumes for the reduction modes, with their oracle diagrams
+    (computed once): smooth blobs, a rough field and i.i.d. noise."""
+    if not _MODE_VOLUMES:
+        rng = np.random.default_rng(11)
+        vols = [(synth.blobs3d(96, 7, n_blobs=80), "blobs 96"),
+                (synth.grf_seeded((64, 56, 60), 2.0, 8), "grf 64x56x60"),
+                (rng.random((44, 40, 48), dtype=np.float32), "uniform 44x40x48")]
+        for img, label in vols:
+            _MODE_VOLUMES[label] = (img, oracle_diag(img))
+    return _MODE_VOLUMES
+
+
+@pytest.mark.parametrize("setting", [
+    # (long_len, yield_iters, wave_short, front_cap, mid_cap, narrow_min, narrow_cap, group_max, group_cap)
+    None,                                                                           # the defaults
+    ("0", "4", "1000000", "128", "256", "1000000000", "256", "1000000000", "128"),  # group mode, small lists
+    ("0", "4", "1000000", "128", "0", "0", "128", "0", "4096"),                     # narrow mode, small lists
+    ("8", "64", "1000000", "128", "512", "1000000000", "256", "0", "4096"),         # wide mode, small lists
+    ("32", "16", "0", "4032", "100000", "1000000000", "256", "1000000000", "4096"),  # large lists, group mode
+])
+def test_reduction_modes_larger(setting):
+    """Volumes of 10^5 to 10^6 pixels with many long columns, each reduction mode forced
+    with lists small enough that owner columns go to every level (P, F, the
+    middle list directly, the middle list by merge) and the lists fold often."""
+    import os
+    try:
+        if setting is not None:
+            for k, v in zip(WAVE_ENV, setting):
+                os.environ[k] = v
+        for label, (img, want) in _mode_volumes().items():
+            assert_same(gpu_diag(img), want, f"{label} {setting}")
+    finally:
+        for k in WAVE_ENV:
+            os.environ.pop(k, None)
