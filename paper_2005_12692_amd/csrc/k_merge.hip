@@ -50,7 +50,7 @@ __device__ inline void trip_merge(uint64_t* T, uint32_t a, uint32_t b, uint32_t 
       b = (uint32_t)old;
       s = os;
     }
-    if (aborted(st)) return;
+    if ((it & 15) == 15 && aborted(st)) return;
   }
   raise_flag(st, &st->iter_cap);
 }
@@ -128,9 +128,10 @@ __global__ void k_h0_merge(const uint64_t* __restrict__ skeys, const unsigned lo
                            uint64_t* __restrict__ T, Status* __restrict__ st) {
   uint64_t off, n;
   segment(dim_count, 1, &off, &n);
+  uint32_t j = 0;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x) {
-    if (aborted(st)) return;
+    if ((j++ & 15) == 0 && aborted(st)) return;  // (a flag read costs a round trip to L2)
     const uint64_t k = skeys[off + i];
     const ImgDesc d = imgs[skey_img(L, k)];
     int c[3];
@@ -188,9 +189,10 @@ __global__ void k_dual_merge(int top, const uint64_t* __restrict__ skeys,
                              const uint8_t* __restrict__ neg, uint64_t* __restrict__ T, Status* __restrict__ st) {
   uint64_t off, n;
   segment(dim_count, top - 1, &off, &n);
+  uint32_t jj = 0;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x) {
-    if (aborted(st)) return;
+    if ((jj++ & 15) == 0 && aborted(st)) return;  // (a flag read costs a round trip to L2)
     const uint64_t k = skeys[off + i];
     const int im = skey_img(L, k);
     const ImgDesc d = imgs[im];
