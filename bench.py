@@ -238,8 +238,7 @@ def main():
                     help="only time a 256 MiB device copy (the reference kernel for profiler byte counts)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(the sharded design is described in DESIGN.md, not built)", file=sys.stderr)
+        print("bench.py: runs on one GPU only; --gpus must be 1 (sharding over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
