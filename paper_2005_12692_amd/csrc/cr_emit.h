@@ -23,40 +23,97 @@ __device__ inline uint64_t canon_key(const Layout& L, int img, int dim, uint64_t
   return ((uint64_t)img << (2 + 2 * L.pb)) | ((uint64_t)dim << (2 * L.pb)) | (bl << L.pb) | dl;
 }
 
-// Adds one to cnt[key] for every active lane with one atomic per distinct key
-// in the wavefront; every lane of the wavefront must call it.
-__device__ inline void wave_count(uint32_t* cnt, bool active, int key) {
-  uint64_t mask = __ballot(active);
-  while (mask) {
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    const int lk = __shfl(key, leader, 64);
-    const uint64_t peers = __ballot(active && key == lk);
-    if (__lane_id() == leader) atomicAdd(&cnt[lk], (uint32_t)__popcll(peers));
-    mask &= ~peers;
-  }
+// The abort flag read once for the whole workgroup, so that a flag raised while
+// its threads start cannot send some of them past a barrier the others skip.
+__device__ inline bool aborted_block(const Status* st) {
+  __shared__ int s_ab;
+  if (threadIdx.x == 0) s_ab = aborted(st) ? 1 : 0;
+  __syncthreads();
+  return s_ab != 0;
 }
 
-// Appends one row per active lane; every lane of the wavefront must call it.
-__device__ inline void emit_rows(const EmitCtx& E, bool active, int img, uint64_t ckey) {
-  const uint64_t mask = __ballot(active);
-  if (!mask) return;
-  const int lane = __lane_id();
-  const int leader = __ffsll((unsigned long long)mask) - 1;
-  unsigned long long base = 0;
-  if (lane == leader) base = atomicAdd(E.cand_count, (unsigned long long)__popcll(mask));
-  base = __shfl(base, leader, 64);
-  bool stored = false;
-  if (active) {
-    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const unsigned long long pos = base + __popcll(mask & lt);
-    if (pos < E.cand_cap) {
-      E.cand[pos] = ckey;
-      stored = true;
-    } else {
-      raise_flag(E.st, &E.st->overflow, OVF_ROWS);
+// Rows of the positions [0, n) of one pairing stage; row(r, &img, &key) tells
+// whether position r gives a row.  A workgroup takes tiles of ROW_PER positions
+// per thread (ROW_PER * blockDim in all): it decides the rows of a tile in
+// registers, reserves their places in the row buffer with one atomic, writes
+// them, and adds the tile's per-image row counts with one atomic per image and
+// wavefront.  A single counter bumped once per wavefront would serialise every
+// wavefront of the GPU on one address.  Positions come in key order, so images
+// come in runs and a tile rarely holds more than one.  Every thread of the
+// workgroup must call it (it synchronises the workgroup).
+constexpr int ROW_PER = 8;
+constexpr int ROW_MAX_WAVES = 16;  // workgroups of at most 1024 threads
+
+template <class F>
+__device__ inline void emit_tiled(const EmitCtx& E, uint64_t n, F row) {
+  __shared__ uint32_t s_wave[ROW_MAX_WAVES];
+  __shared__ unsigned long long s_base;
+  const int tid = threadIdx.x, lane = __lane_id(), wv = tid >> 6, nw = blockDim.x >> 6;
+  const uint64_t tile = (uint64_t)ROW_PER * blockDim.x;
+  const Walk w = xcd_part((n + tile - 1) / tile, 1);
+  for (uint64_t t = w.i; t < w.end; t += w.stride) {
+    uint64_t ck[ROW_PER];
+    int im[ROW_PER];
+    uint32_t act = 0;
+#pragma unroll
+    for (int k = 0; k < ROW_PER; ++k) {
+      const uint64_t r = t * tile + (uint64_t)k * blockDim.x + tid;
+      ck[k] = 0;
+      im[k] = 0;
+      if (r < n && row(r, &im[k], &ck[k])) act |= 1u << k;
+    }
+    // places: wavefront scan of the per-thread counts, then the workgroup's
+    const uint32_t cnt = __popc(act);
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t up = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += up;
+    }
+    if (lane == 63) s_wave[wv] = incl;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t tot = 0;
+      for (int v = 0; v < nw; ++v) tot += s_wave[v];
+      s_base = tot ? atomicAdd(E.cand_count, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    uint64_t pos = s_base + incl - cnt;
+    for (int v = 0; v < wv; ++v) pos += s_wave[v];
+    __syncthreads();  // s_wave and s_base are rewritten by the next tile
+    uint32_t stored = 0;
+#pragma unroll
+    for (int k = 0; k < ROW_PER; ++k)
+      if (act >> k & 1u) {
+        if (pos < E.cand_cap) {
+          E.cand[pos] = ck[k];
+          stored |= 1u << k;
+        } else {
+          raise_flag(E.st, &E.st->overflow, OVF_ROWS);
+        }
+        ++pos;
+      }
+    // per-image counts: the lowest image among the lanes' uncounted rows first
+    while (__ballot(stored != 0)) {
+      int mine = 0x7FFFFFFF;
+#pragma unroll
+      for (int k = ROW_PER - 1; k >= 0; --k)
+        if (stored >> k & 1u) mine = min(mine, im[k]);
+      int lo = mine;
+#pragma unroll
+      for (int o = 32; o; o >>= 1) lo = min(lo, __shfl_xor(lo, o, 64));
+      uint32_t c = 0;
+#pragma unroll
+      for (int k = 0; k < ROW_PER; ++k)
+        if ((stored >> k & 1u) && im[k] == lo) {
+          ++c;
+          stored &= ~(1u << k);
+        }
+#pragma unroll
+      for (int o = 32; o; o >>= 1) c += __shfl_xor(c, o, 64);
+      if (lane == 0) atomicAdd(&E.img_pairs[lo], c);
     }
   }
-  wave_count(E.img_pairs, stored, img);
 }
 
 // Row for the pair (birth cell, death cell) given by their sort keys; returns

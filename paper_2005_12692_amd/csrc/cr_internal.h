@@ -123,6 +123,34 @@ __device__ inline int64_t cell_argmax_pixel(const float* __restrict__ img, const
   return best;
 }
 
+// ---- XCD-aware walks over a range -----------------------------------------------
+// Workgroups are dispatched to the eight XCDs in turn, so workgroup b runs on
+// XCD b % 8.  A range [0, n) is cut into one contiguous part per XCD (a multiple
+// of `align` long) and each part is walked by that XCD's workgroups alone: the
+// images an XCD works on at a time then share its L2 instead of being spread
+// over all eight.  Any grid is correct; one that is not a multiple of 8 walks
+// [0, n) as a single part.
+struct Walk {
+  uint64_t i, end, stride;
+};
+// Units (e.g. tiles) of the range per workgroup: i, i + stride, ... below end.
+__device__ inline Walk xcd_part(uint64_t n, uint64_t align) {
+  const uint32_t nx = (gridDim.x % 8 == 0) ? 8 : 1;
+  const uint32_t x = blockIdx.x % nx, b = blockIdx.x / nx;
+  const uint64_t part = ((n + nx - 1) / nx + align - 1) / align * align;
+  const uint64_t lo = min(n, (uint64_t)x * part), hi = min(n, lo + part);
+  return {lo + b, hi, (uint64_t)(gridDim.x / nx)};
+}
+// Positions per thread; parts are multiples of 64, so the lanes of a wavefront
+// make the same number of steps.
+__device__ inline Walk xcd_walk(uint64_t n) {
+  const uint32_t nx = (gridDim.x % 8 == 0) ? 8 : 1;
+  const uint32_t x = blockIdx.x % nx, b = blockIdx.x / nx;
+  const uint64_t part = ((n + nx - 1) / nx + 63) & ~63ull;
+  const uint64_t lo = min(n, (uint64_t)x * part), hi = min(n, lo + part);
+  return {lo + (uint64_t)b * blockDim.x + threadIdx.x, hi, (uint64_t)(gridDim.x / nx) * blockDim.x};
+}
+
 // ---- device-scope atomics (coherent across the XCDs of one GPU) ----------------
 __device__ inline uint64_t ld_acq64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);

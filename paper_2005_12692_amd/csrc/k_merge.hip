@@ -129,8 +129,8 @@ __global__ void k_h0_merge(const uint64_t* __restrict__ skeys, const unsigned lo
   uint64_t off, n;
   segment(dim_count, 1, &off, &n);
   uint32_t j = 0;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
+  const Walk w = xcd_walk(n);
+  for (uint64_t i = w.i; i < w.end; i += w.stride) {
     if ((j++ & 15) == 0 && aborted(st)) return;  // (a flag read costs a round trip to L2)
     const uint64_t k = skeys[off + i];
     const ImgDesc d = imgs[skey_img(L, k)];
@@ -149,28 +149,23 @@ __global__ void k_h0_merge(const uint64_t* __restrict__ skeys, const unsigned lo
 // Degree 0 rows; marks edges that kill a component (they are not 1-columns).
 __global__ void k_h0_emit(const uint64_t* __restrict__ skeys, const unsigned long long* __restrict__ dim_count,
                           const uint64_t* __restrict__ T, uint8_t* __restrict__ neg, EmitCtx E) {
-  if (aborted(E.st)) return;
+  if (aborted_block(E.st)) return;
   uint64_t off0, n0, off1, n1;
   segment(dim_count, 0, &off0, &n0);
   segment(dim_count, 1, &off1, &n1);
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint64_t nr = (n0 + 63) & ~63ull;
-  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < nr; r += stride) {
-    bool active = false;
-    int im = 0;
-    uint64_t ck = 0;
-    if (r < n0) {
-      const uint64_t t = T[r];
-      const uint32_t s = (uint32_t)(t >> 32);
-      const bool ess = s == TRIP_INF;
-      if (!ess) {
-        if (s >= n1) raise_flag(E.st, &E.st->internal);
-        else neg[s] = 1;
+  emit_tiled(E, n0, [&](uint64_t r, int* im, uint64_t* ck) {
+    const uint64_t t = T[r];
+    const uint32_t s = (uint32_t)(t >> 32);
+    const bool ess = s == TRIP_INF;
+    if (!ess) {
+      if (s >= n1) {
+        raise_flag(E.st, &E.st->internal);
+        return false;
       }
-      active = pair_row(E, skeys[off0 + r], ess ? 0 : skeys[off1 + s], ess, &im, &ck);
+      neg[s] = 1;
     }
-    emit_rows(E, active, im, ck);
-  }
+    return pair_row(E, skeys[off0 + r], ess ? 0 : skeys[off1 + s], ess, im, ck);
+  });
 }
 
 // Top degree on the dual graph.  For an image (top = 2) the columns are the
@@ -190,8 +185,8 @@ __global__ void k_dual_merge(int top, const uint64_t* __restrict__ skeys,
   uint64_t off, n;
   segment(dim_count, top - 1, &off, &n);
   uint32_t jj = 0;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
+  const Walk w = xcd_walk(n);
+  for (uint64_t i = w.i; i < w.end; i += w.stride) {
     if ((jj++ & 15) == 0 && aborted(st)) return;  // (a flag read costs a round trip to L2)
     const uint64_t k = skeys[off + i];
     const int im = skey_img(L, k);
@@ -199,16 +194,19 @@ __global__ void k_dual_merge(int top, const uint64_t* __restrict__ skeys,
     int c[3];
     kidx_coords(d, skey_kidx(L, k), c);
     if (dual_col_skipped(top, i, neg)) continue;
-    // the one even axis of the cell within the image's own dimensions
+    // the one even axis of the cell within the image's own dimensions (selects,
+    // not an index: an indexed local array would be placed in LDS)
     const int a = (top == 2) ? ((c[1] & 1) ? 2 : 1) : (!(c[0] & 1) ? 0 : (!(c[1] & 1) ? 1 : 2));
-    if (d.K[a] == 1) continue;  // no cofacet at all (a flat image): a loop at the exterior node
-    uint32_t ends[2];
-    for (int j = 0; j < 2; ++j) {
-      int t[3] = {c[0], c[1], c[2]};
-      t[a] += j ? 1 : -1;
-      ends[j] = (t[a] < 0 || t[a] >= d.K[a]) ? (uint32_t)im : forest_root(tlink, anchor_pixel(d, t), st);
-    }
-    trip_merge(T, ends[0], ends[1], (uint32_t)(n - 1 - i), st);
+    const int ka = a == 0 ? d.K[0] : a == 1 ? d.K[1] : d.K[2];
+    const int ca = a == 0 ? c[0] : a == 1 ? c[1] : c[2];
+    if (ka == 1) continue;  // no cofacet at all (a flat image): a loop at the exterior node
+    // the two top cofacets differ from c by -1 and +1 along a; one outside the
+    // image is the exterior node
+    const int lo[3] = {c[0] - (a == 0), c[1] - (a == 1), c[2] - (a == 2)};
+    const int hi[3] = {c[0] + (a == 0), c[1] + (a == 1), c[2] + (a == 2)};
+    const uint32_t e0 = ca == 0 ? (uint32_t)im : forest_root(tlink, anchor_pixel(d, lo), st);
+    const uint32_t e1 = ca + 1 >= ka ? (uint32_t)im : forest_root(tlink, anchor_pixel(d, hi), st);
+    trip_merge(T, e0, e1, (uint32_t)(n - 1 - i), st);
   }
 }
 
@@ -217,29 +215,21 @@ __global__ void k_dual_merge(int top, const uint64_t* __restrict__ skeys,
 __global__ void k_dual_emit(int top, const uint64_t* __restrict__ skeys,
                             const unsigned long long* __restrict__ dim_count, const uint64_t* __restrict__ T,
                             uint8_t* __restrict__ mark, int emit, EmitCtx E) {
-  if (aborted(E.st)) return;
+  if (aborted_block(E.st)) return;
   uint64_t offc, nc, offt, nt;
   segment(dim_count, top - 1, &offc, &nc);
   segment(dim_count, top, &offt, &nt);
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint64_t nr = (nt + 63) & ~63ull;
-  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < nr; r += stride) {
-    bool active = false;
-    int im = 0;
-    uint64_t ck = 0;
-    if (r < nt) {
-      const uint64_t id = E.L.nimg + (nt - 1 - r);
-      const uint64_t t = T[id];
-      const uint32_t s = (uint32_t)(t >> 32);
-      if (s == TRIP_INF || s >= nc) {
-        raise_flag(E.st, &E.st->internal);  // a top cell that never dies: impossible in a box
-      } else {
-        if (mark) mark[nc - 1 - s] = 1;
-        if (emit) active = pair_row(E, skeys[offc + (nc - 1 - s)], skeys[offt + r], false, &im, &ck);
-      }
+  emit_tiled(E, nt, [&](uint64_t r, int* im, uint64_t* ck) {
+    const uint64_t id = E.L.nimg + (nt - 1 - r);
+    const uint64_t t = T[id];
+    const uint32_t s = (uint32_t)(t >> 32);
+    if (s == TRIP_INF || s >= nc) {
+      raise_flag(E.st, &E.st->internal);  // a top cell that never dies: impossible in a box
+      return false;
     }
-    emit_rows(E, active, im, ck);
-  }
+    if (mark) mark[nc - 1 - s] = 1;
+    return emit != 0 && pair_row(E, skeys[offc + (nc - 1 - s)], skeys[offt + r], false, im, ck);
+  });
 }
 
 // ---- host launchers ------------------------------------------------------------

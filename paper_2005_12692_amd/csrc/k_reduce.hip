@@ -1692,26 +1692,22 @@ __global__ void k_red_reset(RedCtx R, const uint32_t* __restrict__ list_t, const
 // Degree-1 rows of a volume: column c pairs its final pivot edge (birth) with
 // its square (death).
 __global__ void k_h1_emit(RedCtx R, EmitCtx E) {
-  if (aborted(R.st)) return;
+  if (aborted_block(R.st)) return;
   const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
   const uint64_t n2 = R.dim_count[2];
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint64_t nr = (n2 + 63) & ~63ull;
-  for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nr; c += stride) {
-    bool active = false;
-    int im = 0;
-    uint64_t ck = 0;
-    if (c < n2 && !R.cleared[c]) {
-      const uint64_t e = R.piv[c];
-      const ImgDesc d = R.imgs[skey_img(R.L, e)];
-      int ec[3];
-      kidx_coords(d, skey_kidx(R.L, e), ec);
-      const uint64_t ow = R.owner[edge_slot(d, ec)];
-      if (ow == NO_OWNER || (uint32_t)(ow >> 32) != (uint32_t)c) raise_flag(R.st, &R.st->internal);
-      else active = pair_row(E, e, R.skeys[off2 + c], false, &im, &ck);
+  emit_tiled(E, n2, [&](uint64_t c, int* im, uint64_t* ck) {
+    if (R.cleared[c]) return false;
+    const uint64_t e = R.piv[c];
+    const ImgDesc d = R.imgs[skey_img(R.L, e)];
+    int ec[3];
+    kidx_coords(d, skey_kidx(R.L, e), ec);
+    const uint64_t ow = R.owner[edge_slot(d, ec)];
+    if (ow == NO_OWNER || (uint32_t)(ow >> 32) != (uint32_t)c) {
+      raise_flag(R.st, &R.st->internal);
+      return false;
     }
-    emit_rows(E, active, im, ck);
-  }
+    return pair_row(E, e, R.skeys[off2 + c], false, im, ck);
+  });
 }
 
 RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64_t* skeys,
