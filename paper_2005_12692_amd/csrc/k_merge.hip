@@ -107,19 +107,42 @@ __global__ void k_troot_init(const uint64_t* __restrict__ skeys, const unsigned 
   }
 }
 
-__device__ inline uint32_t forest_root(const int32_t* link, int64_t x, Status* st) {
+// Roots of the forest nodes x and y, walked together (their loads overlap); a
+// side with `done` set is not walked and keeps the value in *rx / *ry.
+__device__ inline void forest_roots2(const int32_t* link, int64_t x, int64_t y, bool dx, bool dy,
+                                     uint32_t* rx, uint32_t* ry, Status* st) {
   for (uint32_t it = 0; it < ITER_CAP; ++it) {
-    const int32_t v = link[x];
-    if (v == -1) break;  // a root that was never numbered: inconsistent state
-    if (v < 0) return (uint32_t)(-(v + 2));
-    x = v;
-  }
-  if (link[x] == -1) {
-    raise_flag(st, &st->internal);
-    return 0;
+    if (dx && dy) return;
+    const int32_t vx = dx ? 0 : link[x];
+    const int32_t vy = dy ? 0 : link[y];
+    if (!dx) {
+      if (vx == -1) {  // a root that was never numbered: inconsistent state
+        raise_flag(st, &st->internal);
+        *rx = 0;
+        dx = true;
+      } else if (vx < 0) {
+        *rx = (uint32_t)(-(vx + 2));
+        dx = true;
+      } else {
+        x = vx;
+      }
+    }
+    if (!dy) {
+      if (vy == -1) {
+        raise_flag(st, &st->internal);
+        *ry = 0;
+        dy = true;
+      } else if (vy < 0) {
+        *ry = (uint32_t)(-(vy + 2));
+        dy = true;
+      } else {
+        y = vy;
+      }
+    }
   }
   raise_flag(st, &st->iter_cap);
-  return 0;
+  *rx = 0;
+  *ry = 0;
 }
 
 // Degree 0: insert every surviving edge (level = its rank among edges).
@@ -140,8 +163,8 @@ __global__ void k_h0_merge(const uint64_t* __restrict__ skeys, const unsigned lo
     int p[3] = {c[0], c[1], c[2]}, q[3] = {c[0], c[1], c[2]};
     p[a] -= 1;
     q[a] += 1;
-    const uint32_t ra = forest_root(vlink, anchor_pixel(d, p), st);
-    const uint32_t rb = forest_root(vlink, anchor_pixel(d, q), st);
+    uint32_t ra = 0, rb = 0;
+    forest_roots2(vlink, anchor_pixel(d, p), anchor_pixel(d, q), false, false, &ra, &rb, st);
     trip_merge(T, ra, rb, (uint32_t)i, st);
   }
 }
@@ -204,8 +227,10 @@ __global__ void k_dual_merge(int top, const uint64_t* __restrict__ skeys,
     // image is the exterior node
     const int lo[3] = {c[0] - (a == 0), c[1] - (a == 1), c[2] - (a == 2)};
     const int hi[3] = {c[0] + (a == 0), c[1] + (a == 1), c[2] + (a == 2)};
-    const uint32_t e0 = ca == 0 ? (uint32_t)im : forest_root(tlink, anchor_pixel(d, lo), st);
-    const uint32_t e1 = ca + 1 >= ka ? (uint32_t)im : forest_root(tlink, anchor_pixel(d, hi), st);
+    const bool out0 = ca == 0, out1 = ca + 1 >= ka;
+    uint32_t e0 = (uint32_t)im, e1 = (uint32_t)im;
+    forest_roots2(tlink, out0 ? 0 : anchor_pixel(d, lo), out1 ? 0 : anchor_pixel(d, hi), out0, out1, &e0, &e1,
+                  st);
     trip_merge(T, e0, e1, (uint32_t)(n - 1 - i), st);
   }
 }
