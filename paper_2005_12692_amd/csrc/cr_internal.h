@@ -141,14 +141,20 @@ __device__ inline Walk xcd_part(uint64_t n, uint64_t align) {
   const uint64_t lo = min(n, (uint64_t)x * part), hi = min(n, lo + part);
   return {lo + b, hi, (uint64_t)(gridDim.x / nx)};
 }
-// Positions per thread; parts are multiples of 64, so the lanes of a wavefront
-// make the same number of steps.
-__device__ inline Walk xcd_walk(uint64_t n) {
+// Positions per thread, each wavefront taking one contiguous chunk of its XCD's
+// part and walking it 64 positions at a time in order.  For the union-find
+// merges this keeps the edges in flight in any one image at nearby levels, so
+// fewer links are made out of order and later replaced.
+__device__ inline Walk xcd_wave_walk(uint64_t n) {
   const uint32_t nx = (gridDim.x % 8 == 0) ? 8 : 1;
-  const uint32_t x = blockIdx.x % nx, b = blockIdx.x / nx;
-  const uint64_t part = ((n + nx - 1) / nx + 63) & ~63ull;
+  const uint32_t x = blockIdx.x % nx, b = blockIdx.x / nx, nb = gridDim.x / nx;
+  const uint64_t part = (n + nx - 1) / nx;
   const uint64_t lo = min(n, (uint64_t)x * part), hi = min(n, lo + part);
-  return {lo + (uint64_t)b * blockDim.x + threadIdx.x, hi, (uint64_t)(gridDim.x / nx) * blockDim.x};
+  const uint32_t wpb = blockDim.x >> 6;
+  const uint64_t waves = (uint64_t)nb * wpb, wv = (uint64_t)b * wpb + (threadIdx.x >> 6);
+  const uint64_t chunk = (hi - lo + waves - 1) / waves;
+  const uint64_t clo = min(hi, lo + wv * chunk), chi = min(hi, clo + chunk);
+  return {clo + (threadIdx.x & 63), chi, 64};
 }
 
 // ---- device-scope atomics (coherent across the XCDs of one GPU) ----------------

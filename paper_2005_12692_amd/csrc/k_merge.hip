@@ -152,7 +152,7 @@ __global__ void k_h0_merge(const uint64_t* __restrict__ skeys, const unsigned lo
   uint64_t off, n;
   segment(dim_count, 1, &off, &n);
   uint32_t j = 0;
-  const Walk w = xcd_walk(n);
+  const Walk w = xcd_wave_walk(n);
   for (uint64_t i = w.i; i < w.end; i += w.stride) {
     if ((j++ & 15) == 0 && aborted(st)) return;  // (a flag read costs a round trip to L2)
     const uint64_t k = skeys[off + i];
@@ -208,7 +208,7 @@ __global__ void k_dual_merge(int top, const uint64_t* __restrict__ skeys,
   uint64_t off, n;
   segment(dim_count, top - 1, &off, &n);
   uint32_t jj = 0;
-  const Walk w = xcd_walk(n);
+  const Walk w = xcd_wave_walk(n);
   for (uint64_t i = w.i; i < w.end; i += w.stride) {
     if ((jj++ & 15) == 0 && aborted(st)) return;  // (a flag read costs a round trip to L2)
     const uint64_t k = skeys[off + i];
