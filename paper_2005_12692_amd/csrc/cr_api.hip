@@ -72,7 +72,7 @@ constexpr int N_TILE_VARIANTS = 3;    // stencil tile shapes (see stencil_tile)
 cr_tuning default_tuning(int ndim) {
   cr_tuning t;
   t.tile = 0;
-  t.grid = 4096;
+  t.grid = 2048;
   t.long_len = 32;
   t.yield_iters = 1024;
   t.wave_short = 4096;

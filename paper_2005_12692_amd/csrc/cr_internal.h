@@ -141,20 +141,26 @@ __device__ inline Walk xcd_part(uint64_t n, uint64_t align) {
   const uint64_t lo = min(n, (uint64_t)x * part), hi = min(n, lo + part);
   return {lo + b, hi, (uint64_t)(gridDim.x / nx)};
 }
-// Positions per thread, each wavefront taking one contiguous chunk of its XCD's
-// part and walking it 64 positions at a time in order.  For the union-find
-// merges this keeps the edges in flight in any one image at nearby levels, so
-// fewer links are made out of order and later replaced.
-__device__ inline Walk xcd_wave_walk(uint64_t n) {
+// Positions per thread.  chunks == 0: the whole grid strides over [0, n), so
+// the positions in flight are consecutive.  Otherwise each XCD's part is cut
+// into `chunks` contiguous chunks (at most one per wavefront of the XCD), each
+// walked in order by its own whole wavefronts.  For the union-find merges the
+// positions in flight in one image then sit at nearby levels, so fewer links
+// are made out of order and later replaced.
+__device__ inline Walk chunk_walk(uint64_t n, uint32_t chunks) {
+  if (chunks == 0) return {blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, n, (uint64_t)gridDim.x * blockDim.x};
   const uint32_t nx = (gridDim.x % 8 == 0) ? 8 : 1;
   const uint32_t x = blockIdx.x % nx, b = blockIdx.x / nx, nb = gridDim.x / nx;
   const uint64_t part = (n + nx - 1) / nx;
   const uint64_t lo = min(n, (uint64_t)x * part), hi = min(n, lo + part);
-  const uint32_t wpb = blockDim.x >> 6;
-  const uint64_t waves = (uint64_t)nb * wpb, wv = (uint64_t)b * wpb + (threadIdx.x >> 6);
-  const uint64_t chunk = (hi - lo + waves - 1) / waves;
-  const uint64_t clo = min(hi, lo + wv * chunk), chi = min(hi, clo + chunk);
-  return {clo + (threadIdx.x & 63), chi, 64};
+  const uint64_t waves = (uint64_t)nb * (blockDim.x >> 6);
+  const uint64_t nc = min(waves, (uint64_t)chunks * (8 / nx));
+  const uint64_t tg = (waves / nc) * 64;  // threads per chunk, whole wavefronts
+  const uint64_t tx = (uint64_t)b * blockDim.x + threadIdx.x, g = tx / tg;
+  if (g >= nc) return {0, 0, 1};
+  const uint64_t cs = (hi - lo + nc - 1) / nc;
+  const uint64_t clo = min(hi, lo + g * cs), chi = min(hi, clo + cs);
+  return {clo + tx % tg, chi, tg};
 }
 
 // ---- device-scope atomics (coherent across the XCDs of one GPU) ----------------

@@ -148,11 +148,11 @@ __device__ inline void forest_roots2(const int32_t* link, int64_t x, int64_t y, 
 // Degree 0: insert every surviving edge (level = its rank among edges).
 __global__ void k_h0_merge(const uint64_t* __restrict__ skeys, const unsigned long long* __restrict__ dim_count,
                            const ImgDesc* __restrict__ imgs, Layout L, const int32_t* __restrict__ vlink,
-                           uint64_t* __restrict__ T, Status* __restrict__ st) {
+                           uint64_t* __restrict__ T, uint32_t chunks, Status* __restrict__ st) {
   uint64_t off, n;
   segment(dim_count, 1, &off, &n);
   uint32_t j = 0;
-  const Walk w = xcd_wave_walk(n);
+  const Walk w = chunk_walk(n, chunks);
   for (uint64_t i = w.i; i < w.end; i += w.stride) {
     if ((j++ & 15) == 0 && aborted(st)) return;  // (a flag read costs a round trip to L2)
     const uint64_t k = skeys[off + i];
@@ -208,7 +208,7 @@ __global__ void k_dual_merge(int top, const uint64_t* __restrict__ skeys,
   uint64_t off, n;
   segment(dim_count, top - 1, &off, &n);
   uint32_t jj = 0;
-  const Walk w = xcd_wave_walk(n);
+  const Walk w = chunk_walk(n, ~0u);  // one chunk per wavefront
   for (uint64_t i = w.i; i < w.end; i += w.stride) {
     if ((jj++ & 15) == 0 && aborted(st)) return;  // (a flag read costs a round trip to L2)
     const uint64_t k = skeys[off + i];
@@ -263,7 +263,10 @@ void launch_h0(int grid, const uint64_t* skeys, const unsigned long long* dim_co
                hipStream_t s) {
   k_vroot_init<<<grid, 256, 0, s>>>(skeys, dim_count, imgs, L, vlink, st);
   k_trip_init<<<grid, 256, 0, s>>>(T, dim_count, 0, 0);
-  k_h0_merge<<<grid, 256, 0, s>>>(skeys, dim_count, imgs, L, vlink, T, st);
+  // degree 0: a single image is walked by the whole grid at once (measured
+  // best on a 256^3 volume); a batch gets about one chunk per image
+  const uint32_t chunks = L.nimg < 8 ? 0u : (uint32_t)((L.nimg + 7) / 8);
+  k_h0_merge<<<grid, 256, 0, s>>>(skeys, dim_count, imgs, L, vlink, T, chunks, st);
   k_h0_emit<<<grid, 256, 0, s>>>(skeys, dim_count, T, neg, E);
 }
 
