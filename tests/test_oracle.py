@@ -275,3 +275,91 @@ def test_maxdim_filter():
             assert np.array_equal(getattr(part, f), getattr(full, f)[keep])
     # maxdim above the data is clamped
     assert len(oracle.persistence(vol, maxdim=5)) == len(full)
+
+
+def test_one_dimensional():
+    # a 1D image is a 2D image on one line (Sec. 2).  Worked by hand: minima 0,
+    # 1, 2 at pixels 0, 2, 4; the edges (0,1), (1,2) enter at 3 and (2,3),
+    # (3,4) at 4; the edge at 3 joining {0,1} to {2} kills the younger
+    # component (born 1) at the edge's larger vertex, pixel 1, and the edge at
+    # 4 joining pixel 4 kills it at pixel 3.
+    d = oracle.persistence(np.array([0, 3, 1, 4, 2], np.float32))
+    rows = list(zip(d.dim.tolist(), d.birth.tolist(), d.death.tolist(), d.birth_pixel.tolist(),
+                    d.death_pixel.tolist()))
+    assert rows == [(0, 0.0, float("inf"), 0, -1), (0, 1.0, 3.0, 2, 1), (0, 2.0, 4.0, 4, 3)]
+    rng = np.random.default_rng(5)
+    for n in [1, 2, 3, 7, 16, 40]:
+        for levels in [3, 1000]:
+            s = rng.integers(0, levels, size=n).astype(np.float32)
+            d = oracle.persistence(s)
+            assert diag_counter(d) == brute.diagram_from_ranks(s)
+            # the same signal as a 1 x n and an n x 1 image: same diagram, same pixels
+            for t in (s[None, :], s[:, None]):
+                e = oracle.persistence(np.ascontiguousarray(t))
+                for f in ("dim", "birth", "death", "birth_pixel", "death_pixel"):
+                    assert np.array_equal(getattr(d, f), getattr(e, f))
+    # the paper's time-series example: sin(x) + 0.1 x on 100 samples of [0, 4 pi]
+    x = np.linspace(0, 4 * np.pi, 100)
+    s = (np.sin(x) + 0.1 * x).astype(np.float32)
+    d = oracle.persistence(s)
+    assert diag_counter(d) == brute.diagram_from_ranks(s)
+    assert len(d) == 3 and int((d.death_pixel < 0).sum()) == 1  # three valleys, one essential
+
+
+def test_masked_domains():
+    # pixels outside a non-rectangular domain take +inf (Sec. 2).  An annulus of
+    # constant value c: one component [c, inf) and one loop born at c that dies
+    # only when the +inf hole enters -- a finite pair whose death is +inf, told
+    # apart from an essential bar by its death pixel.
+    yy, xx = np.mgrid[:13, :13]
+    r2 = (yy - 6) ** 2 + (xx - 6) ** 2
+    ring = (r2 >= 4) & (r2 <= 25)
+    img = np.where(ring, np.float32(1.5), np.float32(np.inf)).astype(np.float32)
+    d = oracle.persistence(img)
+    rows = sorted(zip(d.dim.tolist(), d.birth.tolist(), d.death.tolist(), (d.death_pixel >= 0).tolist()))
+    assert rows == [(0, 1.5, float("inf"), False), (1, 1.5, float("inf"), True)]
+    assert np.isinf(img.reshape(-1)[d.death_pixel[d.dim == 1][0]])
+    # varying values on the annulus: the exact diagram from persistent Betti numbers
+    rng = np.random.default_rng(8)
+    small = ((yy[:9, :9] - 4) ** 2 + (xx[:9, :9] - 4) ** 2)
+    mask = (small >= 2) & (small <= 12)
+    for _ in range(3):
+        v = np.where(mask, rng.integers(0, 4, size=mask.shape).astype(np.float32), np.float32(np.inf))
+        d = oracle.persistence(v.astype(np.float32))
+        assert diag_counter(d) == brute.diagram_from_ranks(v)
+        assert int((d.death_pixel < 0).sum()) == 1  # one essential bar: the full grid is contractible
+    # a spherical shell of value 0 in a +inf volume: one void [0, inf), finite
+    z, y, x = np.mgrid[:9, :9, :9]
+    r = (z - 4) ** 2 + (y - 4) ** 2 + (x - 4) ** 2
+    vol = np.where((r >= 4) & (r <= 12), np.float32(0), np.float32(np.inf)).astype(np.float32)
+    d = oracle.persistence(vol)
+    rows = sorted(zip(d.dim.tolist(), d.birth.tolist(), d.death.tolist(), (d.death_pixel >= 0).tolist()))
+    assert rows == [(0, 0.0, float("inf"), False), (2, 0.0, float("inf"), True)]
+
+
+def test_lifetime_image_and_locations():
+    # the worked 1D example above: bars (0,[0,inf)) at pixel 0, (0,[1,3)) born at
+    # pixel 2 killed at pixel 1, (0,[2,4)) born at 4 killed at 3 (Sec. 4: each
+    # pixel holds the largest lifetime of the bars located there)
+    d = oracle.persistence(np.array([0, 3, 1, 4, 2], np.float32))
+    lb = oracle.lifetime_image(d, (5,))
+    assert lb.shape == (3, 5)
+    assert lb[0].tolist() == [float("inf"), 0.0, 2.0, 0.0, 2.0] and not lb[1:].any()
+    ld = oracle.lifetime_image(d, (5,), "death")
+    assert ld[0].tolist() == [0.0, 2.0, 0.0, 2.0, 0.0] and not ld[1:].any()
+    # two bars at one pixel keep the larger lifetime
+    two = oracle.Diagram(np.array([1, 1], np.int32), np.array([0, 1], np.float32),
+                         np.array([5, 2], np.float32), np.array([3, 3]), np.array([0, 1]))
+    assert oracle.lifetime_image(two, (2, 2))[1].tolist() == [[0, 0], [0, 5]]
+    # a binary image: every component is born at its own pixel, lifetime 1
+    # (or inf for the one essential bar)
+    rng = np.random.default_rng(4)
+    img = (rng.random((10, 12)) < 0.5).astype(np.float32)
+    d = oracle.persistence(img)
+    c0 = oracle.lifetime_image(d, img.shape)[0]
+    k0 = brute.betti(img, 0.0)[0]
+    assert int((c0 == 1).sum()) == k0 - 1 and int(np.isinf(c0).sum()) == 1 and int((c0 != 0).sum()) == k0
+    # locations: (x, y, z) with x the last axis
+    assert oracle.pixel_coords(np.array([0, 7, 11, -1]), (3, 4)).tolist() == [
+        [0, 0, 0], [3, 1, 0], [3, 2, 0], [-1, -1, -1]]
+    assert oracle.pixel_coords(np.array([1 * 20 + 2 * 5 + 3]), (2, 4, 5)).tolist() == [[3, 2, 1]]
