@@ -1,6 +1,7 @@
 /*
  * cr.h -- C ABI of libcr: persistent homology over Z/2 of the weighted cubical
- * complex (V-construction) of 2D images and 3D volumes on one AMD MI355X.
+ * complex (V-construction) of 1D signals, 2D images and 3D volumes on one AMD
+ * MI355X.
  *
  * The problem is the one Kaji, Sudo and Ahara state for Cubical Ripser
  * (arXiv:2005.12692): an image is a real function on a regular grid (Sec. 2);
@@ -93,7 +94,8 @@ typedef struct cr_diagram {
  * maximum over each cell's vertices, sort, apparent pairs, degree 0 by
  * union-find, higher degrees by coboundary reduction with clearing).
  *   image : device, prod(shape) floats, C order; not modified, not retained.
- *   ndim  : 2 or 3.  shape : host, ndim extents >= 1, C order.
+ *   ndim  : 1, 2 or 3 (a 1D signal is a 1 x n image: it lies on one line of
+ *           the grid, Sec. 2).  shape : host, ndim extents >= 1, C order.
  *   maxdim: highest dimension reported; >= 0, clamped to ndim-1.
  *   flags : 0 or CR_FLAG_STAGE_TIMES.
  * Synchronises `stream` once (to learn the number of rows), then allocates
@@ -110,7 +112,7 @@ void cr_diagram_free(cr_context* ctx, cr_diagram* d);
  * every stage (the images share each launch).
  *   packed        : device floats; image i occupies [pixel_offsets[i], pixel_offsets[i+1]).
  *   pixel_offsets : host, n_images+1 entries, pixel_offsets[0] = 0, consistent with shapes.
- *   shapes        : host, n_images*ndim extents, C order per image.
+ *   shapes        : host, n_images*ndim extents, C order per image (ndim 1, 2 or 3).
  *   dim..death_pixel: device arrays of `capacity` rows (caller-provided).
  *   pair_offsets  : device, n_images+1 int64: rows of image i are
  *                   [pair_offsets[i], pair_offsets[i+1]) in canonical order;
@@ -143,6 +145,39 @@ cr_status cr_sync_status(cr_context* ctx, void* stream);
 cr_status cr_persistence_backward(cr_context* ctx, const int64_t* birth_pixel, const int64_t* death_pixel,
                                   const float* grad_birth, const float* grad_death, int64_t n_pairs,
                                   float* grad_image, int64_t n_pixels, void* stream);
+
+/* The lifetime-enhanced image of Sec. 4 (localised features), its three
+ * persistence channels: for d = 0, 1, 2,
+ *   out[d * n_pixels + p] = max (death_i - birth_i) over the rows i with
+ *                           dim_i == d located at pixel p, and 0 where none is,
+ * the difference taken in float32.  A row is located at its birth pixel
+ * (location 0) or at its death pixel (location 1, the paper's
+ * "--location death"; rows with death_pixel -1 are then skipped).  With birth
+ * locations an essential bar's lifetime is +INFINITY.  Rows with a lifetime
+ * that is not positive leave the image alone.  The rows are device arrays of
+ * n_pairs entries in any order: a plain diagram with n_pixels the image's
+ * size, or a batched one with n_pixels the packed size (image i's channel d is
+ * then out[d * n_pixels + pixel_offsets[i] ...]).  out: device, 3 * n_pixels
+ * floats, overwritten.  Stacking the image on top gives the paper's
+ * four-channel image.  A dimension outside 0..2 or a pixel index outside
+ * [0, n_pixels) gives CR_ERR_INVALID_ARGUMENT once the stream has completed
+ * (this call synchronises `stream` once). */
+cr_status cr_lifetime_image(cr_context* ctx, const int32_t* dim, const float* birth, const float* death,
+                            const int64_t* birth_pixel, const int64_t* death_pixel, int64_t n_pairs, int location,
+                            float* out, int64_t n_pixels, void* stream);
+
+/* Locations of pixels as the (x, y, z) columns of the paper's output rows
+ * (Sec. 3: the location of the cell giving birth to, or killing, a cycle):
+ * for each of the n device entries of `pixel`, q = pixel[i] - base is a flat
+ * C-order index into an image of `shape` (host, ndim extents, ndim 1..3) and
+ *   xyz[3 i] = x (the last axis), xyz[3 i + 1] = y, xyz[3 i + 2] = z,
+ * axes the image does not have being 0; pixel[i] == -1 (no death pixel) gives
+ * (-1, -1, -1).  `base` is 0 for a plain diagram and pixel_offsets[i] for image
+ * i of a batched one.  xyz: device, 3 n int32.  An index outside the image
+ * gives CR_ERR_INVALID_ARGUMENT once the stream has completed (this call
+ * synchronises `stream` once). */
+cr_status cr_pixel_coords(cr_context* ctx, const int64_t* pixel, int64_t n, int64_t base, int ndim,
+                          const int64_t* shape, int32_t* xyz, void* stream);
 
 /* Sizes seen by the last plain or batched call on this context. */
 typedef struct cr_stats {
@@ -184,8 +219,9 @@ typedef struct cr_tuning {
   int32_t front_cap;    /* ... keys of a wavefront's LDS front list, 128 .. 4032 */
 } cr_tuning;
 
-/* The parameters the context uses for ndim (2 or 3), and a validated setter
- * (INVALID_ARGUMENT for a value out of range). */
+/* The parameters the context uses for ndim (1, 2 or 3; 1D signals share the
+ * 2D setting), and a validated setter (INVALID_ARGUMENT for a value out of
+ * range). */
 cr_status cr_get_tuning(cr_context* ctx, int ndim, cr_tuning* out);
 cr_status cr_set_tuning(cr_context* ctx, int ndim, const cr_tuning* t);
 

@@ -102,6 +102,8 @@ def lib():
                                              ctypes.c_uint32, vp, vp, vp, vp, vp, vp, i64, vp, vp]
         L.cr_sync_status.argtypes = [vp, vp]
         L.cr_persistence_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, i64, vp]
+        L.cr_lifetime_image.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp, i64, vp]
+        L.cr_pixel_coords.argtypes = [vp, vp, i64, i64, i32, ctypes.POINTER(i64), vp, vp]
         L.cr_get_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
         L.cr_get_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
         batch = [vp, i32, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), i32, i32]
@@ -117,7 +119,7 @@ def lib():
         L.cr_graph_destroy.argtypes = [vp]
         L.cr_graph_destroy.restype = None
         for f in ("cr_create", "cr_persistence", "cr_persistence_batched", "cr_sync_status",
-                  "cr_persistence_backward", "cr_get_stats", "cr_get_stage_times", "cr_get_tuning",
+                  "cr_persistence_backward", "cr_lifetime_image", "cr_pixel_coords", "cr_get_stats", "cr_get_stage_times", "cr_get_tuning",
                   "cr_set_tuning", "cr_tile_variants", "cr_tile_shape", "cr_autotune_batched",
                   "cr_batched_graph_create", "cr_graph_launch", "cr_graph_sync_status"):
             getattr(L, f).restype = ctypes.c_int
@@ -151,7 +153,7 @@ class Diagram(NamedTuple):
     death_pixel: torch.Tensor  # int64, -1 for essential bars
 
 
-def _check_image(image: torch.Tensor, ndims=(2, 3)) -> torch.Tensor:
+def _check_image(image: torch.Tensor, ndims=(1, 2, 3)) -> torch.Tensor:
     if not isinstance(image, torch.Tensor) or image.device.type != "cuda":
         raise TypeError("image must be a CUDA (HIP) tensor")
     if image.dtype != torch.float32:
@@ -171,7 +173,7 @@ STAGES = ("stencil", "sort_cells", "degree0", "degree1", "degree2", "sort_rows")
 
 
 def persistence(image: torch.Tensor, maxdim: int | None = None, stage_times: bool = False) -> Diagram:
-    """Persistence diagram of a 2D image or 3D volume (float32, on the GPU).
+    """Persistence diagram of a 1D signal, 2D image or 3D volume (float32, on the GPU).
 
     With ``stage_times`` the library records HIP events between its stages;
     read them with ``stage_times()``."""
@@ -431,6 +433,42 @@ def backward(birth_pixel: torch.Tensor, death_pixel: torch.Tensor, grad_birth: t
     _check(lib().cr_persistence_backward(h, p(birth_pixel.contiguous()), p(death_pixel.contiguous()), p(gb),
                                          p(gd), n, p(grad_image), grad_image.numel(), _stream(grad_image.device)))
     return grad_image
+
+
+def lifetime_image(d, n_pixels: int, location: str = "birth") -> torch.Tensor:
+    """The three persistence channels of the lifetime-enhanced image (Sec. 4):
+    channel k holds at each pixel the largest lifetime (death - birth) of the
+    bars of degree k located there (their birth or death pixel), 0 elsewhere.
+
+    ``d`` is a Diagram or a BatchedDiagram; ``n_pixels`` the image size (or the
+    packed size).  Returns a flat (3, n_pixels) float32 tensor: reshape a plain
+    image's channels with ``.view(3, *shape)``; image i of a batch has
+    ``out[:, pixel_offsets[i]:pixel_offsets[i + 1]]``."""
+    if location not in ("birth", "death"):
+        raise ValueError("location must be 'birth' or 'death'")
+    dev = d.birth.device
+    h, _ = _context(dev)
+    out = torch.empty((3, int(n_pixels)), dtype=torch.float32, device=dev)
+    t = [x.contiguous() for x in (d.dim, d.birth, d.death, d.birth_pixel, d.death_pixel)]
+    p = lambda x: ctypes.c_void_p(x.data_ptr())
+    _check(lib().cr_lifetime_image(h, *(p(x) for x in t), int(t[0].shape[0]), 1 if location == "death" else 0,
+                                   p(out), int(n_pixels), _stream(dev)))
+    return out
+
+
+def pixel_coords(pixel: torch.Tensor, shape, base: int = 0) -> torch.Tensor:
+    """(x, y, z) int32 rows of flat pixel indices (minus ``base``) in an image of
+    ``shape``: the location columns of the paper's output rows; -1 gives
+    (-1, -1, -1)."""
+    dev = pixel.device
+    h, _ = _context(dev)
+    pixel = pixel.contiguous()
+    n = int(pixel.shape[0])
+    out = torch.empty((n, 3), dtype=torch.int32, device=dev)
+    shp = (ctypes.c_int64 * len(shape))(*[int(x) for x in shape])
+    _check(lib().cr_pixel_coords(h, ctypes.c_void_p(pixel.data_ptr()), n, int(base), len(shape), shp,
+                                 ctypes.c_void_p(out.data_ptr()), _stream(dev)))
+    return out
 
 
 class PersistenceFn(torch.autograd.Function):

@@ -37,6 +37,10 @@ void launch_img_offsets(const uint32_t* cnt, const uint32_t* img_status, int nim
 void launch_backward(const int64_t* bpix, const int64_t* dpix, const float* gb, const float* gd, int64_t n,
                      float* grad, int64_t n_pixels, uint32_t* bad, hipStream_t s);
 void launch_check_empty(const unsigned long long* count, Status* st, hipStream_t s);
+void launch_lifetime(const int32_t* dim, const float* birth, const float* death, const int64_t* loc, int64_t n,
+                     float* out, int64_t n_pixels, int skip_missing, uint32_t* bad, hipStream_t s);
+void launch_pixel_coords(const int64_t* pixel, int64_t n, int64_t base, const int64_t ext[3], int32_t* xyz,
+                         uint32_t* bad, hipStream_t s);
 bool stencil_tile(int ndim, int variant, int ext[3]);
 
 }  // namespace cr
@@ -131,14 +135,18 @@ namespace {
 // counters block: surv_count, dim_count[4], cand_count, arena_top, lists[4], wave work counter
 enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* four words */, C_WORK = 11, C_WORDS = 12 };
 
+// A 1D signal lies on one line of the grid (Sec. 2): it runs as a 1 x n image,
+// with the 2D launch parameters.
+int grid_ndim(int ndim) { return ndim == 1 ? 2 : ndim; }
+
 cr_status build_problem(Problem& pb, int nimg, const int64_t* pixel_offsets, const int64_t* shapes, int ndim,
                         int maxdim, int tile_variant) {
   if (nimg < 1) return fail(CR_ERR_INVALID_ARGUMENT, "n_images must be >= 1");
-  if (ndim != 2 && ndim != 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
+  if (ndim < 1 || ndim > 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 1, 2 or 3");
   if (maxdim < 0) return fail(CR_ERR_INVALID_ARGUMENT, "maxdim must be >= 0");
   if (!shapes) return fail(CR_ERR_INVALID_ARGUMENT, "shape is NULL");
   pb.nimg = nimg;
-  pb.ndim = ndim;
+  pb.ndim = grid_ndim(ndim);
   pb.maxdim = std::min(maxdim, ndim - 1);
   pb.imgs.resize(nimg);
   pb.tiles.clear();
@@ -146,7 +154,7 @@ cr_status build_problem(Problem& pb, int nimg, const int64_t* pixel_offsets, con
   pb.N = 0;
   uint64_t maxN = 1, maxP = 1;
   int tile[3];
-  if (!stencil_tile(ndim, tile_variant, tile)) return fail(CR_ERR_INVALID_ARGUMENT, "bad stencil tile variant");
+  if (!stencil_tile(pb.ndim, tile_variant, tile)) return fail(CR_ERR_INVALID_ARGUMENT, "bad stencil tile variant");
   for (int i = 0; i < nimg; ++i) {
     int64_t n[3] = {1, 1, 1};
     for (int a = 0; a < ndim; ++a) {
@@ -530,7 +538,7 @@ cr_status check_batch_args(cr_context* ctx, const BatchArgs& a) {
   if (a.capacity < 0 || (a.capacity > 0 && (!a.dim || !a.birth || !a.death || !a.birth_pixel || !a.death_pixel)))
     return fail(CR_ERR_INVALID_ARGUMENT, "bad output buffers");
   if (a.flags != 0) return fail(CR_ERR_INVALID_ARGUMENT, "flags must be 0");
-  if (a.ndim != 2 && a.ndim != 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
+  if (a.ndim < 1 || a.ndim > 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 1, 2 or 3");
   if (a.n_images < 1) return fail(CR_ERR_INVALID_ARGUMENT, "n_images must be >= 1");
   if (a.pixel_offsets[0] != 0) return fail(CR_ERR_INVALID_ARGUMENT, "pixel_offsets[0] must be 0");
   return CR_OK;
@@ -545,7 +553,7 @@ cr_status enqueue_batch(cr_context* ctx, const BatchArgs& a, hipStream_t s, bool
   cr_status rc = enqueue_pipeline(ctx, a.packed, s, &cand, upload);
   if (rc != CR_OK) return rc;
   const Plan& p = ctx->plan;
-  launch_gather(ctx->tune[a.ndim].grid, cand, at<unsigned long long>(ctx, p.counters) + C_CAND,
+  launch_gather(ctx->tune[grid_ndim(a.ndim)].grid, cand, at<unsigned long long>(ctx, p.counters) + C_CAND,
                 (uint64_t)a.capacity, a.packed, at<ImgDesc>(ctx, p.imgs), ctx->prob.L, a.dim, a.birth, a.death,
                 a.birth_pixel, a.death_pixel, s);
   launch_img_offsets(at<uint32_t>(ctx, p.img_pairs), at<uint32_t>(ctx, p.img_status), a.n_images,
@@ -647,8 +655,8 @@ cr_status cr_persistence(cr_context* ctx, const float* image, int ndim, const in
   ctx->timing = (flags & CR_FLAG_STAGE_TIMES) != 0;
   ctx->sync_allowed = true;
   hipStream_t s = (hipStream_t)stream;
-  if (ndim != 2 && ndim != 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
-  cr_status rc = build_problem(ctx->prob, 1, nullptr, shape, ndim, maxdim, ctx->tune[ndim].tile);
+  if (ndim < 1 || ndim > 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 1, 2 or 3");
+  cr_status rc = build_problem(ctx->prob, 1, nullptr, shape, ndim, maxdim, ctx->tune[grid_ndim(ndim)].tile);
   if (rc != CR_OK) return rc;
   for (int attempt = 0; attempt < 4; ++attempt) {
     ctx->plan = make_plan(ctx->prob, ctx->arena_entries);
@@ -695,7 +703,7 @@ cr_status cr_persistence(cr_context* ctx, const float* image, int ndim, const in
     out->birth_pixel = (int64_t*)b;
     b += align_up(8 * n, 256);
     out->death_pixel = (int64_t*)b;
-    launch_gather(ctx->tune[ndim].grid, cand, at<unsigned long long>(ctx, ctx->plan.counters) + C_CAND, (uint64_t)n,
+    launch_gather(ctx->tune[grid_ndim(ndim)].grid, cand, at<unsigned long long>(ctx, ctx->plan.counters) + C_CAND, (uint64_t)n,
                   image,
                   at<ImgDesc>(ctx, ctx->plan.imgs), ctx->prob.L, out->dim, out->birth, out->death,
                   out->birth_pixel, out->death_pixel, s);
@@ -729,7 +737,7 @@ cr_status cr_persistence_batched(cr_context* ctx, int n_images, const float* pac
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   ctx->last_batched_valid = false;
-  rc = build_problem(ctx->prob, n_images, pixel_offsets, shapes, ndim, maxdim, ctx->tune[ndim].tile);
+  rc = build_problem(ctx->prob, n_images, pixel_offsets, shapes, ndim, maxdim, ctx->tune[grid_ndim(ndim)].tile);
   if (rc != CR_OK) return rc;
   ctx->plan = make_plan(ctx->prob, ctx->arena_entries);
   rc = ensure_scratch(ctx, ctx->plan.total);
@@ -751,6 +759,32 @@ cr_status cr_sync_status(cr_context* ctx, void* stream) {
   return status_error(h.st, &arena_over);
 }
 
+// The context's argument-check flag, cleared on stream s (allocated on first use).
+cr_status flag_begin(cr_context* ctx, hipStream_t s, uint32_t** bad) {
+  if (!ctx->bwd_flag && hipMalloc(&ctx->bwd_flag, 256) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->bwd_flag = nullptr;
+    return fail(CR_ERR_OUT_OF_MEMORY, "hipMalloc failed");
+  }
+  *bad = ctx->bwd_flag;
+  launch_fill_u32(*bad, 0, 1, s);
+  return CR_OK;
+}
+
+// Waits for stream s and reports the flag set by the kernels in between.
+cr_status flag_end(cr_context* ctx, hipStream_t s, const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(CR_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  cr_status rc = ensure_stage(ctx, 4);
+  if (rc != CR_OK) return rc;
+  HIP_TRY(hipMemcpyAsync(ctx->host_stage, ctx->bwd_flag, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  uint32_t hb = 0;
+  std::memcpy(&hb, ctx->host_stage, 4);
+  if (hb) return fail(CR_ERR_INVALID_ARGUMENT, what);
+  return CR_OK;
+}
+
 cr_status cr_persistence_backward(cr_context* ctx, const int64_t* birth_pixel, const int64_t* death_pixel,
                                   const float* grad_birth, const float* grad_death, int64_t n_pairs,
                                   float* grad_image, int64_t n_pixels, void* stream) {
@@ -761,23 +795,51 @@ cr_status cr_persistence_backward(cr_context* ctx, const int64_t* birth_pixel, c
     return fail(CR_ERR_INVALID_ARGUMENT, "a required pointer is NULL");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  if (!ctx->bwd_flag && hipMalloc(&ctx->bwd_flag, 256) != hipSuccess) {
-    (void)hipGetLastError();
-    ctx->bwd_flag = nullptr;
-    return fail(CR_ERR_OUT_OF_MEMORY, "hipMalloc failed");
-  }
-  uint32_t* bad = ctx->bwd_flag;
-  launch_fill_u32(bad, 0, 1, s);
-  cr_status rc;
-  launch_backward(birth_pixel, death_pixel, grad_birth, grad_death, n_pairs, grad_image, n_pixels, bad, s);
-  rc = ensure_stage(ctx, 4);
+  uint32_t* bad = nullptr;
+  cr_status rc = flag_begin(ctx, s, &bad);
   if (rc != CR_OK) return rc;
-  HIP_TRY(hipMemcpyAsync(ctx->host_stage, bad, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  uint32_t hb = 0;
-  std::memcpy(&hb, ctx->host_stage, 4);
-  if (hb) return fail(CR_ERR_INVALID_ARGUMENT, "a pixel index is out of range");
-  return CR_OK;
+  launch_backward(birth_pixel, death_pixel, grad_birth, grad_death, n_pairs, grad_image, n_pixels, bad, s);
+  return flag_end(ctx, s, "a pixel index is out of range");
+}
+
+cr_status cr_lifetime_image(cr_context* ctx, const int32_t* dim, const float* birth, const float* death,
+                            const int64_t* birth_pixel, const int64_t* death_pixel, int64_t n_pairs, int location,
+                            float* out, int64_t n_pixels, void* stream) {
+  if (!ctx) return fail(CR_ERR_INVALID_ARGUMENT, "ctx is NULL");
+  if (n_pairs < 0 || n_pixels < 0) return fail(CR_ERR_INVALID_ARGUMENT, "negative size");
+  if (location != 0 && location != 1) return fail(CR_ERR_INVALID_ARGUMENT, "location must be 0 (birth) or 1 (death)");
+  if (n_pixels > 0 && !out) return fail(CR_ERR_INVALID_ARGUMENT, "out is NULL");
+  if (n_pairs > 0 && (!dim || !birth || !death || !(location ? death_pixel : birth_pixel)))
+    return fail(CR_ERR_INVALID_ARGUMENT, "a required pointer is NULL");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* bad = nullptr;
+  cr_status rc = flag_begin(ctx, s, &bad);
+  if (rc != CR_OK) return rc;
+  launch_fill_u32(reinterpret_cast<uint32_t*>(out), 0, 3 * (uint64_t)n_pixels, s);
+  launch_lifetime(dim, birth, death, location ? death_pixel : birth_pixel, n_pairs, out, n_pixels, location, bad, s);
+  return flag_end(ctx, s, "a dimension or pixel index is out of range");
+}
+
+cr_status cr_pixel_coords(cr_context* ctx, const int64_t* pixel, int64_t n, int64_t base, int ndim,
+                          const int64_t* shape, int32_t* xyz, void* stream) {
+  if (!ctx) return fail(CR_ERR_INVALID_ARGUMENT, "ctx is NULL");
+  if (n < 0) return fail(CR_ERR_INVALID_ARGUMENT, "negative size");
+  if (ndim < 1 || ndim > 3 || !shape) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 1, 2 or 3");
+  int64_t ext[3] = {1, 1, 1};
+  for (int a = 0; a < ndim; ++a) {
+    if (shape[a] < 1 || shape[a] > (1 << 29)) return fail(CR_ERR_INVALID_ARGUMENT, "bad extent");
+    ext[3 - ndim + a] = shape[a];
+  }
+  if (n == 0) return CR_OK;
+  if (!pixel || !xyz) return fail(CR_ERR_INVALID_ARGUMENT, "a required pointer is NULL");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* bad = nullptr;
+  cr_status rc = flag_begin(ctx, s, &bad);
+  if (rc != CR_OK) return rc;
+  launch_pixel_coords(pixel, n, base, ext, xyz, bad, s);
+  return flag_end(ctx, s, "a pixel index is out of range");
 }
 
 cr_status cr_get_stage_times(cr_context* ctx, float* ms, int capacity, int* n_stages) {
@@ -796,14 +858,15 @@ cr_status cr_get_stats(cr_context* ctx, cr_stats* out) {
 
 cr_status cr_get_tuning(cr_context* ctx, int ndim, cr_tuning* out) {
   if (!ctx || !out) return fail(CR_ERR_INVALID_ARGUMENT, "NULL argument");
-  if (ndim != 2 && ndim != 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
-  *out = ctx->tune[ndim];
+  if (ndim < 1 || ndim > 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 1, 2 or 3");
+  *out = ctx->tune[grid_ndim(ndim)];
   return CR_OK;
 }
 
 cr_status cr_set_tuning(cr_context* ctx, int ndim, const cr_tuning* t) {
   if (!ctx || !t) return fail(CR_ERR_INVALID_ARGUMENT, "NULL argument");
-  if (ndim != 2 && ndim != 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
+  if (ndim < 1 || ndim > 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 1, 2 or 3");
+  ndim = grid_ndim(ndim);
   cr_status rc = check_tuning(ndim, *t);
   if (rc != CR_OK) return rc;
   ctx->tune[ndim] = *t;
@@ -837,7 +900,7 @@ cr_status cr_batched_graph_create(cr_context* ctx, int n_images, const float* pa
   cr_graph* g = new (std::nothrow) cr_graph();
   if (!g) return fail(CR_ERR_OUT_OF_MEMORY, "graph allocation failed");
   g->ctx = ctx;
-  rc = build_problem(g->own.prob, n_images, pixel_offsets, shapes, ndim, maxdim, ctx->tune[ndim].tile);
+  rc = build_problem(g->own.prob, n_images, pixel_offsets, shapes, ndim, maxdim, ctx->tune[grid_ndim(ndim)].tile);
   if (rc != CR_OK) {
     delete g;
     return rc;
@@ -924,10 +987,11 @@ cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  const cr_tuning start = ctx->tune[ndim];
+  const int nd = grid_ndim(ndim);
+  const cr_tuning start = ctx->tune[nd];
   // time one candidate: a warm-up call, then `repeats` timed calls
   auto time_it = [&](const cr_tuning& t, float* ms) -> cr_status {
-    ctx->tune[ndim] = t;
+    ctx->tune[nd] = t;
     for (int r = 0; r <= repeats; ++r) {
       if (r == 1) HIP_TRY(hipEventRecord(e0, s));
       cr_status c = cr_persistence_batched(ctx, n_images, packed, pixel_offsets, shapes, ndim, maxdim, 0, stream,
@@ -973,7 +1037,7 @@ cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  ctx->tune[ndim] = rc == CR_OK ? best : start;
+  ctx->tune[nd] = rc == CR_OK ? best : start;
   if (rc == CR_OK && chosen) *chosen = best;
   return rc;
 }

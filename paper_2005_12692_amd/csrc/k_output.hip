@@ -88,6 +88,52 @@ __global__ void k_backward(const int64_t* __restrict__ bpix, const int64_t* __re
   }
 }
 
+// Lifetime-enhanced image channels (Sec. 4): out[k * n_pixels + p] = max over
+// the bars of degree k located at pixel p of death - birth.  The location is
+// the birth pixel, or the death pixel (essential bars then have none and are
+// skipped).  Lifetimes are positive (bars of positive length, +inf for an
+// essential bar), so the maximum is taken on their bit patterns, which order
+// as unsigned integers; a non-positive or NaN lifetime leaves the pixel alone.
+__global__ void k_lifetime(const int32_t* __restrict__ dim, const float* __restrict__ birth,
+                           const float* __restrict__ death, const int64_t* __restrict__ loc, int64_t n,
+                           float* __restrict__ out, int64_t n_pixels, int skip_missing, uint32_t* __restrict__ bad) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t k = dim[i];
+    const int64_t p = loc[i];
+    if (p == -1 && skip_missing) continue;
+    if (k < 0 || k > 2 || p < 0 || p >= n_pixels) {
+      atomicOr(bad, 1u);
+      continue;
+    }
+    const float life = death[i] - birth[i];
+    if (!(life > 0.0f)) continue;
+    atomicMax(reinterpret_cast<unsigned int*>(out) + (k * n_pixels + p), __float_as_uint(life));
+  }
+}
+
+// (x, y, z) of flat pixel indices (minus base) in an image of extents n[0..2]
+// (z, y, x; 1 for absent axes); -1 gives (-1, -1, -1).
+__global__ void k_pixel_coords(const int64_t* __restrict__ pixel, int64_t n, int64_t base, int64_t nz,
+                               int64_t ny, int64_t nx, int32_t* __restrict__ xyz, uint32_t* __restrict__ bad) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = pixel[i];
+    int32_t x = -1, y = -1, z = -1;
+    if (q != -1) {
+      const int64_t p = q - base;
+      if (p < 0 || p >= nz * ny * nx) {
+        atomicOr(bad, 1u);
+      } else {
+        x = (int32_t)(p % nx);
+        y = (int32_t)((p / nx) % ny);
+        z = (int32_t)(p / (nx * ny));
+      }
+    }
+    xyz[3 * i] = x;
+    xyz[3 * i + 1] = y;
+    xyz[3 * i + 2] = z;
+  }
+}
+
 // Raises the iteration flag if a pair of reduction lists is still non-empty.
 __global__ void k_check_empty(const unsigned long long* count, Status* st) {
   if (count[0] || count[1]) raise_flag(st, &st->iter_cap);
@@ -121,6 +167,22 @@ void launch_backward(const int64_t* bpix, const int64_t* dpix, const float* gb, 
   int64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   k_backward<<<(unsigned)blocks, 256, 0, s>>>(bpix, dpix, gb, gd, n, grad, n_pixels, bad);
+}
+
+void launch_lifetime(const int32_t* dim, const float* birth, const float* death, const int64_t* loc, int64_t n,
+                     float* out, int64_t n_pixels, int skip_missing, uint32_t* bad, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_lifetime<<<(unsigned)blocks, 256, 0, s>>>(dim, birth, death, loc, n, out, n_pixels, skip_missing, bad);
+}
+
+void launch_pixel_coords(const int64_t* pixel, int64_t n, int64_t base, const int64_t ext[3], int32_t* xyz,
+                         uint32_t* bad, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  k_pixel_coords<<<(unsigned)blocks, 256, 0, s>>>(pixel, n, base, ext[0], ext[1], ext[2], xyz, bad);
 }
 
 }  // namespace cr

@@ -65,6 +65,10 @@ def test_null_context_calls_fail_cleanly(libcr):
     assert libcr.cr_persistence(None, None, 2, None, 1, 0, None, None) == 1
     libcr.cr_persistence_backward.restype = ctypes.c_int
     assert libcr.cr_persistence_backward(None, None, None, None, None, 0, None, 0, None) == 1
+    libcr.cr_lifetime_image.restype = ctypes.c_int
+    assert libcr.cr_lifetime_image(None, None, None, None, None, None, 0, 0, None, 0, None) == 1
+    libcr.cr_pixel_coords.restype = ctypes.c_int
+    assert libcr.cr_pixel_coords(None, None, 0, 0, 2, None, None, None) == 1
 
 
 def test_package_does_not_import_the_oracle():
