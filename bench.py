@@ -227,13 +227,62 @@ def bench_fwd_bwd(reps: int = 2) -> dict:
             "batched_vs_loop": p_s / b_s, "gradients_agree": same and nact == nact_p}
 
 
+def bench_next(x, d, reps: int = 3) -> dict:
+    """The widened inputs and outputs: a masked volume (+inf outside the
+    inscribed ball), a long 1D signal, and the lifetime image of the 256^3
+    diagram."""
+    import torch
+    import paper_2005_12692_amd as cr
+    import synth
+    n = x.shape[0]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    mask = torch.from_numpy(synth.ball_mask((n, n, n))).cuda()
+    xm = torch.where(mask, x, torch.full_like(x, float("inf")))
+    m_s = timed(lambda: cr.persistence(xm, maxdim=2))
+    m_rows = int(cr.persistence(xm, maxdim=2).dim.shape[0])
+    print(f"next: masked volume {m_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    ns = 1 << 24
+    sig = torch.from_numpy(synth.random_walk(ns)).cuda()
+    s_s = timed(lambda: cr.persistence(sig))
+    s_rows = int(cr.persistence(sig).dim.shape[0])
+    print(f"next: 1D signal {s_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    npix = x.numel()
+    rows = int(d.dim.shape[0])
+    l_s = timed(lambda: cr.lifetime_image(d, npix, "birth"))
+    # per call: read dim, birth, death (4 B each) and the location (8 B) of
+    # every row, one 4 B max per row, and clear 3 channels of 4 B per pixel
+    lbytes = rows * (4 + 4 + 4 + 8 + 4) + 3 * 4 * npix
+    l_ach = lbytes / l_s / 1e9
+    print(f"next: lifetime image {l_s * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    cells = (2 * n - 1) ** 3
+    return {"masked_volume": {"workload": "the same 256^3 volume, +inf outside the inscribed ball; H0+H1+H2",
+                              "ms": m_s * 1e3, "cells_per_s": cells / m_s, "rows": m_rows},
+            "signal_1d": {"workload": "random walk of 2^24 N(0,1) steps (seed 7); H0",
+                          "ms": s_s * 1e3, "samples_per_s": ns / s_s, "rows": s_rows},
+            "lifetime_image": {"workload": "3 channels of the 256^3 diagram, birth locations",
+                               "ms": l_s * 1e3, "rows": rows, "algorithmic_bytes": lbytes,
+                               "achieved_GBs": l_ach, "peak_GBs": HBM_PEAK_GBS, "frac": l_ach / HBM_PEAK_GBS,
+                               "note": "whole entry point: clear, scatter and the one synchronising "
+                                       "read-back of the argument-check flag"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-forms", action="store_true", help="skip the batched and fwd+bwd measurements")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched, fwd+bwd, masked, 1D and lifetime-image measurements")
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a 256 MiB device copy (the reference kernel for profiler byte counts)")
     args = ap.parse_args()
@@ -339,6 +388,7 @@ def main():
     if not args.no_forms:
         line["batched"] = bench_batched()
         line["fwd_bwd"] = bench_fwd_bwd()
+        line["next"] = bench_next(x, d)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(vol)
     print(json.dumps(line), flush=True)

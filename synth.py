@@ -20,6 +20,11 @@ Recipes (all arithmetic in float64, cast to float32 at the end, -0.0 -> +0.0):
   sigma = 2.
 * ``batch3d_grf(n_volumes, side, sigma, seed)``: GRF volumes, one spawned stream
   per volume.
+* ``random_walk(n, seed)``: a 1D time series, the running sum of n i.i.d.
+  N(0,1) steps.
+* ``ball_mask(shape, hole)``: True inside the ball inscribed in the grid and
+  outside the concentric ball of radius ``hole`` times the first; a masked
+  input takes +inf where it is False (pixels outside the domain).
 """
 from __future__ import annotations
 
@@ -93,6 +98,19 @@ def batch2d(n_images: int = 512, seed: int = 3, lo: int = 28, hi: int = 512):
 def batch3d_grf(n_volumes: int = 32, side: int = 128, sigma: float = 3.0, seed: int = 4):
     streams = np.random.SeedSequence(seed).spawn(n_volumes)
     return [grf((side,) * 3, sigma, np.random.default_rng(s)) for s in streams]
+
+
+def random_walk(n: int, seed: int = 7) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return _finish(np.cumsum(rng.standard_normal(n)))
+
+
+def ball_mask(shape, hole: float = 0.0) -> np.ndarray:
+    grids = np.indices(tuple(shape), dtype=np.float64)
+    c = [(s - 1) / 2 for s in shape]
+    r2 = sum((g - ci) ** 2 for g, ci in zip(grids, c))
+    rmax = (min(shape) - 1) / 2
+    return (r2 <= rmax ** 2) & (r2 >= (hole * rmax) ** 2)
 
 
 def config(name: str, small: bool = False):

@@ -6,6 +6,8 @@ Each entry records the digest of the float32 input bytes and of the diagram
 bytes (dim int32, birth float32, death float32, birth_pixel int64, death_pixel
 int64, concatenated, canonical row order, pixel indices local to the image) and
 the number of rows per dimension.  Run: python tests/golden/make_oracle_digests.py
+[NAME ...] (with names, only those entries are computed and merged into the
+existing file).
 """
 import concurrent.futures as cf
 import hashlib
@@ -43,7 +45,28 @@ def entry(img):
             "rows_per_dim": np.bincount(d.dim, minlength=3).tolist()}
 
 
+def masked_c3():
+    """The 256^3 volume with +inf outside the inscribed ball."""
+    v = synth.config("C3")
+    return np.where(synth.ball_mask(v.shape), v, np.float32(np.inf)).astype(np.float32)
+
+
+def walk_2_24():
+    return synth.random_walk(1 << 24)
+
+
+EXTRA = {"C3_masked": masked_c3, "walk_2_24": walk_2_24}
+
+
 def main():
+    if len(sys.argv) > 1:
+        out = json.load(open(OUT))
+        t = time.time()
+        for name in sys.argv[1:]:
+            out[name] = entry(EXTRA[name]())
+            print(f"{name}: {time.time() - t:.0f} s", flush=True)
+        json.dump(out, open(OUT, "w"), indent=1)
+        return
     out = {}
     t = time.time()
     with cf.ThreadPoolExecutor(8) as ex:
@@ -53,6 +76,8 @@ def main():
         out["C4"] = c4.result()
         out["C5"] = c5.result()
     out["C2"] = entry(synth.config("C2"))
+    for name, make in EXTRA.items():
+        out[name] = entry(make())
     json.dump(out, open(OUT, "w"), indent=1)
     print(f"wrote {OUT} in {time.time() - t:.0f} s")
 

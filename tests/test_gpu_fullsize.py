@@ -161,3 +161,34 @@ def test_batch_32_volumes_forward_backward():
         assert abs(g0[p] - fd) <= 1e-6 * abs(fd) + 4 * np.finfo(np.float32).eps * contrib, (p, g0[p], fd)
         checked += 1
     assert checked >= 8
+
+
+def test_masked_volume_256():
+    m, dg = _digests()
+    vol = m.masked_c3()
+    rows = [t.cpu().numpy() for t in cr.persistence(torch.from_numpy(vol).cuda())]
+    _invariants(vol, rows)
+    check_against_oracle(vol, rows, dg.get("C3_masked"), m, "256^3 blobs, +inf outside the ball")
+
+
+def test_signal_2_24():
+    m, dg = _digests()
+    sig = m.walk_2_24()
+    rows = [t.cpu().numpy() for t in cr.persistence(torch.from_numpy(sig).cuda())]
+    _invariants(sig, rows)
+    check_against_oracle(sig, rows, dg.get("walk_2_24"), m, "random walk of 2^24 steps")
+
+
+def test_lifetime_image_256():
+    # the 256^3 diagram is pinned to the oracle above; here the lifetime image
+    # must be the per-pixel maximum of death - birth over the rows located there
+    vol = synth.config("C3")
+    d = cr.persistence(torch.from_numpy(vol).cuda())
+    dim, birth, death, bp, dp = [t.cpu().numpy() for t in d]
+    life = (death - birth).astype(np.float32)
+    for location, pix in (("birth", bp), ("death", dp)):
+        got = cr.lifetime_image(d, vol.size, location).cpu().numpy()
+        want = np.zeros((3, vol.size), np.float32)
+        keep = pix >= 0
+        np.maximum.at(want, (dim[keep], pix[keep]), life[keep])
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), location

@@ -18,14 +18,6 @@ def masked(img, mask):
     return np.where(mask, img, np.float32(np.inf)).astype(np.float32)
 
 
-def disk_mask(shape, hole=0.0):
-    grids = np.indices(shape)
-    c = [(s - 1) / 2 for s in shape]
-    r2 = sum((g - ci) ** 2 for g, ci in zip(grids, c))
-    rmax = (min(shape) - 1) / 2
-    return (r2 <= rmax ** 2) & (r2 >= (hole * rmax) ** 2)
-
-
 @pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 1000, 100003])
 def test_signals_1d(n):
     rng = np.random.default_rng(n)
@@ -56,7 +48,7 @@ def test_signals_batched():
 
 @pytest.mark.parametrize("shape,hole", [((33, 40), 0.0), ((41, 41), 0.45), ((64, 50), 0.3)])
 def test_masked_2d(shape, hole):
-    m = disk_mask(shape, hole)
+    m = synth.ball_mask(shape, hole)
     check(masked(synth.uniform2d(shape, shape[0]), m), label=f"masked uniform {shape}")
     check(masked(synth.grf_seeded(shape, 2.0, shape[1]), m), label=f"masked grf {shape}")
     rng = np.random.default_rng(shape[1])
@@ -65,7 +57,7 @@ def test_masked_2d(shape, hole):
 
 @pytest.mark.parametrize("shape,hole", [((17, 19, 21), 0.0), ((21, 21, 21), 0.5)])
 def test_masked_3d(shape, hole):
-    m = disk_mask(shape, hole)
+    m = synth.ball_mask(shape, hole)
     check(masked(synth.grf_seeded(shape, 1.5, shape[0]), m), label=f"masked volume {shape}")
     rng = np.random.default_rng(shape[2])
     check(masked(rng.random(shape, dtype=np.float32), m), label=f"masked noise {shape}")
@@ -74,7 +66,7 @@ def test_masked_3d(shape, hole):
 def test_masked_batched():
     imgs = []
     for i, shape in enumerate([(30, 31), (45, 28), (12, 60), (50, 50)]):
-        imgs.append(masked(synth.uniform2d(shape, i), disk_mask(shape, 0.2 * i)))
+        imgs.append(masked(synth.uniform2d(shape, i), synth.ball_mask(shape, 0.2 * i)))
     packed, shapes, offs = cr.pack([torch.from_numpy(a).cuda() for a in imgs])
     d = cr.persistence_batched(packed, shapes, offs)
     po = d.pair_offsets.cpu()
@@ -89,7 +81,7 @@ LIFE_CASES = [
     ("signal", lambda: np.random.default_rng(1).random(5000, dtype=np.float32)),
     ("uniform 2D", lambda: synth.uniform2d((70, 90), 5)),
     ("grf 2D", lambda: synth.grf_seeded((256, 256), 3.0, 2)),
-    ("masked 2D", lambda: masked(synth.uniform2d((41, 41), 4), disk_mask((41, 41), 0.4))),
+    ("masked 2D", lambda: masked(synth.uniform2d((41, 41), 4), synth.ball_mask((41, 41), 0.4))),
     ("grf 3D", lambda: synth.grf_seeded((20, 22, 24), 1.5, 6)),
     ("ties 3D", lambda: np.random.default_rng(2).integers(0, 3, size=(9, 10, 11)).astype(np.float32)),
 ]

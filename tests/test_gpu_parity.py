@@ -147,7 +147,7 @@ def test_nan_and_bad_arguments():
         cr.persistence(torch.rand(8, 8, device="cuda"), maxdim=-1)
     assert e.value.code == cr.CR_ERR_INVALID_ARGUMENT
     with pytest.raises((TypeError, ValueError)):
-        cr.persistence(torch.rand(8, device="cuda"))
+        cr.persistence(torch.rand(2, 3, 4, 5, device="cuda"))  # four axes (1D signals are valid)
     # the context is still usable after errors
     check(synth.uniform2d((16, 16), 2), label="after errors")
 
