@@ -136,3 +136,31 @@ def test_bad_rows_are_errors():
         cr.pixel_coords(d.birth_pixel, (4, 4))
     # the context still works afterwards
     check(img, label="after errors")
+
+
+def test_signals_graph_and_autotune():
+    # the graph and autotuner entry points take ndim 1 too (the 2D setting)
+    rng = np.random.default_rng(9)
+    sigs = [synth.random_walk(int(n), int(n)) for n in rng.integers(2, 20000, size=24)]
+    packed, shapes, offs = cr.pack([torch.from_numpy(s).cuda() for s in sigs])
+    eager = cr.persistence_batched(packed, shapes, offs)
+    cap = int(eager.pair_offsets[-1].item())
+    before = cr.get_tuning(2)
+    try:
+        tuned = cr.autotune(packed, shapes, offs, capacity=cap, repeats=1)
+        assert cr.get_tuning(1) == cr.get_tuning(2) == tuned
+        g = cr.BatchedGraph(packed, shapes, offs, capacity=cap)
+        try:
+            for _ in range(2):
+                g.launch()
+                got = g.result()
+                po = got.pair_offsets.cpu()
+                for i in (0, 7, 23):
+                    rows = [t.cpu().numpy() for t in got.image(i, po)]
+                    rows[3] = rows[3] - offs[i]
+                    rows[4] = np.where(rows[4] >= 0, rows[4] - offs[i], -1)
+                    assert_same(rows, oracle_diag(sigs[i]), f"graph signal {i}")
+        finally:
+            g.close()
+    finally:
+        cr.set_tuning(2, **before)
