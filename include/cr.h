@@ -217,6 +217,11 @@ typedef struct cr_tuning {
                            many additions (>= 1) */
   int32_t wave_short;   /* ... a list of at most this many short columns is run one per wavefront */
   int32_t front_cap;    /* ... keys of a wavefront's LDS front list, 128 .. 4032 */
+  int32_t wave_yield;   /* ... a column reduced one per wavefront (or workgroup) is stored
+                           after this many additions in one round and continues in the next,
+                           so that the rounds stay short and the columns of different images
+                           (or regions) do not wait for one long column; 0 = never.  In a
+                           batched call it applies to the first 64 rounds only. */
 } cr_tuning;
 
 /* The parameters the context uses for ndim (1, 2 or 3; 1D signals share the

@@ -50,7 +50,8 @@ class _Stats(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("grid", ctypes.c_int32), ("long_len", ctypes.c_int32),
-                ("yield_iters", ctypes.c_int32), ("wave_short", ctypes.c_int32), ("front_cap", ctypes.c_int32)]
+                ("yield_iters", ctypes.c_int32), ("wave_short", ctypes.c_int32), ("front_cap", ctypes.c_int32),
+                ("wave_yield", ctypes.c_int32)]
 
 
 TUNING_FIELDS = tuple(f for f, _ in _Tuning._fields_)

@@ -81,6 +81,7 @@ cr_tuning default_tuning(int ndim) {
   t.yield_iters = 1024;
   t.wave_short = 4096;
   t.front_cap = 1024;
+  t.wave_yield = 128;
   (void)ndim;
   return t;
 }
@@ -288,21 +289,24 @@ void mark(cr_context* ctx, int i, hipStream_t s) {
 // Rounds of the degree-1 reduction.  With host synchronisation allowed (plain
 // call) the host checks the active count every ROUND_BATCH rounds; otherwise a
 // fixed budget of rounds is enqueued (rounds with an empty list return at once)
-// and a leftover list raises the iteration flag.
+// and a leftover list raises the iteration flag.  Columns that yield (wave_yield)
+// take more rounds, so within the budget they yield only in the first
+// YIELD_ROUNDS rounds; the rest run every column to its end as without yields.
 constexpr int ROUND_BATCH = 4;
-constexpr int ROUND_BUDGET = 96;
+constexpr int ROUND_BUDGET = 128;
+constexpr int YIELD_ROUNDS = 64;
 constexpr int ROUND_LIMIT = 4096;
 
 cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts,
                      hipStream_t s) {
   ctx->rounds = 0;
   if (!ctx->sync_allowed) {
-    launch_h1_rounds(RGRID, R, lists, counts, 0, ROUND_BUDGET, s);
+    launch_h1_rounds(RGRID, R, lists, counts, 0, ROUND_BUDGET, YIELD_ROUNDS, s);
     launch_check_empty(counts + 2 * (ROUND_BUDGET & 1), R.st, s);
     return CR_OK;
   }
   for (int r = 0; r < ROUND_LIMIT; r += ROUND_BATCH) {
-    launch_h1_rounds(RGRID, R, lists, counts, r, ROUND_BATCH, s);
+    launch_h1_rounds(RGRID, R, lists, counts, r, ROUND_BATCH, ROUND_LIMIT, s);
     const int cur = (r + ROUND_BATCH) & 1;
     cr_status rc = ensure_stage(ctx, 64);
     if (rc != CR_OK) return rc;
@@ -418,6 +422,7 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     R.yield_iters = (uint32_t)tu.yield_iters;
     R.wave_short = (uint32_t)tu.wave_short;
     R.front_cap = (uint32_t)tu.front_cap;
+    R.wave_yield = (uint32_t)tu.wave_yield;
     // thresholds between thread and wave mode and the wave-mode front capacity
     // (CR_LONG_LEN / CR_YIELD_ITERS / CR_WAVE_SHORT / CR_FRONT_CAP override them,
     // e.g. to exercise wave mode and its tail merges on small inputs)
@@ -427,6 +432,7 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     if (const char* v = getenv("CR_MID_CAP")) R.mid_cap = (uint32_t)strtoul(v, nullptr, 10);
     if (const char* v = getenv("CR_NARROW_MIN")) R.narrow_min = (uint32_t)strtoul(v, nullptr, 10);
     if (const char* v = getenv("CR_GROUP_MAX")) R.group_max = (uint32_t)strtoul(v, nullptr, 10);
+    if (const char* v = getenv("CR_WAVE_YIELD")) R.wave_yield = (uint32_t)strtoul(v, nullptr, 10);
     if (const char* v = getenv("CR_GROUP_CAP")) {
       const unsigned long f = strtoul(v, nullptr, 10);
       R.group_cap = (uint32_t)(f < FRONT_CAP_MIN ? FRONT_CAP_MIN : (f > 4096 ? 4096 : f));
@@ -567,7 +573,7 @@ cr_status check_tuning(int ndim, const cr_tuning& t) {
   int ext[3];
   if (!stencil_tile(ndim, t.tile, ext)) return fail(CR_ERR_INVALID_ARGUMENT, "tile variant out of range");
   if (t.grid < 64 || t.grid > 65536) return fail(CR_ERR_INVALID_ARGUMENT, "grid must be in [64, 65536]");
-  if (t.long_len < 0 || t.yield_iters < 1 || t.wave_short < 0)
+  if (t.long_len < 0 || t.yield_iters < 1 || t.wave_short < 0 || t.wave_yield < 0)
     return fail(CR_ERR_INVALID_ARGUMENT, "reduction thresholds out of range");
   if (t.front_cap < (int)FRONT_CAP_MIN || t.front_cap > (int)FRONT_CAP_MAX)
     return fail(CR_ERR_INVALID_ARGUMENT, "front_cap out of range");
@@ -1012,7 +1018,7 @@ cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed
   rc = time_it(best, &best_ms);
   // coordinate descent: one parameter at a time, in the order they matter
   const bool red = ndim == 3 && maxdim >= 1;
-  for (int coord = 0; rc == CR_OK && coord < (red ? 6 : 2); ++coord) {
+  for (int coord = 0; rc == CR_OK && coord < (red ? 7 : 2); ++coord) {
     std::vector<int> vals;
     if (coord == 0) for (int v = 0; v < N_TILE_VARIANTS; ++v) vals.push_back(v);
     if (coord == 1) vals = {512, 1024, 2048, 4096, 8192};
@@ -1020,10 +1026,12 @@ cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed
     if (coord == 3) vals = {8, 16, 32};
     if (coord == 4) vals = {0, 4096, 65536, 1 << 30};
     if (coord == 5) vals = {16, 128, 1024};
+    if (coord == 6) vals = {0, 64, 128, 512};
     for (int v : vals) {
       cr_tuning t = best;
       int* field = coord == 0 ? &t.tile : coord == 1 ? &t.grid : coord == 2 ? &t.front_cap
-                 : coord == 3 ? &t.long_len : coord == 4 ? &t.wave_short : &t.yield_iters;
+                 : coord == 3 ? &t.long_len : coord == 4 ? &t.wave_short : coord == 5 ? &t.yield_iters
+                 : &t.wave_yield;
       if (*field == v) continue;
       *field = v;
       float ms = 0.0f;

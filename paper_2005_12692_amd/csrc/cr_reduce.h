@@ -34,6 +34,10 @@ struct RedCtx {
   uint32_t narrow_cap;     // keys of the narrow configuration's front list
   uint32_t group_max;      // a wave-mode round of at most this many columns runs a workgroup per column
   uint32_t group_cap;      // keys of the group mode's front list
+  uint32_t wave_yield;     // a wave- or group-mode column stores itself and continues in the next round
+                           // after this many additions in one round (0: never)
+  uint32_t* yield_list;    // the next round's long list and its count (set per round)
+  unsigned long long* yield_count;
 };
 constexpr uint64_t NO_OWNER = ~0ull;
 constexpr uint64_t ARENA_SLACK = 64;       // readable entries past the arena end (wave loads of 64 words)
@@ -52,8 +56,9 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
 // two ping-pong pairs of column lists (short columns for thread mode, long ones
 // for wave mode) with their device counts: round r reads pair r & 1 (round 0
 // reads every column) and builds pair (r + 1) & 1; list 2k is short, 2k+1 long.
+// Columns yield after R.wave_yield additions only in rounds below yield_rounds.
 void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round0,
-                      int nrounds, hipStream_t s);
+                      int nrounds, int yield_rounds, hipStream_t s);
 void launch_h1_emit(int grid, const RedCtx& R, const EmitCtx& E, hipStream_t s);
 
 }  // namespace cr

@@ -977,8 +977,53 @@ struct WaveOps {
   }
 };
 
+// Stores the column P ^ F ^ U ^ T as one arena list and records it for column
+// c with pivot key pv: with a claim word, c is proposed for that pivot;
+// without one (pv = YIELDED) c is appended to the next round's long list.
+template <class O>
+__device__ __forceinline__ void store_column(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c,
+                                             uint64_t pv, int32_t* claim_at, int lane) {
+  uint64_t off;
+  uint32_t len;
+  if (W.nf == 0 && W.U.n == 0 && W.T.n == 0) {  // the column is P
+    off = O::alloc(R, S, (uint64_t)W.np + 1, lane);
+    if (off == ~0ull) return;
+    p_stage(W, R.arena + off + 1, lane);
+    len = W.np;
+  } else {
+    if (!O::flush_p(R, S, W, lane)) return;
+    if (W.U.n && W.T.n && !O::push_front(R, S, W, lane)) return;
+    const Tail& G = W.T.n ? W.T : W.U;  // at most one of them is left with F
+    const Tail& H = W.T.n ? W.U : W.T;
+    off = O::alloc(R, S, (uint64_t)W.nf + G.n + H.n + 1, lane);
+    if (off == ~0ull) return;
+    if (H.n) {
+      len = O::merge_gg(S, G.v, G.n, H.v, H.n, R.arena + off + 1, lane);
+    } else if (G.n) {
+      len = O::merge_tail(S, G.v, G.n, fbuf(S, W.cur), W.nf, R.arena + off + 1, lane);
+    } else {
+      O::copy_out(S, R.arena + off + 1, fbuf(S, W.cur), W.nf, lane);
+      len = W.nf;
+    }
+  }
+  if (O::leader(lane)) {
+    R.arena[off] = len;
+    const auto* K = cold(R);
+    K->col_ptr[c] = off;
+    K->piv[c] = pv;
+    if (claim_at) {
+      atomicMin(claim_at, (int32_t)c);
+    } else {
+      const unsigned long long i = atomicAdd(K->yield_count, 1ull);
+      K->yield_list[i] = c;
+    }
+  }
+}
+
 // Reduces column c for one round: until its pivot has no owner to its left,
-// then stores it and proposes it for its pivot.
+// then stores it and proposes it for its pivot; or, after wave_yield additions,
+// stores it unfinished for the next round, so that one long column does not
+// hold back the columns of every other image at the round's end.
 template <class O>
 __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c, uint64_t off2,
                                               int lane) {
@@ -1028,12 +1073,16 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
       tail_set(W.T, src, len, lane);
     }
   }
+  const uint32_t ylim = uni(cold(R)->wave_yield ? cold(R)->wave_yield : 0xFFFFFFFFu);
+  uint64_t out_piv = YIELDED;   // what is stored when the loop ends: the pivot and its
+  int32_t* claim_at = nullptr;  // claim word, or YIELDED and none after wave_yield additions
   for (uint32_t it = 0;; ++it) {
     if (it >= RED_ITER_CAP) {
       if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->iter_cap);
       return;
     }
     if ((it & 63) == 63 && O::aborted(R, S)) return;
+    if (it >= ylim) break;
     int where = 0;
     const uint64_t e = w_pivot(S, W, lane, &where);
     if (e == 0) {  // a zero column: impossible after clearing
@@ -1109,43 +1158,11 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
       return;
     }
     // store P ^ F ^ U ^ T and propose c for e
-    if (W.nf == 0 && W.U.n == 0 && W.T.n == 0) {  // the column is P
-      const uint64_t off = O::alloc(R, S, (uint64_t)W.np + 1, lane);
-      if (off == ~0ull) return;
-      p_stage(W, R.arena + off + 1, lane);
-      if (O::leader(lane)) {
-        R.arena[off] = W.np;
-        const auto* K = cold(R);
-        K->col_ptr[c] = off;
-        K->piv[c] = e;
-        atomicMin(&K->claim[3 * d.pix_off + slot], (int32_t)c);
-      }
-      return;
-    }
-    if (!O::flush_p(R, S, W, lane)) return;
-    if (W.U.n && W.T.n && !O::push_front(R, S, W, lane)) return;
-    const Tail& G = W.T.n ? W.T : W.U;  // at most one of them is left with F
-    const Tail& H = W.T.n ? W.U : W.T;
-    const uint64_t off = O::alloc(R, S, (uint64_t)W.nf + G.n + H.n + 1, lane);
-    if (off == ~0ull) return;
-    uint32_t len;
-    if (H.n) {
-      len = O::merge_gg(S, G.v, G.n, H.v, H.n, R.arena + off + 1, lane);
-    } else if (G.n) {
-      len = O::merge_tail(S, G.v, G.n, fbuf(S, W.cur), W.nf, R.arena + off + 1, lane);
-    } else {
-      O::copy_out(S, R.arena + off + 1, fbuf(S, W.cur), W.nf, lane);
-      len = W.nf;
-    }
-    if (O::leader(lane)) {
-      R.arena[off] = len;
-      const auto* K = cold(R);
-      K->col_ptr[c] = off;
-      K->piv[c] = e;
-      atomicMin(&K->claim[3 * d.pix_off + slot], (int32_t)c);
-    }
-    return;
+    out_piv = e;
+    claim_at = &cold(R)->claim[3 * d.pix_off + slot];
+    break;
   }
+  store_column<O>(R, S, W, c, out_piv, claim_at, lane);
 }
 
 // Wave-mode round over the long-column list (and the short list when it has at
@@ -1741,6 +1758,9 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.narrow_cap = 256;
   R.group_max = 1024;
   R.group_cap = 2048;
+  R.wave_yield = 0;
+  R.yield_list = nullptr;
+  R.yield_count = nullptr;
   return R;
 }
 
@@ -1760,7 +1780,7 @@ static size_t wave_setup(uint32_t front_cap, int ncu, int* grid) {
 }
 
 void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round0,
-                      int nrounds, hipStream_t s) {
+                      int nrounds, int yield_rounds, hipStream_t s) {
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1789,9 +1809,13 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
     else
       k_red_round<THREAD_CAP><<<grid, 256, 0, s>>>(R, lt, ct, first, lists[2 * nxt], cnx, lists[2 * nxt + 1], cnx + 1);
     if (!first) {
-      k_red_round_wave<NarrowCfg><<<ngrid, 64 * WPB, nlds, s>>>(R, lt, ct, lb, ct + 1, R.narrow_cap);
-      k_red_round_wave<WideCfg><<<wgrid, 64 * WPB, lds, s>>>(R, lt, ct, lb, ct + 1, R.front_cap);
-      k_red_round_group<<<ncu, 64 * GNW, glds, s>>>(R, lt, ct, lb, ct + 1, gcap);
+      RedCtx Rr = R;  // columns that yield go to this round's next long list
+      Rr.yield_list = lists[2 * nxt + 1];
+      Rr.yield_count = cnx + 1;
+      if (r >= yield_rounds) Rr.wave_yield = 0;
+      k_red_round_wave<NarrowCfg><<<ngrid, 64 * WPB, nlds, s>>>(Rr, lt, ct, lb, ct + 1, R.narrow_cap);
+      k_red_round_wave<WideCfg><<<wgrid, 64 * WPB, lds, s>>>(Rr, lt, ct, lb, ct + 1, R.front_cap);
+      k_red_round_group<<<ncu, 64 * GNW, glds, s>>>(Rr, lt, ct, lb, ct + 1, gcap);
     }
     k_red_commit<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first, lists[2 * nxt], lists[2 * nxt + 1], cnx);
     k_red_reset<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first);

@@ -177,3 +177,28 @@ def test_batched_backward_matches_plain():
         (l[a] ** 2).sum().backward()
         np.testing.assert_allclose(gb[offs[i]:offs[i + 1]], x.grad.cpu().numpy().ravel(), rtol=1e-6,
                                    atol=1e-6)
+
+
+def test_batched_yield_within_the_round_budget():
+    """Wave columns stored and resumed after every addition: the batched call
+    (a fixed budget of rounds, no host checks) still finishes and matches the
+    oracle, because columns yield only in the first part of the budget."""
+    import os
+    vols = [synth.grf_seeded((20, 22, 18), 1.5, 30 + i) for i in range(5)] + [synth.blobs3d(24, 9)]
+    packed, shapes, offs = cr.pack([torch.from_numpy(v).cuda() for v in vols])
+    try:
+        for y in ("1", "4"):
+            os.environ["CR_WAVE_YIELD"] = y
+            os.environ["CR_LONG_LEN"] = "0"
+            os.environ["CR_YIELD_ITERS"] = "1"
+            d = cr.persistence_batched(packed, shapes, offs)
+            po = d.pair_offsets.cpu()
+            for i, v in enumerate(vols):
+                got = [t.cpu().numpy() for t in d.image(i, po)]
+                got[3] = got[3] - offs[i]
+                got[4] = np.where(got[4] >= 0, got[4] - offs[i], -1)
+                o = oracle.persistence(v)
+                assert_same(got, [o.dim, o.birth, o.death, o.birth_pixel, o.death_pixel], f"yield {y} volume {i}")
+    finally:
+        for k in ("CR_WAVE_YIELD", "CR_LONG_LEN", "CR_YIELD_ITERS"):
+            os.environ.pop(k, None)

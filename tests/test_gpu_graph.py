@@ -84,7 +84,7 @@ def test_every_tuning_gives_the_same_bytes(ndim):
     settings += [dict(grid=64), dict(grid=100), dict(grid=8192)]  # 100: not a multiple of the 8 XCDs
     if ndim == 3:
         settings += [dict(long_len=0, yield_iters=1, front_cap=128), dict(long_len=1000000, yield_iters=1000000),
-                     dict(wave_short=0, front_cap=300)]
+                     dict(wave_short=0, front_cap=300), dict(wave_yield=0), dict(wave_yield=1, yield_iters=1)]
     try:
         for kw in settings:
             cr.set_tuning(ndim, **{**default, **kw})

@@ -162,22 +162,23 @@ def test_deterministic_repeat():
 
 
 WAVE_ENV = ("CR_LONG_LEN", "CR_YIELD_ITERS", "CR_WAVE_SHORT", "CR_FRONT_CAP", "CR_MID_CAP", "CR_NARROW_MIN",
-            "CR_NARROW_CAP", "CR_GROUP_MAX", "CR_GROUP_CAP")
+            "CR_NARROW_CAP", "CR_GROUP_MAX", "CR_GROUP_CAP", "CR_WAVE_YIELD")
 
 
 @pytest.mark.parametrize("setting", [
-    # every column to wave mode after two additions; narrow configuration with a tiny front list
-    ("0", "2", "0", "4032", "8192", "0", "128", "0", "4096"),
-    ("8", "8", "0", "4032", "8192", "1000000000", "256", "0", "4096"),  # wide configuration only
+    # every column to wave mode after two additions; narrow configuration with a
+    # tiny front list; wave columns stored and resumed every 3 additions
+    ("0", "2", "0", "4032", "8192", "0", "128", "0", "4096", "3"),
+    ("8", "8", "0", "4032", "8192", "1000000000", "256", "0", "4096", "0"),  # wide configuration only
     # whole rounds in wave mode, tiny front and middle lists
-    ("0", "1", "1000000", "128", "300", "1000000000", "320", "0", "4096"),
-    ("0", "1", "1000000", "128", "300", "0", "320", "0", "4096"),
+    ("0", "1", "1000000", "128", "300", "1000000000", "320", "0", "4096", "1"),
+    ("0", "1", "1000000", "128", "300", "0", "320", "0", "4096", "5"),
     # the middle list folded into the tail at every push; all three configurations
-    ("4", "4", "64", "200", "0", "64", "200", "16", "128"),
+    ("4", "4", "64", "200", "0", "64", "200", "16", "128", "2"),
     # a workgroup per column in every wave-mode round: small lists, then the defaults
-    ("0", "1", "1000000", "128", "300", "1000000000", "256", "1000000000", "128"),
-    ("0", "2", "0", "1024", "0", "1000000000", "256", "1000000000", "200"),
-    ("16", "1024", "4096", "1024", "8192", "8192", "256", "1000000000", "4096"),
+    ("0", "1", "1000000", "128", "300", "1000000000", "256", "1000000000", "128", "1"),
+    ("0", "2", "0", "1024", "0", "1000000000", "256", "1000000000", "200", "0"),
+    ("16", "1024", "4096", "1024", "8192", "8192", "256", "1000000000", "4096", "16"),
 ])
 def test_wave_mode_forced(setting):
     """Volumes whose columns are handed to the wavefront-per-column mode after a
@@ -217,12 +218,13 @@ def _mode_volumes():
 
 
 @pytest.mark.parametrize("setting", [
-    # (long_len, yield_iters, wave_short, front_cap, mid_cap, narrow_min, narrow_cap, group_max, group_cap)
-    None,                                                                           # the defaults
-    ("0", "4", "1000000", "128", "256", "1000000000", "256", "1000000000", "128"),  # group mode, small lists
-    ("0", "4", "1000000", "128", "0", "0", "128", "0", "4096"),                     # narrow mode, small lists
-    ("8", "64", "1000000", "128", "512", "1000000000", "256", "0", "4096"),         # wide mode, small lists
-    ("32", "16", "0", "4032", "100000", "1000000000", "256", "1000000000", "4096"),  # large lists, group mode
+    # (long_len, yield_iters, wave_short, front_cap, mid_cap, narrow_min, narrow_cap, group_max, group_cap,
+    #  wave_yield)
+    None,                                                                                 # the defaults
+    ("0", "4", "1000000", "128", "256", "1000000000", "256", "1000000000", "128", "1"),   # group mode, small lists
+    ("0", "4", "1000000", "128", "0", "0", "128", "0", "4096", "7"),                      # narrow mode, small lists
+    ("8", "64", "1000000", "128", "512", "1000000000", "256", "0", "4096", "3"),          # wide mode, small lists
+    ("32", "16", "0", "4032", "100000", "1000000000", "256", "1000000000", "4096", "0"),  # large lists, group mode
 ])
 def test_reduction_modes_larger(setting):
     """Volumes of 10^5 to 10^6 pixels with many long columns, each reduction mode forced
