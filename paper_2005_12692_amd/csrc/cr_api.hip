@@ -115,6 +115,7 @@ struct cr_context {
   size_t host_stage_bytes = 0;
   hipEvent_t stage_done = nullptr;
   bool stage_pending = false;
+  hipEvent_t round_ev[2] = {};   // the reduction's list counts of a batch of rounds have landed
   uint64_t arena_entries = 1ull << 28;
   Plan plan{};
   Problem prob{};
@@ -305,19 +306,29 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
     launch_check_empty(counts + 2 * (ROUND_BUDGET & 1), R.st, s);
     return CR_OK;
   }
-  for (int r = 0; r < ROUND_LIMIT; r += ROUND_BATCH) {
+  // Batches of rounds are enqueued one ahead of the check: the counts left by
+  // batch k-1 are read while batch k runs, so the GPU does not idle during the
+  // host's round trip; a finished reduction leaves batch k's rounds empty.
+  cr_status rc = ensure_stage(ctx, 64);
+  if (rc != CR_OK) return rc;
+  for (hipEvent_t& e : ctx->round_ev)
+    if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (int k = 0; k * ROUND_BATCH < ROUND_LIMIT; ++k) {
+    const int r = k * ROUND_BATCH;
     launch_h1_rounds(RGRID, R, lists, counts, r, ROUND_BATCH, ROUND_LIMIT, s);
     const int cur = (r + ROUND_BATCH) & 1;
-    cr_status rc = ensure_stage(ctx, 64);
-    if (rc != CR_OK) return rc;
-    HIP_TRY(hipMemcpyAsync(ctx->host_stage, counts + 2 * cur, 16, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(ctx->host_stage + 16, &R.st->abort, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    char* slot = ctx->host_stage + 32 * (k & 1);
+    HIP_TRY(hipMemcpyAsync(slot, counts + 2 * cur, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(slot + 16, &R.st->abort, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(ctx->round_ev[k & 1], s));
+    if (k == 0) continue;
+    HIP_TRY(hipEventSynchronize(ctx->round_ev[(k - 1) & 1]));
+    const char* prev = ctx->host_stage + 32 * ((k - 1) & 1);
     unsigned long long left[2] = {0, 0};
     uint32_t ab = 0;
-    std::memcpy(left, ctx->host_stage, 16);
-    std::memcpy(&ab, ctx->host_stage + 16, 4);
-    ctx->rounds = r + ROUND_BATCH;
+    std::memcpy(left, prev, 16);
+    std::memcpy(&ab, prev + 16, 4);
+    ctx->rounds = r;
     if ((left[0] == 0 && left[1] == 0) || ab) return CR_OK;
   }
   launch_check_empty(counts + 2 * (ROUND_LIMIT & 1), R.st, s);
@@ -640,6 +651,8 @@ void cr_destroy(cr_context* ctx) {
   if (ctx->bwd_flag) (void)hipFree(ctx->bwd_flag);
   if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
   if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
+  for (hipEvent_t e : ctx->round_ev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->ev_ready)
     for (int i = 0; i < EV_N; ++i) (void)hipEventDestroy(ctx->ev[i]);
   delete ctx;
