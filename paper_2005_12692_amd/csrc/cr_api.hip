@@ -6,6 +6,7 @@
 #include <cstring>
 #include <algorithm>
 #include <cstdlib>
+#include <functional>
 
 #include "cr.h"
 #include "cr_reduce.h"
@@ -100,6 +101,7 @@ struct Plan {
   size_t status, counters, img_status, img_pairs, imgs, tiles, surv_a, surv_b, hist, vlink, tlink, T, neg,
       owner, claim, piv, colptr, arena, cleared, list[4], eapp, total;
   uint64_t surv_cap, e_cap, arena_cap;
+  size_t T0 = 0;  // degree 0's own merge structure when it runs beside degree 2 and the reduction (0: none)
 };
 
 }  // namespace
@@ -116,6 +118,8 @@ struct cr_context {
   hipEvent_t stage_done = nullptr;
   bool stage_pending = false;
   hipEvent_t round_ev[2] = {};   // the reduction's list counts of a batch of rounds have landed
+  hipStream_t side = nullptr;    // degree 0 of a volume runs here beside degree 2 and the reduction
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   uint64_t arena_entries = 1ull << 28;
   Plan plan{};
   Problem prob{};
@@ -200,7 +204,7 @@ cr_status build_problem(Problem& pb, int nimg, const int64_t* pixel_offsets, con
   return CR_OK;
 }
 
-Plan make_plan(const Problem& pb, uint64_t arena_entries) {
+Plan make_plan(const Problem& pb, uint64_t arena_entries, bool side_h0 = false) {
   Plan p{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -233,6 +237,7 @@ Plan make_plan(const Problem& pb, uint64_t arena_entries) {
   p.claim = take(vol ? 4 * 3 * pb.P : 0);
   for (int i = 0; i < 4; ++i) p.list[i] = take(vol ? 4 * p.e_cap : 0);
   p.eapp = take(vol ? 3 * pb.P : 0);
+  if (vol && side_h0) p.T0 = take(8 * (pb.P + pb.nimg + 64));
   p.total = o;
   return p;
 }
@@ -280,7 +285,8 @@ T* at(cr_context* ctx, size_t off) {
 
 // stage boundaries; A and B close the two higher-degree stages (2D: degree 1
 // then nothing; 3D: degree 2 then degree 1)
-enum { EV_START = 0, EV_STENCIL, EV_SORT, EV_H0, EV_A, EV_B, EV_ROWS, EV_N };
+// EV_H0S: the start of degree 0 when it runs on the side stream
+enum { EV_START = 0, EV_STENCIL, EV_SORT, EV_H0, EV_A, EV_B, EV_ROWS, EV_H0S, EV_N };
 
 // Records stage boundary `i` when stage timing is on.
 void mark(cr_context* ctx, int i, hipStream_t s) {
@@ -298,8 +304,13 @@ constexpr int ROUND_BUDGET = 128;
 constexpr int YIELD_ROUNDS = 64;
 constexpr int ROUND_LIMIT = 4096;
 
+// side_start, if given, is called once after the first SIDE_AFTER rounds have
+// been enqueued (or when the reduction ends sooner), to start work beside the
+// latency-bound later rounds.
+constexpr int SIDE_AFTER = 20;
+
 cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts,
-                     hipStream_t s) {
+                     hipStream_t s, const std::function<cr_status()>& side_start = nullptr) {
   ctx->rounds = 0;
   if (!ctx->sync_allowed) {
     launch_h1_rounds(RGRID, R, lists, counts, 0, ROUND_BUDGET, YIELD_ROUNDS, s);
@@ -313,9 +324,19 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
   if (rc != CR_OK) return rc;
   for (hipEvent_t& e : ctx->round_ev)
     if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  bool side_started = !side_start;
+  auto start_side = [&]() -> cr_status {
+    if (side_started) return CR_OK;
+    side_started = true;
+    return side_start();
+  };
   for (int k = 0; k * ROUND_BATCH < ROUND_LIMIT; ++k) {
     const int r = k * ROUND_BATCH;
     launch_h1_rounds(RGRID, R, lists, counts, r, ROUND_BATCH, ROUND_LIMIT, s);
+    if (r + ROUND_BATCH >= SIDE_AFTER) {
+      rc = start_side();
+      if (rc != CR_OK) return rc;
+    }
     const int cur = (r + ROUND_BATCH) & 1;
     char* slot = ctx->host_stage + 32 * (k & 1);
     HIP_TRY(hipMemcpyAsync(slot, counts + 2 * cur, 16, hipMemcpyDeviceToHost, s));
@@ -329,8 +350,10 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
     std::memcpy(left, prev, 16);
     std::memcpy(&ab, prev + 16, 4);
     ctx->rounds = r;
-    if ((left[0] == 0 && left[1] == 0) || ab) return CR_OK;
+    if ((left[0] == 0 && left[1] == 0) || ab) return start_side();
   }
+  rc = start_side();
+  if (rc != CR_OK) return rc;
   launch_check_empty(counts + 2 * (ROUND_LIMIT & 1), R.st, s);
   return CR_OK;
 }
@@ -409,8 +432,40 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
   uint8_t* neg = at<uint8_t>(ctx, p.neg);
   launch_fill_u32(reinterpret_cast<uint32_t*>(neg), 0, p.e_cap / 4, s);
   uint64_t* T = at<uint64_t>(ctx, p.T);
-  launch_h0(tu.grid, skeys, &cnt[C_DIM], d_imgs, L, vlink, T, neg, E, st, s);
-  mark(ctx, EV_H0, s);
+  // Degree 0 of a volume depends on nothing that degrees 1 and 2 compute, so a
+  // plain call runs it on a second stream, on its own merge structure, beside
+  // the dual merge and the latency-bound reduction rounds.
+  // Degree 0 of a volume depends on nothing that degrees 1 and 2 compute, so a
+  // plain call runs it on a second stream, on its own merge structure, started
+  // once the reduction has reached its latency-bound rounds.
+  const bool side_h0 = p.T0 != 0;
+  struct Join {  // every return after the fork makes s wait for the side stream
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    ~Join() {
+      if (e) (void)hipStreamWaitEvent(s, e, 0);
+    }
+  } join;
+  std::function<cr_status()> fork_h0;
+  if (side_h0) {
+    if (!ctx->side) HIP_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    if (!ctx->fork_ev) HIP_TRY(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+    if (!ctx->join_ev) HIP_TRY(hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
+    fork_h0 = [&]() -> cr_status {
+      HIP_TRY(hipEventRecord(ctx->fork_ev, s));
+      HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
+      mark(ctx, EV_H0S, ctx->side);
+      launch_h0(tu.grid, skeys, &cnt[C_DIM], d_imgs, L, vlink, at<uint64_t>(ctx, p.T0), neg, E, st, ctx->side);
+      mark(ctx, EV_H0, ctx->side);
+      HIP_TRY(hipEventRecord(ctx->join_ev, ctx->side));
+      join.s = s;
+      join.e = ctx->join_ev;
+      return CR_OK;
+    };
+  } else {
+    launch_h0(tu.grid, skeys, &cnt[C_DIM], d_imgs, L, vlink, T, neg, E, st, s);
+    mark(ctx, EV_H0, s);
+  }
 
   uint64_t* owner = at<uint64_t>(ctx, p.owner);
   if (pb.ndim == 2) {
@@ -458,13 +513,17 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     }
     uint32_t* lists[4] = {at<uint32_t>(ctx, p.list[0]), at<uint32_t>(ctx, p.list[1]), at<uint32_t>(ctx, p.list[2]),
                           at<uint32_t>(ctx, p.list[3])};
-    cr_status rrc = run_rounds(ctx, R, lists, &cnt[C_LIST], s);
+    cr_status rrc = run_rounds(ctx, R, lists, &cnt[C_LIST], s, fork_h0);
     if (rrc != CR_OK) return rrc;
     launch_h1_emit(tu.grid, R, E, s);
     mark(ctx, EV_B, s);
   } else {
     mark(ctx, EV_A, s);
     mark(ctx, EV_B, s);
+  }
+  if (side_h0) {  // degree 0's rows are in
+    join.e = nullptr;
+    HIP_TRY(hipStreamWaitEvent(s, ctx->join_ev, 0));
   }
   // canonical order: sort the row keys.  The survivor keys are dead now, so
   // their buffer is the scratch of this sort.
@@ -492,6 +551,10 @@ cr_status read_counters(cr_context* ctx, hipStream_t s, HostCounters* h) {
     float ms[6] = {};
     for (int i = 0; i < 6; ++i) (void)hipEventElapsedTime(&ms[i], ctx->ev[i], ctx->ev[i + 1]);
     const bool vol = ctx->prob.ndim == 3;
+    if (ctx->plan.T0) {  // degree 0 ran on the side stream; degree 2 follows the sort
+      (void)hipEventElapsedTime(&ms[2], ctx->ev[EV_H0S], ctx->ev[EV_H0]);
+      (void)hipEventElapsedTime(&ms[3], ctx->ev[EV_SORT], ctx->ev[EV_A]);
+    }
     ctx->stage_ms[0] = ms[0];
     ctx->stage_ms[1] = ms[1];
     ctx->stage_ms[2] = ms[2];
@@ -653,6 +716,9 @@ void cr_destroy(cr_context* ctx) {
   if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
   for (hipEvent_t e : ctx->round_ev)
     if (e) (void)hipEventDestroy(e);
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   if (ctx->ev_ready)
     for (int i = 0; i < EV_N; ++i) (void)hipEventDestroy(ctx->ev[i]);
   delete ctx;
@@ -678,7 +744,7 @@ cr_status cr_persistence(cr_context* ctx, const float* image, int ndim, const in
   cr_status rc = build_problem(ctx->prob, 1, nullptr, shape, ndim, maxdim, ctx->tune[grid_ndim(ndim)].tile);
   if (rc != CR_OK) return rc;
   for (int attempt = 0; attempt < 4; ++attempt) {
-    ctx->plan = make_plan(ctx->prob, ctx->arena_entries);
+    ctx->plan = make_plan(ctx->prob, ctx->arena_entries, /*side_h0=*/true);
     rc = ensure_scratch(ctx, ctx->plan.total);
     if (rc != CR_OK) return rc;
     uint64_t* cand = nullptr;
