@@ -433,9 +433,6 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
   launch_fill_u32(reinterpret_cast<uint32_t*>(neg), 0, p.e_cap / 4, s);
   uint64_t* T = at<uint64_t>(ctx, p.T);
   // Degree 0 of a volume depends on nothing that degrees 1 and 2 compute, so a
-  // plain call runs it on a second stream, on its own merge structure, beside
-  // the dual merge and the latency-bound reduction rounds.
-  // Degree 0 of a volume depends on nothing that degrees 1 and 2 compute, so a
   // plain call runs it on a second stream, on its own merge structure, started
   // once the reduction has reached its latency-bound rounds.
   const bool side_h0 = p.T0 != 0;
