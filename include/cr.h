@@ -128,6 +128,19 @@ cr_status cr_persistence_batched(cr_context* ctx, int n_images, const float* pac
                                  int32_t* dim, float* birth, float* death, int64_t* birth_pixel,
                                  int64_t* death_pixel, int64_t capacity, int64_t* pair_offsets, int32_t* status);
 
+/* Device scratch bytes a batched call of these images needs (the same
+ * arguments as cr_persistence_batched, host only; no device work), and a
+ * reservation of that much scratch in the context ahead of time: a batched
+ * call whose need fits the reservation allocates no device memory, so it can
+ * be enqueued where allocation is not allowed (the pinned host buffer that
+ * uploads the image descriptors is allocated by the context's first batched
+ * call).  cr_reserve never shrinks the scratch; it synchronises the device
+ * when it has to grow it.  Errors: INVALID_ARGUMENT, TOO_LARGE,
+ * OUT_OF_MEMORY. */
+cr_status cr_batched_workspace_size(cr_context* ctx, int n_images, const int64_t* shapes, int ndim, int maxdim,
+                                    size_t* bytes);
+cr_status cr_reserve(cr_context* ctx, size_t bytes);
+
 /* Synchronises `stream` and returns the device-side status of the last
  * batched call on this context (CR_OK, CR_ERR_NAN_INPUT, CR_ERR_CAPACITY,
  * CR_ERR_OUT_OF_MEMORY for scratch exhaustion, or CR_ERR_INTERNAL). */

@@ -105,6 +105,8 @@ def lib():
         L.cr_persistence_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, i64, vp]
         L.cr_lifetime_image.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp, i64, vp]
         L.cr_pixel_coords.argtypes = [vp, vp, i64, i64, i32, ctypes.POINTER(i64), vp, vp]
+        L.cr_batched_workspace_size.argtypes = [vp, i32, ctypes.POINTER(i64), i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.cr_reserve.argtypes = [vp, ctypes.c_size_t]
         L.cr_get_stats.argtypes = [vp, ctypes.POINTER(_Stats)]
         L.cr_get_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32, ctypes.POINTER(i32)]
         batch = [vp, i32, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), i32, i32]
@@ -120,7 +122,8 @@ def lib():
         L.cr_graph_destroy.argtypes = [vp]
         L.cr_graph_destroy.restype = None
         for f in ("cr_create", "cr_persistence", "cr_persistence_batched", "cr_sync_status",
-                  "cr_persistence_backward", "cr_lifetime_image", "cr_pixel_coords", "cr_get_stats", "cr_get_stage_times", "cr_get_tuning",
+                  "cr_persistence_backward", "cr_lifetime_image", "cr_pixel_coords", "cr_batched_workspace_size",
+                  "cr_reserve", "cr_get_stats", "cr_get_stage_times", "cr_get_tuning",
                   "cr_set_tuning", "cr_tile_variants", "cr_tile_shape", "cr_autotune_batched",
                   "cr_batched_graph_create", "cr_graph_launch", "cr_graph_sync_status"):
             getattr(L, f).restype = ctypes.c_int
@@ -434,6 +437,28 @@ def backward(birth_pixel: torch.Tensor, death_pixel: torch.Tensor, grad_birth: t
     _check(lib().cr_persistence_backward(h, p(birth_pixel.contiguous()), p(death_pixel.contiguous()), p(gb),
                                          p(gd), n, p(grad_image), grad_image.numel(), _stream(grad_image.device)))
     return grad_image
+
+
+def workspace_size(shapes, maxdim: int | None = None, device=None) -> int:
+    """Device scratch bytes a batched call of images of these shapes needs."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    h, _ = _context(dev)
+    shapes = [tuple(int(x) for x in s) for s in shapes]
+    ndim = len(shapes[0])
+    if any(len(s) != ndim for s in shapes):
+        raise ValueError("all images must have the same ndim")
+    flat = (ctypes.c_int64 * (ndim * len(shapes)))(*[x for s in shapes for x in s])
+    out = ctypes.c_size_t()
+    _check(lib().cr_batched_workspace_size(h, len(shapes), flat, ndim, ndim - 1 if maxdim is None else int(maxdim),
+                                           ctypes.byref(out)))
+    return int(out.value)
+
+
+def reserve(nbytes: int, device=None) -> None:
+    """Reserves device scratch so that batched calls needing at most nbytes allocate nothing."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    h, _ = _context(dev)
+    _check(lib().cr_reserve(h, int(nbytes)))
 
 
 def lifetime_image(d, n_pixels: int, location: str = "birth") -> torch.Tensor:

@@ -808,6 +808,23 @@ void cr_diagram_free(cr_context* ctx, cr_diagram* d) {
   d->birth_pixel = nullptr; d->death_pixel = nullptr;
 }
 
+cr_status cr_batched_workspace_size(cr_context* ctx, int n_images, const int64_t* shapes, int ndim, int maxdim,
+                                    size_t* bytes) {
+  if (!ctx || !bytes) return fail(CR_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (ndim < 1 || ndim > 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 1, 2 or 3");
+  Problem pb;
+  cr_status rc = build_problem(pb, n_images, nullptr, shapes, ndim, maxdim, ctx->tune[grid_ndim(ndim)].tile);
+  if (rc != CR_OK) return rc;
+  *bytes = make_plan(pb, ctx->arena_entries).total;
+  return CR_OK;
+}
+
+cr_status cr_reserve(cr_context* ctx, size_t bytes) {
+  if (!ctx) return fail(CR_ERR_INVALID_ARGUMENT, "ctx is NULL");
+  HIP_TRY(hipSetDevice(ctx->device));
+  return ensure_scratch(ctx, bytes);
+}
+
 cr_status cr_persistence_batched(cr_context* ctx, int n_images, const float* packed, const int64_t* pixel_offsets,
                                  const int64_t* shapes, int ndim, int maxdim, uint32_t flags, void* stream,
                                  int32_t* dim, float* birth, float* death, int64_t* birth_pixel,

@@ -69,6 +69,10 @@ def test_null_context_calls_fail_cleanly(libcr):
     assert libcr.cr_lifetime_image(None, None, None, None, None, None, 0, 0, None, 0, None) == 1
     libcr.cr_pixel_coords.restype = ctypes.c_int
     assert libcr.cr_pixel_coords(None, None, 0, 0, 2, None, None, None) == 1
+    libcr.cr_batched_workspace_size.restype = ctypes.c_int
+    assert libcr.cr_batched_workspace_size(None, 1, None, 2, 1, None) == 1
+    libcr.cr_reserve.restype = ctypes.c_int
+    assert libcr.cr_reserve(None, ctypes.c_size_t(0)) == 1
 
 
 def test_package_does_not_import_the_oracle():

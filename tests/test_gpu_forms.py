@@ -202,3 +202,28 @@ def test_batched_yield_within_the_round_budget():
     finally:
         for k in ("CR_WAVE_YIELD", "CR_LONG_LEN", "CR_YIELD_ITERS"):
             os.environ.pop(k, None)
+
+
+def test_reserve_then_batched_call_allocates_nothing():
+    """cr_batched_workspace_size / cr_reserve: after reserving the reported
+    scratch, a batched call into preallocated outputs takes no device memory."""
+    imgs = [synth.uniform2d((40 + 3 * i, 50 - 2 * i), i) for i in range(8)]
+    packed, shapes, offs = cr.pack([torch.from_numpy(a).cuda() for a in imgs])
+    need = cr.workspace_size(shapes)
+    assert need > 0
+    assert cr.workspace_size(shapes + shapes) > need  # more images, more scratch
+    cr.reserve(need)
+    out = cr._empty_out(int(offs[-1]), len(imgs), packed.device)
+    cr.persistence_batched(packed, shapes, offs, out=out, check=False)  # first call: host staging
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    d = cr.persistence_batched(packed, shapes, offs, out=out, check=False)
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] == free0
+    po = d.pair_offsets.cpu()
+    for i in (0, 5):
+        got = [t.cpu().numpy() for t in d.image(i, po)]
+        got[3] = got[3] - offs[i]
+        got[4] = np.where(got[4] >= 0, got[4] - offs[i], -1)
+        o = oracle.persistence(imgs[i])
+        assert_same(got, [o.dim, o.birth, o.death, o.birth_pixel, o.death_pixel], f"reserved image {i}")
