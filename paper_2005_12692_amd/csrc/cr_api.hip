@@ -139,7 +139,7 @@ struct cr_context {
 namespace {
 
 // counters block: surv_count, dim_count[4], cand_count, arena_top, lists[4], wave work counter
-enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* four words */, C_WORK = 11, C_WORDS = 12 };
+enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* six words */, C_WORK = 13, C_WORDS = 14 };
 
 // A 1D signal lies on one line of the grid (Sec. 2): it runs as a 1 x n image,
 // with the 2D launch parameters.
@@ -314,7 +314,7 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
   ctx->rounds = 0;
   if (!ctx->sync_allowed) {
     launch_h1_rounds(RGRID, R, lists, counts, 0, ROUND_BUDGET, YIELD_ROUNDS, s);
-    launch_check_empty(counts + 2 * (ROUND_BUDGET & 1), R.st, s);
+    launch_check_empty(counts + 2 * (ROUND_BUDGET % 3), R.st, s);
     return CR_OK;
   }
   // Batches of rounds are enqueued one ahead of the check: the counts left by
@@ -337,7 +337,7 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
       rc = start_side();
       if (rc != CR_OK) return rc;
     }
-    const int cur = (r + ROUND_BATCH) & 1;
+    const int cur = (r + ROUND_BATCH) % 3;  // the count pair the next round reads
     char* slot = ctx->host_stage + 32 * (k & 1);
     HIP_TRY(hipMemcpyAsync(slot, counts + 2 * cur, 16, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(slot + 16, &R.st->abort, 4, hipMemcpyDeviceToHost, s));
@@ -354,7 +354,7 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
   }
   rc = start_side();
   if (rc != CR_OK) return rc;
-  launch_check_empty(counts + 2 * (ROUND_LIMIT & 1), R.st, s);
+  launch_check_empty(counts + 2 * (ROUND_LIMIT % 3), R.st, s);
   return CR_OK;
 }
 

@@ -52,10 +52,12 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
                    uint64_t* piv, uint64_t* col_ptr, uint64_t* arena, uint64_t arena_cap,
                    unsigned long long* arena_top, unsigned long long* work, Status* st);
 
-// Enqueues rounds [round0, round0 + nrounds) of the reduction.  lists/counts:
-// two ping-pong pairs of column lists (short columns for thread mode, long ones
-// for wave mode) with their device counts: round r reads pair r & 1 (round 0
-// reads every column) and builds pair (r + 1) & 1; list 2k is short, 2k+1 long.
+// Enqueues rounds [round0, round0 + nrounds) of the reduction.  lists: two
+// ping-pong pairs of column lists (short columns for thread mode, long ones for
+// wave mode): round r reads pair r & 1 (round 0 reads every column) and builds
+// pair (r + 1) & 1; list 2k is short, 2k+1 long.  counts: three pairs of their
+// device counts, rotating: round r reads pair r % 3, builds pair (r + 1) % 3 and
+// clears pair (r + 2) % 3 for the round after (all zero before round 0).
 // Columns yield after R.wave_yield additions only in rounds below yield_rounds.
 void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round0,
                       int nrounds, int yield_rounds, hipStream_t s);

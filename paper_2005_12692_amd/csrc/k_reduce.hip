@@ -332,12 +332,6 @@ __device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64
   }
 }
 
-__global__ void k_fill_count(unsigned long long* c, unsigned long long* work) {
-  c[0] = 0;
-  c[1] = 0;
-  work[0] = 0;
-}
-
 // Thread-mode round.  Round 0 runs every column that is not cleared; later
 // rounds run the short-column list unless it is short enough for wave mode.
 template <int TC>
@@ -1641,10 +1635,19 @@ __device__ inline int64_t pivot_slot(const RedCtx& R, uint64_t e) {
 // Commit: the leftmost proposer of each pivot becomes its owner; losers and
 // displaced owners go to the next round's lists (long stored columns to the
 // wave-mode list).  Yielded columns were already listed.
+// It also clears the counts the round after next will fill (nobody reads them
+// during this round) and the wave-mode column counter, so that no separate
+// launch is needed for them.
 __global__ void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t, const unsigned long long* __restrict__ n_t,
                              const uint32_t* __restrict__ list_b, const unsigned long long* __restrict__ n_b,
-                             int first, uint32_t* next_t, uint32_t* next_b, unsigned long long* __restrict__ n_next) {
+                             int first, uint32_t* next_t, uint32_t* next_b, unsigned long long* __restrict__ n_next,
+                             unsigned long long* __restrict__ n_clear) {
   if (aborted(R.st)) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    n_clear[0] = 0;
+    n_clear[1] = 0;
+    R.work[0] = 0;
+  }
   const uint64_t nt = first ? R.dim_count[2] : *n_t;
   const uint64_t nb = first ? 0 : *n_b;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -1795,14 +1798,14 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
     glds_set = glds;
   }
   for (int r = round0; r < round0 + nrounds; ++r) {
-    const int cur = r & 1, nxt = (r + 1) & 1;
+    const int cur = r & 1, nxt = (r + 1) & 1;  // list pairs alternate; count pairs rotate by three
     const int first = r == 0;
     // lists[2*k + 0] short (thread mode), lists[2*k + 1] long (wave mode); counts likewise
     uint32_t* lt = lists[2 * cur];
     uint32_t* lb = lists[2 * cur + 1];
-    unsigned long long* ct = counts + 2 * cur;
-    unsigned long long* cnx = counts + 2 * nxt;
-    k_fill_count<<<1, 1, 0, s>>>(cnx, R.work);
+    unsigned long long* ct = counts + 2 * (r % 3);
+    unsigned long long* cnx = counts + 2 * ((r + 1) % 3);
+    unsigned long long* cclr = counts + 2 * ((r + 2) % 3);
     if (first)
       k_red_round<THREAD_CAP_FIRST><<<grid, 256, 0, s>>>(R, lt, ct, first, lists[2 * nxt], cnx, lists[2 * nxt + 1],
                                                          cnx + 1);
@@ -1817,7 +1820,7 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
       k_red_round_wave<WideCfg><<<wgrid, 64 * WPB, lds, s>>>(Rr, lt, ct, lb, ct + 1, R.front_cap);
       k_red_round_group<<<ncu, 64 * GNW, glds, s>>>(Rr, lt, ct, lb, ct + 1, gcap);
     }
-    k_red_commit<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first, lists[2 * nxt], lists[2 * nxt + 1], cnx);
+    k_red_commit<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first, lists[2 * nxt], lists[2 * nxt + 1], cnx, cclr);
     k_red_reset<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first);
   }
 }
