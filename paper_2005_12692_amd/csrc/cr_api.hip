@@ -234,7 +234,7 @@ Plan make_plan(const Problem& pb, uint64_t arena_entries, bool side_h0 = false) 
   p.colptr = take(vol ? 8 * p.e_cap : 0);
   p.arena = take(vol ? 8 * (p.arena_cap + ARENA_SLACK) : 0);
   p.cleared = take(vol ? p.e_cap : 0);
-  p.claim = take(vol ? 4 * 3 * pb.P : 0);
+  p.claim = take(vol ? 8 * 3 * pb.P : 0);
   for (int i = 0; i < 4; ++i) p.list[i] = take(vol ? 4 * p.e_cap : 0);
   p.eapp = take(vol ? 3 * pb.P : 0);
   if (vol && side_h0) p.T0 = take(8 * (pb.P + pb.nimg + 64));
@@ -477,8 +477,8 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     launch_dual(tu.grid, 3, skeys, &cnt[C_DIM], d_imgs, L, tlink, nullptr, cleared, pb.maxdim >= 2, T, E, st, s);
     mark(ctx, EV_A, s);
     launch_fill_u32(reinterpret_cast<uint32_t*>(owner), 0xFFFFFFFFu, 2 * 3 * pb.P, s);
-    launch_fill_u32(at<uint32_t>(ctx, p.claim), 0x7FFFFFFFu, 3 * pb.P, s);
-    RedCtx R = make_redctx(image, d_imgs, L, skeys, &cnt[C_DIM], cleared, eapp, owner, at<int32_t>(ctx, p.claim),
+    launch_fill_u32(at<uint32_t>(ctx, p.claim), 0, 2 * 3 * pb.P, s);
+    RedCtx R = make_redctx(image, d_imgs, L, skeys, &cnt[C_DIM], cleared, eapp, owner, at<uint64_t>(ctx, p.claim),
                            at<uint64_t>(ctx, p.piv), at<uint64_t>(ctx, p.colptr), at<uint64_t>(ctx, p.arena),
                            p.arena_cap, &cnt[C_ARENA], &cnt[C_WORK], st);
     R.long_len = (uint32_t)std::min(tu.long_len, 32);

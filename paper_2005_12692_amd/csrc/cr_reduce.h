@@ -16,7 +16,8 @@ struct RedCtx {
   const uint8_t* eapp;     // per edge slot: apparent partner square (2 * axis + dir), 0xFF if none
   uint64_t* owner;         // per edge (3 * anchor pixel + axis of the edge): (owning column << 32) |
                            // arena offset of that column's stored list; NO_OWNER if none
-  int32_t* claim;          // per edge: leftmost proposer of the current round, INT32_MAX if none
+  uint64_t* claim;         // per edge: claim_word(round, column) of the leftmost proposer in the latest
+                           // round that proposed it (larger rounds win), 0 if none
   uint64_t* piv;           // per column: key of its pivot edge (the proposed one while active)
   uint64_t* col_ptr;       // per column: arena offset of its stored list (length word, then keys)
   uint64_t* arena;         // stored lists: a length word followed by that many ascending keys
@@ -38,7 +39,15 @@ struct RedCtx {
                            // after this many additions in one round (0: never)
   uint32_t* yield_list;    // the next round's long list and its count (set per round)
   unsigned long long* yield_count;
+  uint32_t round;          // the round of this launch
 };
+
+// Proposal word of column c in round r: the round in the high half (a later
+// round always wins, so proposals never need clearing), the column inverted in
+// the low half (the leftmost proposer of a round has the largest word).
+__device__ inline unsigned long long claim_word(uint32_t round, uint32_t c) {
+  return ((unsigned long long)(round + 1) << 32) | (0xFFFFFFFFu - c);
+}
 constexpr uint64_t NO_OWNER = ~0ull;
 constexpr uint64_t ARENA_SLACK = 64;       // readable entries past the arena end (wave loads of 64 words)
 constexpr uint64_t ARENA_MAX = (1ull << 32) - ARENA_SLACK;  // offsets fit the low half of an owner word
@@ -48,7 +57,7 @@ constexpr uint32_t FRONT_CAP_NARROW_MAX = 320;  // narrow configuration: eight t
 
 RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64_t* skeys,
                    const unsigned long long* dim_count, const uint8_t* cleared, const uint8_t* eapp,
-                   uint64_t* owner, int32_t* claim,
+                   uint64_t* owner, uint64_t* claim,
                    uint64_t* piv, uint64_t* col_ptr, uint64_t* arena, uint64_t arena_cap,
                    unsigned long long* arena_top, unsigned long long* work, Status* st);
 

@@ -327,7 +327,7 @@ __device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64
     if (off == ~0ull) return;
     R.col_ptr[c] = off;
     R.piv[c] = e;
-    atomicMin(&R.claim[slot], (int32_t)c);
+    atomicMax(reinterpret_cast<unsigned long long*>(&R.claim[slot]), claim_word(R.round, c));
     return;
   }
 }
@@ -976,7 +976,7 @@ struct WaveOps {
 // without one (pv = YIELDED) c is appended to the next round's long list.
 template <class O>
 __device__ __forceinline__ void store_column(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c,
-                                             uint64_t pv, int32_t* claim_at, int lane) {
+                                             uint64_t pv, uint64_t* claim_at, int lane) {
   uint64_t off;
   uint32_t len;
   if (W.nf == 0 && W.U.n == 0 && W.T.n == 0) {  // the column is P
@@ -1006,7 +1006,7 @@ __device__ __forceinline__ void store_column(const RedCtx& R, const WaveBufs& S,
     K->col_ptr[c] = off;
     K->piv[c] = pv;
     if (claim_at) {
-      atomicMin(claim_at, (int32_t)c);
+      atomicMax(reinterpret_cast<unsigned long long*>(claim_at), claim_word(K->round, c));
     } else {
       const unsigned long long i = atomicAdd(K->yield_count, 1ull);
       K->yield_list[i] = c;
@@ -1069,7 +1069,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
   }
   const uint32_t ylim = uni(cold(R)->wave_yield ? cold(R)->wave_yield : 0xFFFFFFFFu);
   uint64_t out_piv = YIELDED;   // what is stored when the loop ends: the pivot and its
-  int32_t* claim_at = nullptr;  // claim word, or YIELDED and none after wave_yield additions
+  uint64_t* claim_at = nullptr;  // claim word, or YIELDED and none after wave_yield additions
   for (uint32_t it = 0;; ++it) {
     if (it >= RED_ITER_CAP) {
       if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->iter_cap);
@@ -1668,7 +1668,7 @@ __global__ void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t, cons
       if (e != YIELDED) {
         const int64_t slot = pivot_slot(R, e);
         bool push = true;
-        if (R.claim[slot] == (int32_t)c) {
+        if (R.claim[slot] == claim_word(R.round, c)) {
           const uint64_t old = R.owner[slot];
           R.owner[slot] = ((uint64_t)c << 32) | R.col_ptr[c];
           push = old != NO_OWNER;
@@ -1685,27 +1685,6 @@ __global__ void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t, cons
     }
     wave_push(next_t, n_next, again_short, again);
     wave_push(next_b, n_next + 1, again_long, again);
-  }
-}
-
-// Clears the proposals of the round that was just committed.
-__global__ void k_red_reset(RedCtx R, const uint32_t* __restrict__ list_t, const unsigned long long* __restrict__ n_t,
-                            const uint32_t* __restrict__ list_b, const unsigned long long* __restrict__ n_b,
-                            int first) {
-  if (aborted(R.st)) return;
-  const uint64_t nt = first ? R.dim_count[2] : *n_t;
-  const uint64_t nb = first ? 0 : *n_b;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nt + nb; i += stride) {
-    uint32_t c;
-    if (i < nt) {
-      c = first ? (uint32_t)i : list_t[i];
-      if (first && R.cleared[c]) continue;
-    } else {
-      c = list_b[i - nt];
-    }
-    const uint64_t e = R.piv[c];
-    if (e != YIELDED) R.claim[pivot_slot(R, e)] = 0x7FFFFFFF;
   }
 }
 
@@ -1732,7 +1711,7 @@ __global__ void k_h1_emit(RedCtx R, EmitCtx E) {
 
 RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64_t* skeys,
                    const unsigned long long* dim_count, const uint8_t* cleared, const uint8_t* eapp,
-                   uint64_t* owner, int32_t* claim,
+                   uint64_t* owner, uint64_t* claim,
                    uint64_t* piv, uint64_t* col_ptr, uint64_t* arena, uint64_t arena_cap,
                    unsigned long long* arena_top, unsigned long long* work, Status* st) {
   RedCtx R;
@@ -1764,6 +1743,7 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.wave_yield = 0;
   R.yield_list = nullptr;
   R.yield_count = nullptr;
+  R.round = 0;
   return R;
 }
 
@@ -1806,22 +1786,22 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
     unsigned long long* ct = counts + 2 * (r % 3);
     unsigned long long* cnx = counts + 2 * ((r + 1) % 3);
     unsigned long long* cclr = counts + 2 * ((r + 2) % 3);
+    RedCtx Rr = R;  // this round's number; columns that yield go to its next long list
+    Rr.round = (uint32_t)r;
+    Rr.yield_list = lists[2 * nxt + 1];
+    Rr.yield_count = cnx + 1;
+    if (r >= yield_rounds) Rr.wave_yield = 0;
     if (first)
-      k_red_round<THREAD_CAP_FIRST><<<grid, 256, 0, s>>>(R, lt, ct, first, lists[2 * nxt], cnx, lists[2 * nxt + 1],
+      k_red_round<THREAD_CAP_FIRST><<<grid, 256, 0, s>>>(Rr, lt, ct, first, lists[2 * nxt], cnx, lists[2 * nxt + 1],
                                                          cnx + 1);
     else
-      k_red_round<THREAD_CAP><<<grid, 256, 0, s>>>(R, lt, ct, first, lists[2 * nxt], cnx, lists[2 * nxt + 1], cnx + 1);
+      k_red_round<THREAD_CAP><<<grid, 256, 0, s>>>(Rr, lt, ct, first, lists[2 * nxt], cnx, lists[2 * nxt + 1], cnx + 1);
     if (!first) {
-      RedCtx Rr = R;  // columns that yield go to this round's next long list
-      Rr.yield_list = lists[2 * nxt + 1];
-      Rr.yield_count = cnx + 1;
-      if (r >= yield_rounds) Rr.wave_yield = 0;
       k_red_round_wave<NarrowCfg><<<ngrid, 64 * WPB, nlds, s>>>(Rr, lt, ct, lb, ct + 1, R.narrow_cap);
       k_red_round_wave<WideCfg><<<wgrid, 64 * WPB, lds, s>>>(Rr, lt, ct, lb, ct + 1, R.front_cap);
       k_red_round_group<<<ncu, 64 * GNW, glds, s>>>(Rr, lt, ct, lb, ct + 1, gcap);
     }
-    k_red_commit<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first, lists[2 * nxt], lists[2 * nxt + 1], cnx, cclr);
-    k_red_reset<<<grid, 256, 0, s>>>(R, lt, ct, lb, ct + 1, first);
+    k_red_commit<<<grid, 256, 0, s>>>(Rr, lt, ct, lb, ct + 1, first, lists[2 * nxt], lists[2 * nxt + 1], cnx, cclr);
   }
 }
 
