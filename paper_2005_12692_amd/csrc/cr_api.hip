@@ -487,9 +487,13 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     R.front_cap = (uint32_t)tu.front_cap;
     R.wave_yield = (uint32_t)tu.wave_yield;
     // a batch's rounds hold the columns of many volumes: a workgroup per column
-    // pays off only in rounds of at most 256 of them (32 x 128^3: 55 -> 52 ms;
-    // a single 256^3 volume is fastest with 1024)
-    if (pb.nimg >= 8) R.group_max = 256;
+    // pays off only in rounds of at most 256 of them, and the narrow wavefront
+    // configuration already from 2048 (32 x 128^3: 55 -> 49.5 ms; a single
+    // 256^3 volume is fastest with 1024 and 8192)
+    if (pb.nimg >= 8) {
+      R.group_max = 256;
+      R.narrow_min = 2048;
+    }
     // thresholds between thread and wave mode and the wave-mode front capacity
     // (CR_LONG_LEN / CR_YIELD_ITERS / CR_WAVE_SHORT / CR_FRONT_CAP override them,
     // e.g. to exercise wave mode and its tail merges on small inputs)
