@@ -381,7 +381,7 @@ def main():
         "rows": rows,
         "rows_per_dim": np.bincount(d.dim.cpu().numpy(), minlength=3).tolist(),
         "reduction": {"arena_entries_used": st["arena_used"], "additions": st["red_adds"],
-                      "entries_merged": st["red_merged"], "max_column": st["red_max_col"],
+                      "entries_merged": st["red_merged"],
                       "rounds": st["red_rounds"]},
     }
     line["copy_ceiling_GBs"] = copy_ceiling()

@@ -98,9 +98,17 @@ typedef struct cr_diagram {
  *           the grid, Sec. 2).  shape : host, ndim extents >= 1, C order.
  *   maxdim: highest dimension reported; >= 0, clamped to ndim-1.
  *   flags : 0 or CR_FLAG_STAGE_TIMES.
- * Synchronises `stream` once (to learn the number of rows), then allocates
- * `out` and enqueues the final copy on `stream`.  Errors: INVALID_ARGUMENT,
- * NAN_INPUT, TOO_LARGE (more than 2^30 cells), OUT_OF_MEMORY, HIP, INTERNAL. */
+ * Host waits: the call returns after the rows are counted (one wait for the
+ * stream), then allocates `out` and enqueues the final copy on `stream`.  A
+ * volume with maxdim >= 1 also waits while the degree-1 reduction runs: its
+ * rounds are enqueued in batches of four and the host reads the count of
+ * columns still active one batch behind (an event wait per batch, about 18 on
+ * a 256^3 volume; the GPU is never left idle by them).  If the reduction's
+ * column arena (the stored columns) overflows, the whole pipeline is rerun with
+ * a larger arena, at most three times (cr_stats.arena_reruns counts reruns);
+ * CR_ARENA_ENTRIES in the environment fixes the first attempt's arena.
+ * Errors: INVALID_ARGUMENT, NAN_INPUT, TOO_LARGE (more than 2^30 cells),
+ * OUT_OF_MEMORY, HIP, INTERNAL. */
 cr_status cr_persistence(cr_context* ctx, const float* image, int ndim, const int64_t* shape, int maxdim,
                          uint32_t flags, void* stream, cr_diagram* out);
 
@@ -109,7 +117,9 @@ void cr_diagram_free(cr_context* ctx, cr_diagram* d);
 
 /* Diagrams of n_images images of one ndim and possibly different shapes,
  * packed back to back in one device buffer, computed together in one pass of
- * every stage (the images share each launch).
+ * every stage (the images share each launch).  Each image's diagram is the one
+ * cr_persistence gives; the batch serves the paper's many-image use, e.g.
+ * lifetime-enhanced images of a whole dataset fed to a network (Example 4.7).
  *   packed        : device floats; image i occupies [pixel_offsets[i], pixel_offsets[i+1]).
  *   pixel_offsets : host, n_images+1 entries, pixel_offsets[0] = 0, consistent with shapes.
  *   shapes        : host, n_images*ndim extents, C order per image (ndim 1, 2 or 3).
@@ -134,9 +144,11 @@ cr_status cr_persistence_batched(cr_context* ctx, int n_images, const float* pac
  * call whose need fits the reservation allocates no device memory, so it can
  * be enqueued where allocation is not allowed (the pinned host buffer that
  * uploads the image descriptors is allocated by the context's first batched
- * call).  cr_reserve never shrinks the scratch; it synchronises the device
- * when it has to grow it.  Errors: INVALID_ARGUMENT, TOO_LARGE,
- * OUT_OF_MEMORY. */
+ * call).  cr_batched_workspace_size takes ctx = NULL for a context's defaults
+ * (then it makes no HIP call at all).  cr_reserve never shrinks the scratch; it
+ * synchronises the device when it has to grow it.  Errors: INVALID_ARGUMENT,
+ * TOO_LARGE (more than 2^30 cells in an image, 2^31 pixels or 2^32 cells in a
+ * call, or a key layout beyond 64 bits), OUT_OF_MEMORY. */
 cr_status cr_batched_workspace_size(cr_context* ctx, int n_images, const int64_t* shapes, int ndim, int maxdim,
                                     size_t* bytes);
 cr_status cr_reserve(cr_context* ctx, size_t bytes);
@@ -146,8 +158,10 @@ cr_status cr_reserve(cr_context* ctx, size_t bytes);
  * CR_ERR_OUT_OF_MEMORY for scratch exhaustion, or CR_ERR_INTERNAL). */
 cr_status cr_sync_status(cr_context* ctx, void* stream);
 
-/* Gradient of a loss L(birth, death) with respect to the image: since
- * birth_i = image[birth_pixel_i] and death_i = image[death_pixel_i],
+/* Gradient of a loss L(birth, death) with respect to the image.  A cell takes
+ * the value of its largest vertex (the V-construction, Sec. 2), so each bar end
+ * is the value of one pixel, its location (Example 4.6):
+ * birth_i = image[birth_pixel_i] and death_i = image[death_pixel_i], hence
  *   grad_image[birth_pixel_i] += grad_birth_i,  grad_image[death_pixel_i] += grad_death_i
  * (rows with death_pixel -1 contribute only their birth).  All arrays are device
  * arrays of n_pairs rows; grad_birth or grad_death may be NULL (zero).
@@ -201,8 +215,8 @@ typedef struct cr_stats {
   int64_t arena_used;   /* 64-bit entries of column storage used by the reduction */
   int64_t red_adds;     /* column additions performed by the reduction */
   int64_t red_merged;   /* list entries read by those additions */
-  int64_t red_max_col;  /* longest working column of the reduction */
   int64_t red_rounds;   /* rounds of the degree-1 reduction (plain call) */
+  int64_t arena_reruns; /* plain calls on this context that reran with a larger column arena */
 } cr_stats;
 cr_status cr_get_stats(cr_context* ctx, cr_stats* out);
 

@@ -394,6 +394,7 @@ int64_t oracle_n_cell_pairs(const oracle_result* r) { return r ? r->n_cell_pairs
 void oracle_get_pairs(const oracle_result* r, int32_t* dim, float* birth, float* death,
                       int64_t* birth_pixel, int64_t* death_pixel) {
     size_t n = (size_t)r->n_pairs;
+    if (n == 0) return;  /* the arrays may be NULL then (memcpy from NULL is undefined) */
     if (dim) memcpy(dim, r->dim, n * sizeof(int32_t));
     if (birth) memcpy(birth, r->birth, n * sizeof(float));
     if (death) memcpy(death, r->death, n * sizeof(float));
@@ -403,6 +404,7 @@ void oracle_get_pairs(const oracle_result* r, int32_t* dim, float* birth, float*
 
 void oracle_get_cell_pairs(const oracle_result* r, int64_t* birth_kidx, int64_t* death_kidx) {
     size_t n = (size_t)r->n_cell_pairs;
+    if (n == 0) return;  /* the degree-0 union-find keeps no cell pairing: NULL arrays */
     if (birth_kidx) memcpy(birth_kidx, r->cp_birth, n * sizeof(int64_t));
     if (death_kidx) memcpy(death_kidx, r->cp_death, n * sizeof(int64_t));
 }

@@ -44,8 +44,8 @@ class _Stats(ctypes.Structure):
     _fields_ = [("n_pixels", ctypes.c_int64), ("n_cells", ctypes.c_int64),
                 ("survivors", ctypes.c_int64 * 4), ("n_rows", ctypes.c_int64),
                 ("arena_used", ctypes.c_int64), ("red_adds", ctypes.c_int64),
-                ("red_merged", ctypes.c_int64), ("red_max_col", ctypes.c_int64),
-                ("red_rounds", ctypes.c_int64)]
+                ("red_merged", ctypes.c_int64),
+                ("red_rounds", ctypes.c_int64), ("arena_reruns", ctypes.c_int64)]
 
 
 class _Tuning(ctypes.Structure):
@@ -553,4 +553,5 @@ def stats(device=None) -> dict:
     _check(lib().cr_get_stats(h, ctypes.byref(s)))
     return {"n_pixels": s.n_pixels, "n_cells": s.n_cells, "survivors": list(s.survivors),
             "n_rows": s.n_rows, "arena_used": s.arena_used, "red_adds": s.red_adds,
-            "red_merged": s.red_merged, "red_max_col": s.red_max_col, "red_rounds": s.red_rounds}
+            "red_merged": s.red_merged, "red_rounds": s.red_rounds,
+            "arena_reruns": s.arena_reruns}

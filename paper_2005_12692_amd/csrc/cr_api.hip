@@ -64,6 +64,12 @@ cr_status fail(cr_status s, const std::string& msg) {
       return fail(CR_ERR_HIP, std::string(#expr " failed: ") + hipGetErrorString(e_));       \
   } while (0)
 
+// A non-negative integer from the environment, or `def` when unset.
+uint64_t env_u64(const char* name, uint64_t def) {
+  const char* v = getenv(name);
+  return (v && *v) ? (uint64_t)strtoull(v, nullptr, 10) : def;
+}
+
 int bits_for(uint64_t x) {  // smallest b with x < 2^b
   int b = 0;
   while (b < 64 && (x >> b) != 0) ++b;
@@ -120,7 +126,7 @@ struct cr_context {
   hipEvent_t round_ev[2] = {};   // the reduction's list counts of a batch of rounds have landed
   hipStream_t side = nullptr;    // degree 0 of a volume runs here beside degree 2 and the reduction
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
-  uint64_t arena_entries = 1ull << 28;
+  uint64_t arena_entries = 1ull << 28;  // column arena of the next call (grown on overflow)
   Plan plan{};
   Problem prob{};
   cr_stats stats{};
@@ -128,6 +134,7 @@ struct cr_context {
   uint32_t* bwd_flag = nullptr;  // device word for the backward index check
   bool sync_allowed = false;     // the plain call may synchronise between reduction rounds
   int rounds = 0;
+  int reruns = 0;                // plain calls rerun with a larger column arena (since creation)
   // stage timing (CR_FLAG_STAGE_TIMES)
   hipEvent_t ev[8] = {};
   bool ev_ready = false;
@@ -137,6 +144,19 @@ struct cr_context {
 };
 
 namespace {
+
+// Column arena (64-bit entries) of a batched call, which cannot rerun: the
+// context's size (grown when a batched call is found to have overflowed it),
+// at least ARENA_PER_PIXEL entries per pixel of the batch (a 256^3 volume of
+// blobs and noise uses ~12.8), or CR_ARENA_ENTRIES when that is set.
+constexpr uint64_t ARENA_PER_PIXEL = 16;
+constexpr uint64_t ARENA_DEFAULT = 1ull << 28;
+uint64_t batch_arena(const cr_context* ctx, const Problem& pb) {
+  const uint64_t env = env_u64("CR_ARENA_ENTRIES", 0);
+  if (env) return env;
+  const uint64_t have = ctx ? ctx->arena_entries : ARENA_DEFAULT;
+  return std::max(have, std::min<uint64_t>(ARENA_MAX, ARENA_PER_PIXEL * pb.P));
+}
 
 // counters block: surv_count, dim_count[4], cand_count, arena_top, lists[4], wave work counter
 enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* six words */, C_WORK = 13, C_WORDS = 14 };
@@ -577,8 +597,8 @@ cr_status read_counters(cr_context* ctx, hipStream_t s, HostCounters* h) {
   S.arena_used = (int64_t)h->cnt[C_ARENA];
   S.red_adds = (int64_t)h->st.adds;
   S.red_merged = (int64_t)h->st.merged;
-  S.red_max_col = (int64_t)h->st.max_col;
   S.red_rounds = ctx->rounds;
+  S.arena_reruns = ctx->reruns;
   return CR_OK;
 }
 
@@ -748,8 +768,12 @@ cr_status cr_persistence(cr_context* ctx, const float* image, int ndim, const in
   if (ndim < 1 || ndim > 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 1, 2 or 3");
   cr_status rc = build_problem(ctx->prob, 1, nullptr, shape, ndim, maxdim, ctx->tune[grid_ndim(ndim)].tile);
   if (rc != CR_OK) return rc;
+  // CR_ARENA_ENTRIES fixes the column arena of the first attempt (e.g. small,
+  // to drive the overflow-and-rerun path on a small volume)
+  const uint64_t arena_env = env_u64("CR_ARENA_ENTRIES", 0);
+  uint64_t arena = arena_env ? arena_env : ctx->arena_entries;
   for (int attempt = 0; attempt < 4; ++attempt) {
-    ctx->plan = make_plan(ctx->prob, ctx->arena_entries, /*side_h0=*/true);
+    ctx->plan = make_plan(ctx->prob, arena, /*side_h0=*/true);
     rc = ensure_scratch(ctx, ctx->plan.total);
     if (rc != CR_OK) return rc;
     uint64_t* cand = nullptr;
@@ -762,8 +786,12 @@ cr_status cr_persistence(cr_context* ctx, const float* image, int ndim, const in
     rc = status_error(h.st, &arena_over);
     if (rc != CR_OK) {
       if (arena_over && attempt < 3 && ctx->plan.arena_cap < ARENA_MAX) {
-        ctx->arena_entries = std::max<uint64_t>(ctx->arena_entries * 4, h.cnt[C_ARENA] * 2);
-        continue;  // rerun with a larger column arena
+        // the arena top counts the entries asked for before the abort, a
+        // lower bound of the need
+        arena = std::max<uint64_t>(arena * 4, h.cnt[C_ARENA] * 2);
+        if (!arena_env) ctx->arena_entries = arena;
+        ++ctx->reruns;
+        continue;  // rerun the whole pipeline with a larger column arena
       }
       return rc;
     }
@@ -818,12 +846,14 @@ void cr_diagram_free(cr_context* ctx, cr_diagram* d) {
 
 cr_status cr_batched_workspace_size(cr_context* ctx, int n_images, const int64_t* shapes, int ndim, int maxdim,
                                     size_t* bytes) {
-  if (!ctx || !bytes) return fail(CR_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (!bytes) return fail(CR_ERR_INVALID_ARGUMENT, "NULL argument");
+  *bytes = 0;
   if (ndim < 1 || ndim > 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 1, 2 or 3");
   Problem pb;
-  cr_status rc = build_problem(pb, n_images, nullptr, shapes, ndim, maxdim, ctx->tune[grid_ndim(ndim)].tile);
+  const int tile = ctx ? ctx->tune[grid_ndim(ndim)].tile : default_tuning(grid_ndim(ndim)).tile;
+  cr_status rc = build_problem(pb, n_images, nullptr, shapes, ndim, maxdim, tile);
   if (rc != CR_OK) return rc;
-  *bytes = make_plan(pb, ctx->arena_entries).total;
+  *bytes = make_plan(pb, batch_arena(ctx, pb)).total;
   return CR_OK;
 }
 
@@ -846,7 +876,7 @@ cr_status cr_persistence_batched(cr_context* ctx, int n_images, const float* pac
   ctx->last_batched_valid = false;
   rc = build_problem(ctx->prob, n_images, pixel_offsets, shapes, ndim, maxdim, ctx->tune[grid_ndim(ndim)].tile);
   if (rc != CR_OK) return rc;
-  ctx->plan = make_plan(ctx->prob, ctx->arena_entries);
+  ctx->plan = make_plan(ctx->prob, batch_arena(ctx, ctx->prob));
   rc = ensure_scratch(ctx, ctx->plan.total);
   if (rc != CR_OK) return rc;
   rc = enqueue_batch(ctx, a, s, true);
@@ -1012,7 +1042,7 @@ cr_status cr_batched_graph_create(cr_context* ctx, int n_images, const float* pa
     delete g;
     return rc;
   }
-  g->own.plan = make_plan(g->own.prob, ctx->arena_entries);
+  g->own.plan = make_plan(g->own.prob, batch_arena(ctx, g->own.prob));
   g->own.bytes = align_up(g->own.plan.total, 1 << 21);
   if (hipMalloc(&g->own.scratch, g->own.bytes) != hipSuccess) {
     (void)hipGetLastError();

@@ -40,7 +40,7 @@ struct Status {
   uint32_t internal;       // an invariant of the algorithm failed (bug guard)
   uint32_t iter_cap;       // a bounded loop hit its iteration cap
   uint32_t abort;          // set together with any of the above: stop early
-  uint32_t max_col;        // longest column seen by the reduction
+  uint32_t pad;
   unsigned long long adds; // column additions performed by the reduction
   unsigned long long merged;  // list entries read by those additions
 };

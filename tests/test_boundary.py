@@ -113,3 +113,34 @@ def test_tile_shapes_and_null_handles(libcr):
     libcr.cr_get_tuning.restype = ctypes.c_int
     assert libcr.cr_get_tuning(None, 3, None) == 1
     libcr.cr_graph_destroy(None)  # a no-op
+
+
+def test_workspace_size_without_a_context(libcr):
+    """cr_batched_workspace_size with ctx = NULL is host-only: it sizes a batch,
+    and reports CR_ERR_TOO_LARGE for an image of 2^30 cells or more and for a
+    batch whose keys would not fit 64 bits."""
+    f = libcr.cr_batched_workspace_size
+    f.restype = ctypes.c_int
+    out = ctypes.c_size_t(7)
+    sh = (ctypes.c_int64 * 2)(64, 64)
+    assert f(None, 1, sh, 2, 1, ctypes.byref(out)) == 0
+    small = out.value
+    assert small > 0
+    sh2 = (ctypes.c_int64 * 4)(64, 64, 128, 64)
+    assert f(None, 2, sh2, 2, 1, ctypes.byref(out)) == 0 and out.value > small
+    # (2 * 600 - 1)^3 = 1.72e9 cells >= 2^30
+    big = (ctypes.c_int64 * 3)(600, 600, 600)
+    out.value = 7
+    assert f(None, 1, big, 3, 2, ctypes.byref(out)) == 3
+    assert out.value == 0
+    assert b"2^30" in libcr.cr_last_error()
+    # one extent beyond 2^29
+    huge = (ctypes.c_int64 * 2)(1, (1 << 29) + 1)
+    assert f(None, 1, huge, 2, 1, ctypes.byref(out)) == 3
+    # 2^16 images of 128 x 64: image field 16 bits + 2 + 32 + 15-bit index > 64
+    n = 1 << 16
+    many = (ctypes.c_int64 * (2 * n))(*([128, 64] * n))
+    assert f(None, n, many, 2, 1, ctypes.byref(out)) == 3
+    # bad arguments stay INVALID_ARGUMENT
+    assert f(None, 1, sh, 4, 1, ctypes.byref(out)) == 1
+    assert f(None, 0, sh, 2, 1, ctypes.byref(out)) == 1
