@@ -153,6 +153,28 @@ cr_status cr_batched_workspace_size(cr_context* ctx, int n_images, const int64_t
                                     size_t* bytes);
 cr_status cr_reserve(cr_context* ctx, size_t bytes);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): cr_persistence_batched with
+ * the same arguments and results, run on a scratch array that the library
+ * holds in static device memory, CR_NOALLOC_SCRATCH_BYTES on every GPU it runs
+ * on (set up by cr_create, kept until the process ends).  The call makes no
+ * device or pinned-host allocation: the image descriptors are copied from
+ * pageable host memory, and the column arena of a volume's reduction is 16
+ * entries per pixel (CR_ARENA_ENTRIES overrides it).  A batch whose scratch
+ * (cr_batched_workspace_size's plan with that arena) exceeds the array is
+ * rejected with CR_ERR_TOO_LARGE before any device work.  Every call on one GPU
+ * shares that GPU's array, from any context: calls that overlap on one GPU
+ * (other streams, other contexts or threads) race and give undefined results;
+ * the array keeps the last call's contents, and the call clears what must
+ * start at zero.  cr_sync_status reports on it like on a batched call until
+ * the next batched call on the context. */
+#define CR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+cr_status cr_persistence_batched_noalloc(cr_context* ctx, int n_images, const float* packed,
+                                         const int64_t* pixel_offsets, const int64_t* shapes, int ndim, int maxdim,
+                                         uint32_t flags, void* stream, int32_t* dim, float* birth, float* death,
+                                         int64_t* birth_pixel, int64_t* death_pixel, int64_t capacity,
+                                         int64_t* pair_offsets, int32_t* status);
+
 /* Synchronises `stream` and returns the device-side status of the last
  * batched call on this context (CR_OK, CR_ERR_NAN_INPUT, CR_ERR_CAPACITY,
  * CR_ERR_OUT_OF_MEMORY for scratch exhaustion, or CR_ERR_INTERNAL). */
@@ -217,6 +239,7 @@ typedef struct cr_stats {
   int64_t red_merged;   /* list entries read by those additions */
   int64_t red_rounds;   /* rounds of the degree-1 reduction (plain call) */
   int64_t arena_reruns; /* plain calls on this context that reran with a larger column arena */
+  int64_t scratch_bytes; /* device scratch the context owns now (0 until a call needs it) */
 } cr_stats;
 cr_status cr_get_stats(cr_context* ctx, cr_stats* out);
 

@@ -45,7 +45,8 @@ class _Stats(ctypes.Structure):
                 ("survivors", ctypes.c_int64 * 4), ("n_rows", ctypes.c_int64),
                 ("arena_used", ctypes.c_int64), ("red_adds", ctypes.c_int64),
                 ("red_merged", ctypes.c_int64),
-                ("red_rounds", ctypes.c_int64), ("arena_reruns", ctypes.c_int64)]
+                ("red_rounds", ctypes.c_int64), ("arena_reruns", ctypes.c_int64),
+                ("scratch_bytes", ctypes.c_int64)]
 
 
 class _Tuning(ctypes.Structure):
@@ -101,6 +102,7 @@ def lib():
         L.cr_diagram_free.restype = None
         L.cr_persistence_batched.argtypes = [vp, i32, vp, ctypes.POINTER(i64), ctypes.POINTER(i64), i32, i32,
                                              ctypes.c_uint32, vp, vp, vp, vp, vp, vp, i64, vp, vp]
+        L.cr_persistence_batched_noalloc.argtypes = L.cr_persistence_batched.argtypes
         L.cr_sync_status.argtypes = [vp, vp]
         L.cr_persistence_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, i64, vp]
         L.cr_lifetime_image.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, vp, i64, vp]
@@ -121,7 +123,8 @@ def lib():
         L.cr_graph_sync_status.argtypes = [vp, vp]
         L.cr_graph_destroy.argtypes = [vp]
         L.cr_graph_destroy.restype = None
-        for f in ("cr_create", "cr_persistence", "cr_persistence_batched", "cr_sync_status",
+        for f in ("cr_create", "cr_persistence", "cr_persistence_batched", "cr_persistence_batched_noalloc",
+                  "cr_sync_status",
                   "cr_persistence_backward", "cr_lifetime_image", "cr_pixel_coords", "cr_batched_workspace_size",
                   "cr_reserve", "cr_get_stats", "cr_get_stage_times", "cr_get_tuning",
                   "cr_set_tuning", "cr_tile_variants", "cr_tile_shape", "cr_autotune_batched",
@@ -289,6 +292,27 @@ def persistence_batched(packed: torch.Tensor, shapes, pixel_offsets=None, maxdim
     _check(code)
     return BatchedDiagram(out.dim[:total], out.birth[:total], out.death[:total], out.birth_pixel[:total],
                           out.death_pixel[:total], out.pair_offsets, out.status)
+
+
+def persistence_batched_noalloc(packed: torch.Tensor, shapes, out: BatchedDiagram, pixel_offsets=None,
+                                maxdim: int | None = None) -> BatchedDiagram:
+    """cr_persistence_batched_noalloc: the batched call on the library's static
+    device scratch, into the caller's preallocated ``out`` (see ``_empty_out``).
+    Neither allocates nor synchronises; read ``out.pair_offsets`` and
+    ``out.status`` (or call ``sync_status``) after the stream completes."""
+    args, ndim, nimg, _, _, _ = _batch_prefix(packed, shapes, pixel_offsets, maxdim)
+    if out.pair_offsets.shape[0] != nimg + 1 or out.status.shape[0] != nimg:
+        raise ValueError("out does not match the number of images")
+    _check(lib().cr_persistence_batched_noalloc(*args, 0, _stream(packed.device), *_out_args(out)))
+    return out
+
+
+def sync_status(device=None) -> None:
+    """cr_sync_status: waits for the current stream and raises on a device-side
+    error of the last batched call on the device's context."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    h, _ = _context(dev)
+    _check(lib().cr_sync_status(h, _stream(dev)))
 
 
 def _batch_prefix(packed, shapes, pixel_offsets, maxdim):
@@ -554,4 +578,4 @@ def stats(device=None) -> dict:
     return {"n_pixels": s.n_pixels, "n_cells": s.n_cells, "survivors": list(s.survivors),
             "n_rows": s.n_rows, "arena_used": s.arena_used, "red_adds": s.red_adds,
             "red_merged": s.red_merged, "red_rounds": s.red_rounds,
-            "arena_reruns": s.arena_reruns}
+            "arena_reruns": s.arena_reruns, "scratch_bytes": s.scratch_bytes}

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <functional>
+#include <mutex>
 
 #include "cr.h"
 #include "cr_reduce.h"
@@ -47,6 +48,13 @@ bool stencil_tile(int ndim, int variant, int ext[3]);
 }  // namespace cr
 
 using namespace cr;
+
+// Scratch of cr_persistence_batched_noalloc, in static device memory: every GPU
+// the library runs on holds its own copy of the array from the load of the code
+// object until the process ends.  In host code this name is only a stand-in for
+// the symbol: the device address comes from hipGetSymbolAddress (noalloc_setup)
+// and is the one passed to kernels and copies.
+static __device__ __align__(256) char noalloc_scratch[CR_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -135,6 +143,8 @@ struct cr_context {
   bool sync_allowed = false;     // the plain call may synchronise between reduction rounds
   int rounds = 0;
   int reruns = 0;                // plain calls rerun with a larger column arena (since creation)
+  char* noalloc = nullptr;       // device address of this device's noalloc_scratch
+  bool last_noalloc = false;     // the last batched call ran on noalloc_scratch
   // stage timing (CR_FLAG_STAGE_TIMES)
   hipEvent_t ev[8] = {};
   bool ev_ready = false;
@@ -156,6 +166,34 @@ uint64_t batch_arena(const cr_context* ctx, const Problem& pb) {
   if (env) return env;
   const uint64_t have = ctx ? ctx->arena_entries : ARENA_DEFAULT;
   return std::max(have, std::min<uint64_t>(ARENA_MAX, ARENA_PER_PIXEL * pb.P));
+}
+
+// Device address of noalloc_scratch on each device, looked up once per device
+// with that device current (each GPU holds its own copy at its own address).
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+cr_status noalloc_setup(int device, char** out) {
+  *out = nullptr;
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return fail(CR_ERR_INVALID_ARGUMENT, "device index too large");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(CR_ERR_HIP, std::string("hipGetSymbolAddress(noalloc_scratch) failed: ") + hipGetErrorString(e));
+    g_noalloc_ptr[device] = static_cast<char*>(ptr);
+  }
+  *out = g_noalloc_ptr[device];
+  return CR_OK;
+}
+
+// Column arena of a batched call on noalloc_scratch: ARENA_PER_PIXEL entries per
+// pixel (at least 2^16), or CR_ARENA_ENTRIES when that is set.
+uint64_t noalloc_arena(const Problem& pb) {
+  const uint64_t env = env_u64("CR_ARENA_ENTRIES", 0);
+  return env ? env : std::max<uint64_t>(1ull << 16, ARENA_PER_PIXEL * pb.P);
 }
 
 // counters block: surv_count, dim_count[4], cand_count, arena_top, lists[4], wave work counter
@@ -397,6 +435,19 @@ cr_status upload_descriptors(cr_context* ctx, hipStream_t s, bool sync) {
     HIP_TRY(hipEventRecord(ctx->stage_done, s));
     ctx->stage_pending = true;
   }
+  return CR_OK;
+}
+
+// The same copies from the problem's own (pageable) host vectors, with no
+// pinned staging buffer: the runtime stages pageable memory itself before the
+// call returns, so the vectors may change afterwards.
+cr_status upload_descriptors_pageable(cr_context* ctx, hipStream_t s) {
+  const Problem& pb = ctx->prob;
+  const Plan& p = ctx->plan;
+  HIP_TRY(hipMemcpyAsync(at<ImgDesc>(ctx, p.imgs), pb.imgs.data(), sizeof(ImgDesc) * pb.nimg,
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(at<int4>(ctx, p.tiles), pb.tiles.data(), sizeof(int4) * pb.tiles.size(),
+                         hipMemcpyHostToDevice, s));
   return CR_OK;
 }
 
@@ -719,6 +770,13 @@ cr_status cr_create(cr_context** out, int device, cr_alloc_fn alloc, cr_free_fn 
   cr_context* c = new (std::nothrow) cr_context();
   if (!c) return fail(CR_ERR_OUT_OF_MEMORY, "context allocation failed");
   c->device = device;
+  {
+    const cr_status src = noalloc_setup(device, &c->noalloc);
+    if (src != CR_OK) {
+      delete c;
+      return src;
+    }
+  }
   for (int d = 0; d < 4; ++d) c->tune[d] = default_tuning(d);
   c->alloc = alloc;
   c->free_fn = free_fn;
@@ -879,8 +937,46 @@ cr_status cr_persistence_batched(cr_context* ctx, int n_images, const float* pac
   ctx->plan = make_plan(ctx->prob, batch_arena(ctx, ctx->prob));
   rc = ensure_scratch(ctx, ctx->plan.total);
   if (rc != CR_OK) return rc;
+  ctx->last_noalloc = false;
   rc = enqueue_batch(ctx, a, s, true);
   if (rc != CR_OK) return rc;
+  ctx->last_batched_valid = true;
+  return CR_OK;
+}
+
+cr_status cr_persistence_batched_noalloc(cr_context* ctx, int n_images, const float* packed,
+                                         const int64_t* pixel_offsets, const int64_t* shapes, int ndim, int maxdim,
+                                         uint32_t flags, void* stream, int32_t* dim, float* birth, float* death,
+                                         int64_t* birth_pixel, int64_t* death_pixel, int64_t capacity,
+                                         int64_t* pair_offsets, int32_t* status) {
+  const BatchArgs a{n_images, packed, pixel_offsets, shapes, ndim, maxdim, flags, dim, birth, death,
+                    birth_pixel, death_pixel, capacity, pair_offsets, status};
+  cr_status rc = check_batch_args(ctx, a);
+  if (rc != CR_OK) return rc;
+  if (!ctx->noalloc) return fail(CR_ERR_INTERNAL, "the context has no static scratch");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  ctx->last_batched_valid = false;
+  rc = build_problem(ctx->prob, n_images, pixel_offsets, shapes, ndim, maxdim, ctx->tune[grid_ndim(ndim)].tile);
+  if (rc != CR_OK) return rc;
+  const Plan plan = make_plan(ctx->prob, noalloc_arena(ctx->prob));
+  if (plan.total > CR_NOALLOC_SCRATCH_BYTES)
+    return fail(CR_ERR_TOO_LARGE, "the batch needs " + std::to_string(plan.total) +
+                                      " bytes of scratch; the static scratch of the allocation-free call holds " +
+                                      std::to_string((size_t)CR_NOALLOC_SCRATCH_BYTES));
+  ctx->plan = plan;
+  // run on this device's static array (the kernels take its device address),
+  // then give the context its own scratch back
+  char* const own = ctx->scratch;
+  const size_t own_bytes = ctx->scratch_bytes;
+  ctx->scratch = ctx->noalloc;
+  ctx->scratch_bytes = CR_NOALLOC_SCRATCH_BYTES;
+  rc = upload_descriptors_pageable(ctx, s);
+  if (rc == CR_OK) rc = enqueue_batch(ctx, a, s, false);
+  ctx->scratch = own;
+  ctx->scratch_bytes = own_bytes;
+  if (rc != CR_OK) return rc;
+  ctx->last_noalloc = true;
   ctx->last_batched_valid = true;
   return CR_OK;
 }
@@ -890,7 +986,10 @@ cr_status cr_sync_status(cr_context* ctx, void* stream) {
   if (!ctx->last_batched_valid) return fail(CR_ERR_INVALID_ARGUMENT, "no batched call to report on");
   HIP_TRY(hipSetDevice(ctx->device));
   HostCounters h;
+  char* const own = ctx->scratch;
+  if (ctx->last_noalloc) ctx->scratch = ctx->noalloc;  // the counters of the last call are there
   cr_status rc = read_counters(ctx, (hipStream_t)stream, &h);
+  ctx->scratch = own;
   if (rc != CR_OK) return rc;
   bool arena_over = false;
   return status_error(h.st, &arena_over);
@@ -989,6 +1088,7 @@ cr_status cr_get_stage_times(cr_context* ctx, float* ms, int capacity, int* n_st
 cr_status cr_get_stats(cr_context* ctx, cr_stats* out) {
   if (!ctx || !out) return fail(CR_ERR_INVALID_ARGUMENT, "NULL argument");
   *out = ctx->stats;
+  out->scratch_bytes = (int64_t)ctx->scratch_bytes;
   return CR_OK;
 }
 
