@@ -9,13 +9,25 @@ N = (2*256-1)^3 = 133,432,831 cells per step.
 
 Also reported (one JSON line):
   roofline     -- the stencil kernel (filtration + apparent pairs + survivor
-                  compaction, the HBM-streaming pass) against the 8 TB/s HBM peak;
+                  compaction, the HBM-streaming pass) against the 8 TB/s HBM peak,
+                  on its algorithmic bytes 4 P + 8 S (read every pixel once, write
+                  each survivor's 64-bit key); the forest links and edge partner
+                  codes it also writes are given apart ("side_output_bytes");
                   its duration is the mean of HIP events recorded around it on the
                   call's stream during the timed steps; "issue" gives its profiled
                   VALU instructions per launch against the single-issue ceiling,
                   "cold" the same stage with the last-level cache flushed before
                   the call (outside the timed steps);
-  cpu_baseline -- the CPU oracle timed on a bounded sample of the workload;
+  roofline_sort -- the sort of the surviving cells, likewise (16 B per key and
+                  pass);
+  image_1024   -- the 1024^2 sigma-4 Gaussian field (seed 1), H0+H1, plain call:
+                  latency (median and min of 20 calls) and cells/s;
+  image_64     -- the 64^2 uniform image (seed 0), H0+H1, plain call latency;
+  cpu_baseline -- the CPU oracle (one host core, in a child process started at
+                  the beginning, running beside the GPU legs) on the full 256^3
+                  volume, and on the two images, with its peak RSS, the CPU model
+                  and the RAM; the digests of its diagrams are compared with the
+                  GPU's; the paper's own timings are quoted with their hardware;
   stages       -- mean per-stage times over the timed steps;
   batched      -- 512 2D images of sides 28..512 (half uniform noise, half
                   sigma-2 fields): images/s of one batched call replayed from a
@@ -43,15 +55,25 @@ VALU_PEAK_GINST = 256 * 4 * 2.4 / 4  # G wavefront VALU instructions per second,
 
 
 def stencil_bytes(shape, survivors_total: int) -> int:
-    """Algorithmic bytes of one stencil launch: read every pixel once (4 B),
-    write each survivor's 64-bit key (8 B), write the vertex-forest link of
-    every pixel (4 B) and the dual-forest link of every top cell (4 B)."""
+    """Algorithmic bytes of one stencil launch: read every pixel once (4 B) and
+    write each survivor's 64-bit key (8 B)."""
+    P = 1
+    for n in shape:
+        P *= n
+    return 4 * P + 8 * survivors_total
+
+
+def stencil_side_bytes(shape, edge_codes: bool) -> int:
+    """Bytes the stencil writes besides the survivor keys, for the later stages:
+    the vertex-forest link of every pixel (4 B), the dual-forest link of every
+    top cell (4 B) and, for a volume's degree-1 reduction, the partner code of
+    each of the three edges anchored at a pixel (1 B each)."""
     P = 1
     C = 1
     for n in shape:
         P *= n
         C *= n - 1
-    return 4 * P + 8 * survivors_total + 4 * P + 4 * C
+    return 4 * P + 4 * C + (3 * P if edge_codes else 0)
 
 
 def sort_bytes(n_keys: int, bits: int) -> int:
@@ -117,17 +139,118 @@ def copy_ceiling(nbytes: int = 1 << 28, reps: int = 5) -> float:
     return 2 * nbytes * reps / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
 
 
-def cpu_baseline(vol):
+def diagram_digest(dim, birth, death, bp, dp) -> str:
+    """sha256 over the five row arrays (dim int32, birth/death float32, pixels
+    int64), concatenated in canonical row order."""
+    import hashlib
     import numpy as np
+    h = hashlib.sha256()
+    for arr, dt in ((dim, np.int32), (birth, np.float32), (death, np.float32), (bp, np.int64), (dp, np.int64)):
+        h.update(np.ascontiguousarray(arr, dt).tobytes())
+    return h.hexdigest()
+
+
+# workloads of the CPU baseline: name, generator name, repetitions
+CPU_RUNS = (("image_64", "C1", 3), ("image_1024", "C2", 3), ("volume_256", "C3", 1))
+
+
+def cpu_worker() -> None:
+    """Child process: times the oracle (one core) on each workload after its
+    input is built, records the peak RSS after each (the workloads grow, so the
+    running maximum is the last one's peak) and prints one JSON line."""
+    import resource
     import oracle
-    sample = np.ascontiguousarray(vol[:128, :128, :128])
-    t0 = time.perf_counter()
-    d = oracle.persistence(sample, maxdim=2)
-    dt = time.perf_counter() - t0
-    cells = 255 ** 3
-    return {"value": cells / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
-            "sample": "the 128^3 corner [:128,:128,:128] of the same volume, degrees 0-2, "
-                      f"{cells} cells, {len(d)} bars, {dt:.2f} s on one host core"}
+    import synth
+    oracle.build()
+    out = {}
+    for name, cfg, reps in CPU_RUNS:
+        img = synth.config(cfg)
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            d = oracle.persistence(img, maxdim=img.ndim - 1)
+            times.append(time.perf_counter() - t0)
+        times.sort()
+        out[name] = {"seconds_median": times[len(times) // 2], "seconds_min": times[0], "runs": reps,
+                     "peak_rss_bytes": resource.getrusage(resource.RUSAGE_SELF).ru_maxrss * 1024,
+                     "rows": len(d), "digest": diagram_digest(d.dim, d.birth, d.death, d.birth_pixel, d.death_pixel)}
+        print(f"cpu: {name} {times[0]:.2f} s", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def host_info() -> dict:
+    model, mem = None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem = int(line.split()[1]) * 1024
+                break
+    except OSError:
+        pass
+    info = {"cpu_model": model, "ram_bytes": mem, "logical_cpus": os.cpu_count()}
+    try:
+        info["cpus_available"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    return info
+
+
+# The paper's own timings (Table 3; Table 1 for the machine): Cubical Ripser on
+# real data of the same sizes, one process on an AMD Ryzen Threadripper 2990WX
+# (32 cores, 64 GB), float64 input, 5-run averages including program load and
+# file I/O.  Context only: other data, other machine, other precision.
+PAPER = {
+    "hardware": "AMD Ryzen Threadripper 2990WX (32 cores), 64 GB RAM, one process, float64 input, "
+                "average of 5 runs including program load and file I/O (Tables 1 and 3)",
+    "volume_256": {"Bonsai256_s": 38.0, "Head256_s": 50.0},
+    "image_1024": {"Lena1024_s": 0.81},
+    "volume_128": {"Bonsai128_s": 4.5, "Head128_s": 6.6},
+}
+
+
+def cpu_baseline(child, gpu_digests: dict) -> dict:
+    """Collects the child's oracle timings; value = cells/s on the full 256^3 volume."""
+    out, _ = child.communicate(timeout=1500)
+    if child.returncode != 0:
+        raise RuntimeError(f"CPU baseline worker failed with status {child.returncode}")
+    res = json.loads(out.strip().splitlines()[-1])
+    v = res["volume_256"]
+    cells = 511 ** 3
+    for name, r in res.items():
+        r["digest_equals_gpu"] = r.pop("digest") == gpu_digests.get(name)
+    return {"value": cells / v["seconds_min"], "unit": "cells/s", "cores": 1, "kind": "oracle",
+            "sample": "the whole 256^3 volume of the headline workload (133,432,831 cells, degrees 0-2), one run "
+                      "on one host core, input already in memory; run in a child process beside the GPU legs",
+            "seconds": v["seconds_min"], "peak_rss_bytes": v["peak_rss_bytes"], "host": host_info(),
+            "runs": res, "paper": PAPER}
+
+
+def bench_plain(x, reps: int = 20, warmup: int = 3) -> dict:
+    """Latency of plain calls on one resident image: median and min over reps
+    (each call synchronised, so the diagram is complete on the device)."""
+    import torch
+    import paper_2005_12692_amd as cr
+    for _ in range(warmup):
+        cr.persistence(x)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        d = cr.persistence(x)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    cells = 1
+    for n in x.shape:
+        cells *= 2 * n - 1
+    med = ts[len(ts) // 2]
+    host = [t.cpu().numpy() for t in d]
+    return {"ms_median": med * 1e3, "ms_min": ts[0] * 1e3, "reps": reps, "cells": cells,
+            "cells_per_s": cells / med, "rows": int(d.dim.shape[0]), "digest": diagram_digest(*host)}
 
 
 def bench_batched(reps: int = 3) -> dict:
@@ -285,7 +408,11 @@ def main():
                     help="skip the batched, fwd+bwd, masked, 1D and lifetime-image measurements")
     ap.add_argument("--copy-only", action="store_true",
                     help="only time a 256 MiB device copy (the reference kernel for profiler byte counts)")
+    ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker:
+        cpu_worker()
+        return
     if args.gpus != 1:
         print("bench.py: runs on one GPU only; --gpus must be 1 (sharding over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
@@ -299,6 +426,12 @@ def main():
 
     import paper_2005_12692_amd as cr
     import synth
+
+    child = None
+    if not args.no_cpu:  # the oracle runs on another host core while the GPU legs run
+        import subprocess
+        child = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker"],
+                                 stdout=subprocess.PIPE, text=True)
 
     n = 256
     vol = synth.blobs3d(n, 2)
@@ -329,6 +462,7 @@ def main():
     sbytes = sort_bytes(surv, sort_bits)
     s_achieved = sbytes / (stages["sort_cells"] * 1e-3) / 1e9
     rows = int(d.dim.shape[0])
+    gpu_digests = {"volume_256": diagram_digest(*[t.cpu().numpy() for t in d])}
     # the same stages with the last-level cache flushed before each call (the
     # 64 MiB input would otherwise stay in the 256 MB Infinity Cache), outside
     # the timed steps: three calls, median stage times
@@ -363,7 +497,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_stencil (filtration + apparent pairs + compaction)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic("k_stencil_256cube_traffic.md"),
-                     "algorithmic_bytes": nbytes, "ms": stages["stencil"],
+                     "algorithmic_bytes": nbytes, "pixels": n ** 3, "survivors": surv,
+                     "side_output_bytes": stencil_side_bytes((n, n, n), True), "ms": stages["stencil"],
                      "issue": issue_rate("k_stencil_256cube_traffic.md", stages["stencil"]),
                      "cold": {"ms": cold["stencil"], "achieved": c_achieved, "frac": c_achieved / HBM_PEAK_GBS}},
         "roofline_sort": {"bound": "hbm", "kernel": "cell sort, %d 8-bit passes (count + scan + scatter)"
@@ -385,12 +520,19 @@ def main():
                       "rounds": st["red_rounds"]},
     }
     line["copy_ceiling_GBs"] = copy_ceiling()
+    for name, cfg in (("image_1024", "C2"), ("image_64", "C1")):
+        r = bench_plain(torch.from_numpy(synth.config(cfg)).cuda())
+        gpu_digests[name] = r.pop("digest")
+        line[name] = r
+        print(f"{name}: {r['ms_median']:.2f} ms", file=sys.stderr, flush=True)
+    line["image_1024"]["workload"] = "2D 1024^2 float32 Gaussian field, sigma 4, seed 1; H0+H1, plain call"
+    line["image_64"]["workload"] = "2D 64^2 float32 U[0,1), seed 0; H0+H1, plain call (launch-bound)"
     if not args.no_forms:
         line["batched"] = bench_batched()
         line["fwd_bwd"] = bench_fwd_bwd()
         line["next"] = bench_next(x, d)
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(vol)
+    if child is not None:
+        line["cpu_baseline"] = cpu_baseline(child, gpu_digests)
     print(json.dumps(line), flush=True)
 
 
