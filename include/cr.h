@@ -127,12 +127,22 @@ void cr_diagram_free(cr_context* ctx, cr_diagram* d);
  *   pair_offsets  : device, n_images+1 int64: rows of image i are
  *                   [pair_offsets[i], pair_offsets[i+1]) in canonical order;
  *                   pair_offsets[n_images] is the total (also when it exceeds capacity).
- *   status        : device, n_images int32: 0, or CR_ERR_NAN_INPUT for an image with NaN.
- * Pixel indices index `packed`.  Never synchronises; when the device-side row
- * count exceeds capacity the rows beyond it are dropped and the total in
- * pair_offsets[n_images] tells the capacity needed.  Host-side argument errors
- * are returned directly.  Call cr_sync_status after the stream completes to
- * learn device-side failures (NaN, capacity, internal). */
+ *   status        : device, n_images int32, per image: 0 (its rows are complete),
+ *                   CR_ERR_NAN_INPUT (it holds NaN), CR_ERR_CAPACITY (its rows do
+ *                   not all fit below capacity), or, when the call stopped early
+ *                   for every image, CR_ERR_OUT_OF_MEMORY (the column arena of
+ *                   the degree-1 reduction ran out) or CR_ERR_INTERNAL.
+ * Pixel indices index `packed`.  Never synchronises and never stops short of a
+ * complete reduction: it enqueues a fixed budget of reduction rounds, then one
+ * workgroup that runs the rounds still needed, if any, to the end.  When the
+ * device-side row count exceeds capacity the rows beyond it are dropped and
+ * the total in pair_offsets[n_images] tells the capacity needed.  The column
+ * arena holds max(the context's arena, 16 entries per pixel) 64-bit entries;
+ * after cr_sync_status (or cr_graph_sync_status) has reported that it ran out,
+ * the context's arena is at least 4 times larger (CR_ARENA_ENTRIES fixes it).
+ * Host-side argument errors are returned directly.  Call cr_sync_status after
+ * the stream completes to learn device-side failures (NaN, capacity, arena,
+ * internal). */
 cr_status cr_persistence_batched(cr_context* ctx, int n_images, const float* packed, const int64_t* pixel_offsets,
                                  const int64_t* shapes, int ndim, int maxdim, uint32_t flags, void* stream,
                                  int32_t* dim, float* birth, float* death, int64_t* birth_pixel,

@@ -238,14 +238,17 @@ def pack(images: Sequence[torch.Tensor]):
 
 def persistence_batched(packed: torch.Tensor, shapes, pixel_offsets=None, maxdim: int | None = None,
                         capacity: int | None = None, out: BatchedDiagram | None = None,
-                        check: bool = True) -> BatchedDiagram:
+                        check: bool = True, _arena_retries: int = 3) -> BatchedDiagram:
     """Diagrams of many images (one ndim) packed in one buffer, in one pass.
 
     ``capacity`` rows are allocated (default: one per pixel).  With ``check``
     the call synchronises, raises on device-side errors and retries once with
-    the exact capacity if the rows did not fit.  With ``check=False`` and a
-    preallocated ``out`` the call neither allocates nor synchronises (it can be
-    captured in a HIP graph once the same shapes have been run before).
+    the exact capacity if the rows did not fit, and again (at most three times)
+    if the reduction's column arena ran out (the context's arena has grown by
+    then).  With ``check=False`` and a preallocated ``out`` the call neither
+    allocates nor synchronises (it can be captured in a HIP graph once the same
+    shapes have been run before); ``out.status`` then holds each image's
+    status once the stream has completed.
     """
     if packed.device.type != "cuda" or packed.dtype != torch.float32 or not packed.is_contiguous():
         raise TypeError("packed must be a contiguous float32 CUDA tensor")
@@ -286,9 +289,13 @@ def persistence_batched(packed: torch.Tensor, shapes, pixel_offsets=None, maxdim
     if not check:
         return out
     code = lib().cr_sync_status(h, stream)
+    if code == CR_ERR_OUT_OF_MEMORY and b"column-arena" in lib().cr_last_error() and _arena_retries > 0:
+        return persistence_batched(packed, shapes, pixel_offsets, maxdim, capacity=capacity, check=True,
+                                   _arena_retries=_arena_retries - 1)
     total = int(out.pair_offsets[-1])
     if total > cap:
-        return persistence_batched(packed, shapes, pixel_offsets, maxdim, capacity=total, check=True)
+        return persistence_batched(packed, shapes, pixel_offsets, maxdim, capacity=total, check=True,
+                                   _arena_retries=_arena_retries)
     _check(code)
     return BatchedDiagram(out.dim[:total], out.birth[:total], out.death[:total], out.birth_pixel[:total],
                           out.death_pixel[:total], out.pair_offsets, out.status)

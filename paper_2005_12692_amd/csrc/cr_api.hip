@@ -34,8 +34,8 @@ void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 void launch_gather(int grid, const uint64_t* cand, const unsigned long long* n_ptr, uint64_t cap,
                    const float* img, const ImgDesc* imgs, Layout L, int32_t* dim, float* birth, float* death,
                    int64_t* bpix, int64_t* dpix, hipStream_t s);
-void launch_img_offsets(const uint32_t* cnt, const uint32_t* img_status, int nimg, int64_t* offsets,
-                        int32_t* status, hipStream_t s);
+void launch_img_offsets(const uint32_t* cnt, const uint32_t* img_status, const Status* st, int64_t capacity,
+                        int nimg, int64_t* offsets, int32_t* status, hipStream_t s);
 void launch_backward(const int64_t* bpix, const int64_t* dpix, const float* gb, const float* gd, int64_t n,
                      float* grad, int64_t n_pixels, uint32_t* bad, hipStream_t s);
 void launch_check_empty(const unsigned long long* count, Status* st, hipStream_t s);
@@ -166,6 +166,14 @@ uint64_t batch_arena(const cr_context* ctx, const Problem& pb) {
   if (env) return env;
   const uint64_t have = ctx ? ctx->arena_entries : ARENA_DEFAULT;
   return std::max(have, std::min<uint64_t>(ARENA_MAX, ARENA_PER_PIXEL * pb.P));
+}
+
+// After a batched call (or graph replay) whose column arena of `cap` entries
+// overflowed, with `top` entries asked for before it stopped (a lower bound of
+// the need): the context's later batched calls and graphs get a larger arena.
+void grow_arena(cr_context* ctx, uint64_t cap, uint64_t top) {
+  const uint64_t want = std::max<uint64_t>(cap * 4, top * 2);
+  ctx->arena_entries = std::max<uint64_t>(ctx->arena_entries, std::min<uint64_t>(want, ARENA_MAX));
 }
 
 // Device address of noalloc_scratch on each device, looked up once per device
@@ -353,10 +361,12 @@ void mark(cr_context* ctx, int i, hipStream_t s) {
 
 // Rounds of the degree-1 reduction.  With host synchronisation allowed (plain
 // call) the host checks the active count every ROUND_BATCH rounds; otherwise a
-// fixed budget of rounds is enqueued (rounds with an empty list return at once)
-// and a leftover list raises the iteration flag.  Columns that yield (wave_yield)
-// take more rounds, so within the budget they yield only in the first
-// YIELD_ROUNDS rounds; the rest run every column to its end as without yields.
+// fixed budget of rounds is enqueued (rounds with an empty list return at once),
+// followed by one workgroup that runs whatever rounds remain to the end (the
+// finisher; it returns at once when the budget sufficed).  Columns that yield
+// (wave_yield) take more rounds, so within the budget they yield only in the
+// first YIELD_ROUNDS rounds; the rest run every column to its end as without
+// yields.
 constexpr int ROUND_BATCH = 4;
 constexpr int ROUND_BUDGET = 128;
 constexpr int YIELD_ROUNDS = 64;
@@ -371,8 +381,12 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
                      hipStream_t s, const std::function<cr_status()>& side_start = nullptr) {
   ctx->rounds = 0;
   if (!ctx->sync_allowed) {
-    launch_h1_rounds(RGRID, R, lists, counts, 0, ROUND_BUDGET, YIELD_ROUNDS, s);
-    launch_check_empty(counts + 2 * (ROUND_BUDGET % 3), R.st, s);
+    // CR_ROUND_BUDGET / CR_YIELD_ROUNDS override the budget (e.g. small, so that
+    // the finishing workgroup does most of the reduction of a small batch)
+    const int budget = (int)std::max<uint64_t>(1, std::min<uint64_t>(env_u64("CR_ROUND_BUDGET", ROUND_BUDGET), 1 << 16));
+    const int yields = (int)std::min<uint64_t>(env_u64("CR_YIELD_ROUNDS", YIELD_ROUNDS), (uint64_t)budget);
+    launch_h1_rounds(RGRID, R, lists, counts, 0, budget, yields, s);
+    launch_h1_finish(R, lists, counts, budget, s);  // the rounds beyond the budget, if any
     return CR_OK;
   }
   // Batches of rounds are enqueued one ahead of the check: the counts left by
@@ -712,8 +726,8 @@ cr_status enqueue_batch(cr_context* ctx, const BatchArgs& a, hipStream_t s, bool
   launch_gather(ctx->tune[grid_ndim(a.ndim)].grid, cand, at<unsigned long long>(ctx, p.counters) + C_CAND,
                 (uint64_t)a.capacity, a.packed, at<ImgDesc>(ctx, p.imgs), ctx->prob.L, a.dim, a.birth, a.death,
                 a.birth_pixel, a.death_pixel, s);
-  launch_img_offsets(at<uint32_t>(ctx, p.img_pairs), at<uint32_t>(ctx, p.img_status), a.n_images,
-                     a.pair_offsets, a.status, s);
+  launch_img_offsets(at<uint32_t>(ctx, p.img_pairs), at<uint32_t>(ctx, p.img_status), at<Status>(ctx, p.status),
+                     a.capacity, a.n_images, a.pair_offsets, a.status, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(CR_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return CR_OK;
@@ -992,7 +1006,9 @@ cr_status cr_sync_status(cr_context* ctx, void* stream) {
   ctx->scratch = own;
   if (rc != CR_OK) return rc;
   bool arena_over = false;
-  return status_error(h.st, &arena_over);
+  rc = status_error(h.st, &arena_over);
+  if (arena_over) grow_arena(ctx, ctx->plan.arena_cap, h.cnt[C_ARENA]);
+  return rc;
 }
 
 // The context's argument-check flag, cleared on stream s (allocated on first use).
@@ -1195,7 +1211,9 @@ cr_status cr_graph_sync_status(cr_graph* g, void* stream) {
   swap_state(ctx, g->own);
   if (rc != CR_OK) return rc;
   bool arena_over = false;
-  return status_error(h.st, &arena_over);
+  rc = status_error(h.st, &arena_over);
+  if (arena_over) grow_arena(ctx, g->own.plan.arena_cap, h.cnt[C_ARENA]);
+  return rc;
 }
 
 void cr_graph_destroy(cr_graph* g) {

@@ -70,6 +70,10 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
 // Columns yield after R.wave_yield additions only in rounds below yield_rounds.
 void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round0,
                       int nrounds, int yield_rounds, hipStream_t s);
+// One workgroup that runs the rounds from round0 on (lists and counts as
+// above) until a round has no columns: the end of a reduction enqueued with a
+// fixed budget of rounds.
+void launch_h1_finish(const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round0, hipStream_t s);
 void launch_h1_emit(int grid, const RedCtx& R, const EmitCtx& E, hipStream_t s);
 
 }  // namespace cr

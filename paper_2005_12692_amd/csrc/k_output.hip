@@ -40,9 +40,14 @@ __global__ void k_gather(const uint64_t* __restrict__ cand, const unsigned long 
 }
 
 // pair_offsets[0..nimg] = exclusive scan of the per-image row counts (one workgroup).
-// Also turns the per-image flags into the per-image status codes of the C ABI.
+// Also sets the per-image status codes of the C ABI: CR_ERR_NAN_INPUT for an
+// image with NaN; otherwise, when the call stopped early (scratch exhausted, an
+// iteration cap or a failed check), CR_ERR_OUT_OF_MEMORY or CR_ERR_INTERNAL for
+// every image (no image's rows are complete then); otherwise CR_ERR_CAPACITY
+// for an image whose rows do not all fit below `capacity`.
 __global__ __launch_bounds__(1024) void k_img_offsets(const uint32_t* __restrict__ cnt,
-                                                      const uint32_t* __restrict__ img_status, int nimg,
+                                                      const uint32_t* __restrict__ img_status,
+                                                      const Status* __restrict__ st, int64_t capacity, int nimg,
                                                       int64_t* __restrict__ offsets, int32_t* __restrict__ status) {
   __shared__ int64_t part[1024];
   const int tid = threadIdx.x;
@@ -59,10 +64,11 @@ __global__ __launch_bounds__(1024) void k_img_offsets(const uint32_t* __restrict
     __syncthreads();
   }
   int64_t run = part[tid] - s;
+  const int32_t stopped = st->abort ? (st->overflow ? 5 /* CR_ERR_OUT_OF_MEMORY */ : 7 /* CR_ERR_INTERNAL */) : 0;
   for (int i = lo; i < hi; ++i) {
     offsets[i] = run;
     run += cnt[i];
-    status[i] = img_status[i] ? 2 /* CR_ERR_NAN_INPUT */ : 0;
+    status[i] = img_status[i] ? 2 /* CR_ERR_NAN_INPUT */ : (stopped ? stopped : (run > capacity ? 4 /* CR_ERR_CAPACITY */ : 0));
   }
   if (tid == 1023) offsets[nimg] = part[1023];
 }
@@ -156,9 +162,9 @@ void launch_gather(int grid, const uint64_t* cand, const unsigned long long* n_p
   k_gather<<<grid, 256, 0, s>>>(cand, n_ptr, cap, img, imgs, L, dim, birth, death, bpix, dpix);
 }
 
-void launch_img_offsets(const uint32_t* cnt, const uint32_t* img_status, int nimg, int64_t* offsets,
-                        int32_t* status, hipStream_t s) {
-  k_img_offsets<<<1, 1024, 0, s>>>(cnt, img_status, nimg, offsets, status);
+void launch_img_offsets(const uint32_t* cnt, const uint32_t* img_status, const Status* st, int64_t capacity,
+                        int nimg, int64_t* offsets, int32_t* status, hipStream_t s) {
+  k_img_offsets<<<1, 1024, 0, s>>>(cnt, img_status, st, capacity, nimg, offsets, status);
 }
 
 void launch_backward(const int64_t* bpix, const int64_t* dpix, const float* gb, const float* gd, int64_t n,

@@ -934,6 +934,9 @@ __device__ __forceinline__ float rdlane_f(float v, uint32_t i) {
 template <class C>
 struct WaveOps {
   __device__ static bool leader(int lane) { return lane == 0; }
+  // the round of this launch and the additions after which a column yields
+  __device__ static uint32_t round(const RedCtx& R) { return cold(R)->round; }
+  __device__ static uint32_t wave_yield(const RedCtx& R) { return cold(R)->wave_yield; }
   __device__ static bool aborted(const RedCtx& R, const WaveBufs&) { return cr::aborted(cold(R)->st); }
   __device__ static uint64_t alloc(const RedCtx& R, const WaveBufs&, uint64_t n, int lane) { return w_alloc(R, n, lane); }
   __device__ static bool insert3(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t k0, uint64_t k1, uint64_t k2,
@@ -1006,7 +1009,7 @@ __device__ __forceinline__ void store_column(const RedCtx& R, const WaveBufs& S,
     K->col_ptr[c] = off;
     K->piv[c] = pv;
     if (claim_at) {
-      atomicMax(reinterpret_cast<unsigned long long*>(claim_at), claim_word(K->round, c));
+      atomicMax(reinterpret_cast<unsigned long long*>(claim_at), claim_word(O::round(R), c));
     } else {
       const unsigned long long i = atomicAdd(K->yield_count, 1ull);
       K->yield_list[i] = c;
@@ -1067,7 +1070,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
       tail_set(W.T, src, len, lane);
     }
   }
-  const uint32_t ylim = uni(cold(R)->wave_yield ? cold(R)->wave_yield : 0xFFFFFFFFu);
+  const uint32_t ylim = uni(O::wave_yield(R) ? O::wave_yield(R) : 0xFFFFFFFFu);
   uint64_t out_piv = YIELDED;   // what is stored when the loop ends: the pivot and its
   uint64_t* claim_at = nullptr;  // claim word, or YIELDED and none after wave_yield additions
   for (uint32_t it = 0;; ++it) {
@@ -1538,6 +1541,8 @@ __device__ __forceinline__ bool g_insert3(const RedCtx& R, const WaveBufs& S, WS
 // The leader's side of the column steps.
 struct GroupOps {
   __device__ static bool leader(int lane) { return lane == 0; }
+  __device__ static uint32_t round(const RedCtx& R) { return cold(R)->round; }
+  __device__ static uint32_t wave_yield(const RedCtx& R) { return cold(R)->wave_yield; }
   __device__ static bool aborted(const RedCtx& R, const WaveBufs&) { return cr::aborted(cold(R)->st); }
   __device__ static uint64_t alloc(const RedCtx& R, const WaveBufs&, uint64_t n, int lane) { return w_alloc(R, n, lane); }
   __device__ static bool insert3(const RedCtx& R, const WaveBufs& S, WState& W, uint64_t k0, uint64_t k1, uint64_t k2,
@@ -1632,6 +1637,50 @@ __device__ inline int64_t pivot_slot(const RedCtx& R, uint64_t e) {
   return edge_slot(d, ec);
 }
 
+// The commit of the listed columns [i0, nt + nb) with stride `stride` (whole
+// wavefronts): the leftmost proposer of each pivot in round `round` becomes its
+// owner; losers and displaced owners are appended to the next round's lists.
+__device__ inline void commit_range(const RedCtx& R, uint32_t round, const uint32_t* __restrict__ list_t, uint64_t nt,
+                                    const uint32_t* __restrict__ list_b, uint64_t nb, int first, uint64_t i0,
+                                    uint64_t stride, uint32_t* next_t, uint32_t* next_b,
+                                    unsigned long long* __restrict__ n_next) {
+  const uint64_t nr = (nt + nb + 63) & ~63ull;
+  for (uint64_t i = i0; i < nr; i += stride) {
+    bool again_short = false, again_long = false;
+    uint32_t again = 0;
+    if (i < nt + nb) {
+      uint32_t c;
+      bool skip = false;
+      if (i < nt) {
+        c = first ? (uint32_t)i : list_t[i];
+        skip = first && R.cleared[c];
+      } else {
+        c = list_b[i - nt];
+      }
+      const uint64_t e = skip ? YIELDED : R.piv[c];
+      if (e != YIELDED) {
+        const int64_t slot = pivot_slot(R, e);
+        bool push = true;
+        if (R.claim[slot] == claim_word(round, c)) {
+          const uint64_t old = R.owner[slot];
+          R.owner[slot] = ((uint64_t)c << 32) | R.col_ptr[c];
+          push = old != NO_OWNER;
+          again = (uint32_t)(old >> 32);
+        } else {
+          again = c;
+        }
+        if (push) {
+          const bool lng = R.arena[R.col_ptr[again]] > R.long_len;
+          again_long = lng;
+          again_short = !lng;
+        }
+      }
+    }
+    wave_push(next_t, n_next, again_short, again);
+    wave_push(next_b, n_next + 1, again_long, again);
+  }
+}
+
 // Commit: the leftmost proposer of each pivot becomes its owner; losers and
 // displaced owners go to the next round's lists (long stored columns to the
 // wave-mode list).  Yielded columns were already listed.
@@ -1650,41 +1699,90 @@ __global__ void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t, cons
   }
   const uint64_t nt = first ? R.dim_count[2] : *n_t;
   const uint64_t nb = first ? 0 : *n_b;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint64_t nr = (nt + nb + 63) & ~63ull;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nr; i += stride) {
-    bool again_short = false, again_long = false;
-    uint32_t again = 0;
-    if (i < nt + nb) {
-      uint32_t c;
-      bool skip = false;
-      if (i < nt) {
-        c = first ? (uint32_t)i : list_t[i];
-        skip = first && R.cleared[c];
-      } else {
-        c = list_b[i - nt];
-      }
-      const uint64_t e = skip ? YIELDED : R.piv[c];
-      if (e != YIELDED) {
-        const int64_t slot = pivot_slot(R, e);
-        bool push = true;
-        if (R.claim[slot] == claim_word(R.round, c)) {
-          const uint64_t old = R.owner[slot];
-          R.owner[slot] = ((uint64_t)c << 32) | R.col_ptr[c];
-          push = old != NO_OWNER;
-          again = (uint32_t)(old >> 32);
-        } else {
-          again = c;
-        }
-        if (push) {
-          const bool lng = R.arena[R.col_ptr[again]] > R.long_len;
-          again_long = lng;
-          again_short = !lng;
-        }
-      }
+  commit_range(R, R.round, list_t, nt, list_b, nb, first, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x,
+               (uint64_t)gridDim.x * blockDim.x, next_t, next_b, n_next);
+}
+
+// ---- the end of a batched reduction ------------------------------------------
+//
+// A batched call cannot ask the host how many rounds remain, so it enqueues a
+// fixed budget of rounds and then this kernel: one workgroup that runs the
+// rounds still needed (none, usually) to the end.  Each round it reduces every
+// listed column one wavefront at a time without yields (wave mode, wide
+// configuration), then commits them, until a round's lists are empty.  The
+// round number and the yield limit of the columns come from here instead of
+// the kernel arguments.
+constexpr uint32_t FINISH_ROUND_CAP = 4096;  // as the plain call's round limit
+constexpr uint32_t FINISH_FRONT_CAP = 2048;  // front list of the finisher (leaves LDS for its own words)
+__shared__ uint32_t fin_round_lds;
+__shared__ unsigned long long fin_work_lds;
+
+template <class C>
+struct FinishOps : WaveOps<C> {
+  __device__ static uint32_t round(const RedCtx&) { return fin_round_lds; }
+  __device__ static uint32_t wave_yield(const RedCtx&) { return 0u; }
+};
+
+// R must stay the first parameter (see cold()).
+template <class C>
+__global__ __launch_bounds__(64 * WPB) void k_red_finish(RedCtx R, uint32_t* __restrict__ l0, uint32_t* __restrict__ l1,
+                                                        uint32_t* __restrict__ l2, uint32_t* __restrict__ l3,
+                                                        unsigned long long* __restrict__ counts, uint32_t round0,
+                                                        uint32_t front_cap) {
+  extern __shared__ __align__(16) uint64_t lds_words[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint64_t* base = lds_words + (size_t)wv * wave_lds_words<C>(front_cap);
+  WaveBufs S;
+  S.cap = front_cap;
+  S.F0 = base;
+  S.F1 = base + S.cap;
+  S.X = base + 2 * (size_t)S.cap;
+  S.ps = S.X + C::XN;
+  S.hx = S.X;
+  S.po = nullptr;
+  const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
+  WState W;
+  W.adds = 0;
+  W.merged = 0;
+  for (uint32_t r = round0;; ++r) {
+    __syncthreads();
+    unsigned long long* ct = counts + 2 * (r % 3);
+    unsigned long long* cnx = counts + 2 * ((r + 1) % 3);
+    unsigned long long* cclr = counts + 2 * ((r + 2) % 3);
+    const uint64_t nt = uni64(__hip_atomic_load(ct, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint64_t nb = uni64(__hip_atomic_load(ct + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (nt + nb == 0 || aborted(R.st)) break;
+    if (r - round0 >= FINISH_ROUND_CAP) {
+      if (threadIdx.x == 0) raise_flag(R.st, &R.st->iter_cap);
+      break;
     }
-    wave_push(next_t, n_next, again_short, again);
-    wave_push(next_b, n_next + 1, again_long, again);
+    __syncthreads();  // every thread has read the counts before they are cleared below
+    if (threadIdx.x == 0) {
+      fin_round_lds = r;
+      fin_work_lds = 0;
+      cclr[0] = 0;  // the pair the round after next fills
+      cclr[1] = 0;
+    }
+    __syncthreads();
+    const uint32_t* lt = (r & 1) ? l2 : l0;
+    const uint32_t* lb = (r & 1) ? l3 : l1;
+    for (;;) {
+      unsigned long long li = 0;
+      if (lane == 0) li = atomicAdd(&fin_work_lds, 1ull);
+      li = rdlane64(li, 0);
+      if (li >= nt + nb || aborted(R.st)) break;
+      const uint32_t c = uni(li < nb ? lb[li] : lt[li - nb]);
+      reduce_column<FinishOps<C>>(R, S, W, c, off2, lane);
+      wsync();
+    }
+    __threadfence();
+    __syncthreads();
+    commit_range(R, r, lt, nt, lb, nb, 0, threadIdx.x, blockDim.x, (r & 1) ? l0 : l2, (r & 1) ? l1 : l3, cnx);
+    __threadfence();
+  }
+  if (lane == 0 && W.adds) {
+    atomicAdd(&R.st->adds, W.adds);
+    atomicAdd(&R.st->merged, W.merged);
   }
 }
 
@@ -1803,6 +1901,20 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
     }
     k_red_commit<<<grid, 256, 0, s>>>(Rr, lt, ct, lb, ct + 1, first, lists[2 * nxt], lists[2 * nxt + 1], cnx, cclr);
   }
+}
+
+void launch_h1_finish(const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round0, hipStream_t s) {
+  // the column state lives in the arena between rounds, so the finisher's front
+  // capacity need not be the wave kernels'
+  const uint32_t fcap = R.front_cap < FINISH_FRONT_CAP ? R.front_cap : FINISH_FRONT_CAP;
+  const size_t lds = WPB * 8 * wave_lds_words<WideCfg>(fcap);
+  static size_t lds_set = 0;
+  if (lds_set < lds) {
+    (void)hipFuncSetAttribute((const void*)k_red_finish<WideCfg>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    lds_set = lds;
+  }
+  k_red_finish<WideCfg><<<1, 64 * WPB, lds, s>>>(R, lists[0], lists[1], lists[2], lists[3], counts, (uint32_t)round0,
+                                                 fcap);
 }
 
 void launch_h1_emit(int grid, const RedCtx& R, const EmitCtx& E, hipStream_t s) {

@@ -174,6 +174,23 @@ def test_masked_volume_256():
     check_against_oracle(vol, rows, dg.get("C3_masked"), m, "256^3 blobs, +inf outside the ball")
 
 
+def test_batch_of_two_256_volumes():
+    """Two 256^3 volumes in one batched call (the blobs volume and the same
+    volume masked to the ball): each image's rows against the oracle's stored
+    digest of that volume."""
+    m, dg = _digests()
+    vols = [synth.config("C3"), m.masked_c3()]
+    packed, shapes, offs = cr.pack([torch.from_numpy(v).cuda() for v in vols])
+    d = cr.persistence_batched(packed, shapes, offs)
+    assert (d.status.cpu() == 0).all()
+    po = d.pair_offsets.cpu().numpy()
+    for i, (v, key) in enumerate(zip(vols, ("C3", "C3_masked"))):
+        rows = [t[po[i]:po[i + 1]].cpu().numpy() for t in (d.dim, d.birth, d.death, d.birth_pixel, d.death_pixel)]
+        rows = local_rows(rows, offs[i])
+        _invariants(v, rows)
+        check_against_oracle(v, rows, dg.get(key), m, f"batched 256^3 volume {i}")
+
+
 def test_signal_2_24():
     m, dg = _digests()
     sig = m.walk_2_24()
