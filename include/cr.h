@@ -250,6 +250,7 @@ typedef struct cr_stats {
   int64_t red_rounds;   /* rounds of the degree-1 reduction (plain call) */
   int64_t arena_reruns; /* plain calls on this context that reran with a larger column arena */
   int64_t scratch_bytes; /* device scratch the context owns now (0 until a call needs it) */
+  int64_t tuning_from_cache; /* 1 if the last batched call ran with a CR_TUNE_CACHE entry */
 } cr_stats;
 cr_status cr_get_stats(cr_context* ctx, cr_stats* out);
 
@@ -282,11 +283,24 @@ typedef struct cr_tuning {
                            so that the rounds stay short and the columns of different images
                            (or regions) do not wait for one long column; 0 = never.  In a
                            batched call it applies to the first 64 rounds only. */
+  int32_t group_max;    /* ... a round of at most this many long columns runs one workgroup
+                           per column; 0 = automatic (256 for a call of 8 or more volumes,
+                           else 1024) */
+  int32_t narrow_min;   /* ... a round of at least this many long columns runs the narrow
+                           wavefront configuration; 0 = automatic (2048 for a call of 8 or
+                           more volumes, else 8192) */
 } cr_tuning;
 
 /* The parameters the context uses for ndim (1, 2 or 3; 1D signals share the
  * 2D setting), and a validated setter (INVALID_ARGUMENT for a value out of
- * range). */
+ * range).
+ *
+ * Tuning cache: when the environment variable CR_TUNE_CACHE names a file, the
+ * autotuner records its choice there (a JSON object, one entry per key
+ * "<gcn arch>/nd<ndim>/md<maxdim>/img<log2 images>/px<log2 pixels>", the
+ * exponents rounded up), and a batched call or graph of a context on which
+ * cr_set_tuning was not called for that ndim uses the entry of its key when
+ * there is one (the file is read once per context). */
 cr_status cr_get_tuning(cr_context* ctx, int ndim, cr_tuning* out);
 cr_status cr_set_tuning(cr_context* ctx, int ndim, const cr_tuning* t);
 

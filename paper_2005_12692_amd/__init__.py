@@ -46,13 +46,13 @@ class _Stats(ctypes.Structure):
                 ("arena_used", ctypes.c_int64), ("red_adds", ctypes.c_int64),
                 ("red_merged", ctypes.c_int64),
                 ("red_rounds", ctypes.c_int64), ("arena_reruns", ctypes.c_int64),
-                ("scratch_bytes", ctypes.c_int64)]
+                ("scratch_bytes", ctypes.c_int64), ("tuning_from_cache", ctypes.c_int64)]
 
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("grid", ctypes.c_int32), ("long_len", ctypes.c_int32),
                 ("yield_iters", ctypes.c_int32), ("wave_short", ctypes.c_int32), ("front_cap", ctypes.c_int32),
-                ("wave_yield", ctypes.c_int32)]
+                ("wave_yield", ctypes.c_int32), ("group_max", ctypes.c_int32), ("narrow_min", ctypes.c_int32)]
 
 
 TUNING_FIELDS = tuple(f for f, _ in _Tuning._fields_)
@@ -585,4 +585,5 @@ def stats(device=None) -> dict:
     return {"n_pixels": s.n_pixels, "n_cells": s.n_cells, "survivors": list(s.survivors),
             "n_rows": s.n_rows, "arena_used": s.arena_used, "red_adds": s.red_adds,
             "red_merged": s.red_merged, "red_rounds": s.red_rounds,
-            "arena_reruns": s.arena_reruns, "scratch_bytes": s.scratch_bytes}
+            "arena_reruns": s.arena_reruns, "scratch_bytes": s.scratch_bytes,
+            "tuning_from_cache": s.tuning_from_cache}

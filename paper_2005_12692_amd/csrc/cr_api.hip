@@ -6,8 +6,12 @@
 #include <cstring>
 #include <algorithm>
 #include <cstdlib>
+#include <cstdio>
+#include <fstream>
 #include <functional>
+#include <map>
 #include <mutex>
+#include <sstream>
 
 #include "cr.h"
 #include "cr_reduce.h"
@@ -97,6 +101,8 @@ cr_tuning default_tuning(int ndim) {
   t.wave_short = 4096;
   t.front_cap = 1024;
   t.wave_yield = 128;
+  t.group_max = 0;   // automatic (by the number of images)
+  t.narrow_min = 0;
   (void)ndim;
   return t;
 }
@@ -151,6 +157,11 @@ struct cr_context {
   bool timing = false;
   float stage_ms[6] = {};
   cr_tuning tune[4] = {};        // launch parameters per ndim (2, 3)
+  bool tune_set[4] = {};         // cr_set_tuning was called for this ndim (the tuning cache is not used)
+  bool in_autotune = false;      // the autotuner's own calls (the tuning cache is not used)
+  bool cache_loaded = false;     // CR_TUNE_CACHE has been read
+  std::map<std::string, cr_tuning> cache;  // its entries
+  std::string arch;              // gcn arch name of the device (tuning cache key)
 };
 
 namespace {
@@ -572,13 +583,13 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     R.front_cap = (uint32_t)tu.front_cap;
     R.wave_yield = (uint32_t)tu.wave_yield;
     // a batch's rounds hold the columns of many volumes: a workgroup per column
-    // pays off only in rounds of at most 256 of them, and the narrow wavefront
-    // configuration already from 2048 (32 x 128^3: 55 -> 49.5 ms; a single
-    // 256^3 volume is fastest with 1024 and 8192)
-    if (pb.nimg >= 8) {
-      R.group_max = 256;
-      R.narrow_min = 2048;
-    }
+    // pays off only in rounds of few of them, and the narrow wavefront
+    // configuration already from fewer columns than for one volume (automatic
+    // values; measured on 32 x 128^3 forward+backward: 56.6 -> 50.4 ms with 256
+    // and 2048; a single 256^3 volume is fastest with 1024 and 8192)
+    const bool many = pb.nimg >= 8;
+    R.group_max = tu.group_max ? (uint32_t)tu.group_max : (many ? 256u : 1024u);
+    R.narrow_min = tu.narrow_min ? (uint32_t)tu.narrow_min : (many ? 2048u : 8192u);
     // thresholds between thread and wave mode and the wave-mode front capacity
     // (CR_LONG_LEN / CR_YIELD_ITERS / CR_WAVE_SHORT / CR_FRONT_CAP override them,
     // e.g. to exercise wave mode and its tail merges on small inputs)
@@ -737,12 +748,128 @@ cr_status check_tuning(int ndim, const cr_tuning& t) {
   int ext[3];
   if (!stencil_tile(ndim, t.tile, ext)) return fail(CR_ERR_INVALID_ARGUMENT, "tile variant out of range");
   if (t.grid < 64 || t.grid > 65536) return fail(CR_ERR_INVALID_ARGUMENT, "grid must be in [64, 65536]");
-  if (t.long_len < 0 || t.yield_iters < 1 || t.wave_short < 0 || t.wave_yield < 0)
+  if (t.long_len < 0 || t.yield_iters < 1 || t.wave_short < 0 || t.wave_yield < 0 || t.group_max < 0 ||
+      t.narrow_min < 0)
     return fail(CR_ERR_INVALID_ARGUMENT, "reduction thresholds out of range");
   if (t.front_cap < (int)FRONT_CAP_MIN || t.front_cap > (int)FRONT_CAP_MAX)
     return fail(CR_ERR_INVALID_ARGUMENT, "front_cap out of range");
   return CR_OK;
 }
+
+// ---- tuning cache (CR_TUNE_CACHE) --------------------------------------------
+constexpr int TUNE_FIELDS = 9;
+void tuning_to_array(const cr_tuning& t, int32_t a[TUNE_FIELDS]) {
+  const int32_t v[TUNE_FIELDS] = {t.tile, t.grid, t.long_len, t.yield_iters, t.wave_short, t.front_cap,
+                                  t.wave_yield, t.group_max, t.narrow_min};
+  for (int i = 0; i < TUNE_FIELDS; ++i) a[i] = v[i];
+}
+cr_tuning tuning_from_array(const int32_t a[TUNE_FIELDS]) {
+  cr_tuning t;
+  t.tile = a[0]; t.grid = a[1]; t.long_len = a[2]; t.yield_iters = a[3]; t.wave_short = a[4];
+  t.front_cap = a[5]; t.wave_yield = a[6]; t.group_max = a[7]; t.narrow_min = a[8];
+  return t;
+}
+int ceil_log2(uint64_t x) {
+  int b = 0;
+  while (b < 63 && (1ull << b) < x) ++b;
+  return b;
+}
+
+// Key of a batched call: device arch, ndim, maxdim (clamped), and the image
+// and pixel counts rounded up to powers of two.
+std::string cache_key(const cr_context* ctx, int n_images, const int64_t* shapes, int ndim, int maxdim) {
+  uint64_t P = 0;
+  for (int i = 0; i < n_images; ++i) {
+    uint64_t p = 1;
+    for (int a = 0; a < ndim; ++a) p *= (uint64_t)std::max<int64_t>(1, shapes[(int64_t)i * ndim + a]);
+    P += p;
+  }
+  std::ostringstream k;
+  k << ctx->arch << "/nd" << ndim << "/md" << std::min(maxdim, ndim - 1) << "/img" << ceil_log2((uint64_t)n_images)
+    << "/px" << ceil_log2(P);
+  return k.str();
+}
+
+// Reads the cache file: a JSON object of "key": [9 integers] entries.
+void cache_load(cr_context* ctx) {
+  if (ctx->cache_loaded) return;
+  ctx->cache_loaded = true;
+  const char* path = getenv("CR_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ifstream f(path);
+  if (!f) return;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string text = ss.str();
+  size_t i = 0;
+  while ((i = text.find('"', i)) != std::string::npos) {
+    const size_t j = text.find('"', i + 1);
+    if (j == std::string::npos) break;
+    const std::string key = text.substr(i + 1, j - i - 1);
+    const size_t lb = text.find('[', j), rb = text.find(']', j);
+    if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
+    int32_t a[TUNE_FIELDS];
+    int n = 0;
+    std::istringstream nums(text.substr(lb + 1, rb - lb - 1));
+    std::string tok;
+    while (n < TUNE_FIELDS && std::getline(nums, tok, ',')) a[n++] = (int32_t)strtol(tok.c_str(), nullptr, 10);
+    if (n == TUNE_FIELDS) ctx->cache[key] = tuning_from_array(a);
+    i = rb + 1;
+  }
+}
+
+// Writes the cache (all entries this context knows) to CR_TUNE_CACHE, through
+// a temporary file renamed over it.
+void cache_store(cr_context* ctx) {
+  const char* path = getenv("CR_TUNE_CACHE");
+  if (!path || !*path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t k = 0;
+  for (const auto& e : ctx->cache) {
+    int32_t a[TUNE_FIELDS];
+    tuning_to_array(e.second, a);
+    fprintf(f, "  \"%s\": [%d, %d, %d, %d, %d, %d, %d, %d, %d]%s\n", e.first.c_str(), a[0], a[1], a[2], a[3], a[4],
+            a[5], a[6], a[7], a[8], ++k < ctx->cache.size() ? "," : "");
+  }
+  fprintf(f, "}\n");
+  if (fclose(f) == 0) (void)rename(tmp.c_str(), path);
+}
+
+// For the duration of one batched call: the cached tuning of its key, when the
+// context has one and the caller has not set the tuning for this ndim.
+struct CachedTuning {
+  cr_context* ctx = nullptr;
+  int nd = 0;
+  cr_tuning saved{};
+  bool swapped = false;
+  CachedTuning(cr_context* c, int n_images, const int64_t* shapes, int ndim, int maxdim) : ctx(c) {
+    if (!c || !shapes || n_images < 1 || ndim < 1 || ndim > 3 || maxdim < 0) return;
+    nd = grid_ndim(ndim);
+    c->stats.tuning_from_cache = 0;
+    if (c->tune_set[nd] || c->in_autotune || !getenv("CR_TUNE_CACHE")) return;
+    cache_load(c);
+    const auto it = c->cache.find(cache_key(c, n_images, shapes, ndim, maxdim));
+    if (it == c->cache.end() || check_tuning_quiet(nd, it->second)) return;
+    saved = c->tune[nd];
+    c->tune[nd] = it->second;
+    swapped = true;
+    c->stats.tuning_from_cache = 1;
+  }
+  ~CachedTuning() {
+    if (swapped) ctx->tune[nd] = saved;
+  }
+  // true if t is out of range (a stale or edited cache entry is ignored)
+  static bool check_tuning_quiet(int nd, const cr_tuning& t) {
+    const std::string keep = g_err;
+    const bool bad = check_tuning(nd, t) != CR_OK;
+    g_err = keep;
+    return bad;
+  }
+};
+
 
 // Scratch, problem and plan of a context, swapped in and out around work on a
 // graph's own scratch.
@@ -792,6 +919,16 @@ cr_status cr_create(cr_context** out, int device, cr_alloc_fn alloc, cr_free_fn 
     }
   }
   for (int d = 0; d < 4; ++d) c->tune[d] = default_tuning(d);
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+      c->arch = prop.gcnArchName;
+      c->arch = c->arch.substr(0, c->arch.find(':'));
+    } else {
+      (void)hipGetLastError();
+      c->arch = "unknown";
+    }
+  }
   c->alloc = alloc;
   c->free_fn = free_fn;
   c->user = user;
@@ -922,6 +1059,7 @@ cr_status cr_batched_workspace_size(cr_context* ctx, int n_images, const int64_t
   *bytes = 0;
   if (ndim < 1 || ndim > 3) return fail(CR_ERR_INVALID_ARGUMENT, "ndim must be 1, 2 or 3");
   Problem pb;
+  const CachedTuning cached(ctx, n_images, shapes, ndim, maxdim);
   const int tile = ctx ? ctx->tune[grid_ndim(ndim)].tile : default_tuning(grid_ndim(ndim)).tile;
   cr_status rc = build_problem(pb, n_images, nullptr, shapes, ndim, maxdim, tile);
   if (rc != CR_OK) return rc;
@@ -946,6 +1084,7 @@ cr_status cr_persistence_batched(cr_context* ctx, int n_images, const float* pac
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   ctx->last_batched_valid = false;
+  const CachedTuning cached(ctx, n_images, shapes, ndim, maxdim);
   rc = build_problem(ctx->prob, n_images, pixel_offsets, shapes, ndim, maxdim, ctx->tune[grid_ndim(ndim)].tile);
   if (rc != CR_OK) return rc;
   ctx->plan = make_plan(ctx->prob, batch_arena(ctx, ctx->prob));
@@ -971,6 +1110,7 @@ cr_status cr_persistence_batched_noalloc(cr_context* ctx, int n_images, const fl
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   ctx->last_batched_valid = false;
+  const CachedTuning cached(ctx, n_images, shapes, ndim, maxdim);
   rc = build_problem(ctx->prob, n_images, pixel_offsets, shapes, ndim, maxdim, ctx->tune[grid_ndim(ndim)].tile);
   if (rc != CR_OK) return rc;
   const Plan plan = make_plan(ctx->prob, noalloc_arena(ctx->prob));
@@ -1123,6 +1263,7 @@ cr_status cr_set_tuning(cr_context* ctx, int ndim, const cr_tuning* t) {
   cr_status rc = check_tuning(ndim, *t);
   if (rc != CR_OK) return rc;
   ctx->tune[ndim] = *t;
+  ctx->tune_set[ndim] = true;
   return CR_OK;
 }
 
@@ -1153,6 +1294,7 @@ cr_status cr_batched_graph_create(cr_context* ctx, int n_images, const float* pa
   cr_graph* g = new (std::nothrow) cr_graph();
   if (!g) return fail(CR_ERR_OUT_OF_MEMORY, "graph allocation failed");
   g->ctx = ctx;
+  const CachedTuning cached(ctx, n_images, shapes, ndim, maxdim);
   rc = build_problem(g->own.prob, n_images, pixel_offsets, shapes, ndim, maxdim, ctx->tune[grid_ndim(ndim)].tile);
   if (rc != CR_OK) {
     delete g;
@@ -1244,6 +1386,11 @@ cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed
   HIP_TRY(hipEventCreate(&e1));
   const int nd = grid_ndim(ndim);
   const cr_tuning start = ctx->tune[nd];
+  struct InTune {  // the candidates' own calls do not consult the tuning cache
+    cr_context* c;
+    ~InTune() { c->in_autotune = false; }
+  } in_tune{ctx};
+  ctx->in_autotune = true;
   // time one candidate: a warm-up call, then `repeats` timed calls
   auto time_it = [&](const cr_tuning& t, float* ms) -> cr_status {
     ctx->tune[nd] = t;
@@ -1267,7 +1414,7 @@ cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed
   rc = time_it(best, &best_ms);
   // coordinate descent: one parameter at a time, in the order they matter
   const bool red = ndim == 3 && maxdim >= 1;
-  for (int coord = 0; rc == CR_OK && coord < (red ? 7 : 2); ++coord) {
+  for (int coord = 0; rc == CR_OK && coord < (red ? 9 : 2); ++coord) {
     std::vector<int> vals;
     if (coord == 0) for (int v = 0; v < N_TILE_VARIANTS; ++v) vals.push_back(v);
     if (coord == 1) vals = {512, 1024, 2048, 4096, 8192};
@@ -1276,11 +1423,13 @@ cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed
     if (coord == 4) vals = {0, 4096, 65536, 1 << 30};
     if (coord == 5) vals = {16, 128, 1024};
     if (coord == 6) vals = {0, 64, 128, 512};
+    if (coord == 7) vals = {0, 128, 256, 1024};
+    if (coord == 8) vals = {0, 2048, 8192};
     for (int v : vals) {
       cr_tuning t = best;
       int* field = coord == 0 ? &t.tile : coord == 1 ? &t.grid : coord == 2 ? &t.front_cap
                  : coord == 3 ? &t.long_len : coord == 4 ? &t.wave_short : coord == 5 ? &t.yield_iters
-                 : &t.wave_yield;
+                 : coord == 6 ? &t.wave_yield : coord == 7 ? &t.group_max : &t.narrow_min;
       if (*field == v) continue;
       *field = v;
       float ms = 0.0f;
@@ -1296,6 +1445,11 @@ cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed
   (void)hipEventDestroy(e1);
   ctx->tune[nd] = rc == CR_OK ? best : start;
   if (rc == CR_OK && chosen) *chosen = best;
+  if (rc == CR_OK && getenv("CR_TUNE_CACHE")) {  // record the choice for this key
+    cache_load(ctx);
+    ctx->cache[cache_key(ctx, n_images, shapes, ndim, maxdim)] = best;
+    cache_store(ctx);
+  }
   return rc;
 }
 

@@ -4,7 +4,9 @@ autotuner, through the C ABI.
 Every launch parameter changes speed only, so every setting must give the
 same bytes as the default; a graph replay must give the bytes of the eager
 batched call, on every replay, with eager work between replays, and after the
-input buffer is refilled with other values of the same shapes.
+input buffer is refilled with other values of the same shapes.  The tuning
+cache (CR_TUNE_CACHE) records the autotuner's choice and serves it to a fresh
+context's call of the same key only.
 """
 import numpy as np
 import pytest
@@ -120,3 +122,73 @@ def test_autotune_keeps_results(ndim):
         same_batch(host(cr.persistence_batched(packed, shapes, offs)), want, f"after autotune {chosen}")
     finally:
         cr.set_tuning(ndim, **default)
+
+
+def _fresh_context():
+    import ctypes
+    h = ctypes.c_void_p()
+    assert cr.lib().cr_create(ctypes.byref(h), torch.cuda.current_device(), cr._ALLOC_FN(0), cr._FREE_FN(0),
+                              None) == cr.CR_OK
+    return h
+
+
+def _batched_on(h, packed, shapes, offs, maxdim):
+    import ctypes
+    ndim = len(shapes[0])
+    flat = [e for s in shapes for e in s]
+    out = cr._empty_out(int(offs[-1]), len(shapes), packed.device)
+    rc = cr.lib().cr_persistence_batched(h, len(shapes), ctypes.c_void_p(packed.data_ptr()),
+                                         (ctypes.c_int64 * len(offs))(*offs), (ctypes.c_int64 * len(flat))(*flat),
+                                         ndim, maxdim, 0, cr._stream(packed.device), *cr._out_args(out))
+    assert rc == cr.CR_OK, cr.lib().cr_last_error()
+    assert cr.lib().cr_sync_status(h, cr._stream(packed.device)) == cr.CR_OK
+    st = cr._Stats()
+    assert cr.lib().cr_get_stats(h, ctypes.byref(st)) == cr.CR_OK
+    n = int(out.pair_offsets[-1])
+    return [getattr(out, f)[:n].cpu().numpy() for f in FIELDS] + [out.pair_offsets.cpu().numpy()], st
+
+
+def test_tune_cache_round_trip(tmp_path, monkeypatch):
+    """CR_TUNE_CACHE: the autotuner records its choice under the call's key, a
+    fresh context's batched call of the same key runs with it (same bytes), a
+    call of another key or after cr_set_tuning does not."""
+    import ctypes
+    import json
+    import math
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("CR_TUNE_CACHE", str(path))
+    imgs = images_2d()
+    packed, shapes, offs = cr.pack([torch.from_numpy(i).cuda() for i in imgs])
+    want = host(cr.persistence_batched(packed, shapes, offs))
+    h = _fresh_context()
+    try:
+        out = cr._empty_out(int(offs[-1]), len(imgs), packed.device)
+        flat = [e for s in shapes for e in s]
+        t = cr._Tuning()
+        rc = cr.lib().cr_autotune_batched(h, len(imgs), ctypes.c_void_p(packed.data_ptr()),
+                                          (ctypes.c_int64 * len(offs))(*offs), (ctypes.c_int64 * len(flat))(*flat),
+                                          2, 1, cr._stream(packed.device), *cr._out_args(out), 1, ctypes.byref(t))
+        assert rc == cr.CR_OK, cr.lib().cr_last_error()
+    finally:
+        cr.lib().cr_destroy(h)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = f"{arch}/nd2/md1/img{math.ceil(math.log2(len(imgs)))}/px{math.ceil(math.log2(int(offs[-1])))}"
+    entries = json.loads(path.read_text())
+    assert entries[key] == [int(getattr(t, f)) for f in cr.TUNING_FIELDS]
+    h = _fresh_context()
+    try:
+        got, st = _batched_on(h, packed, shapes, offs, 1)
+        assert st.tuning_from_cache == 1
+        same_batch(got, want, "with the cached tuning")
+        small = [i[:5, :6].copy() for i in imgs[:2]]
+        p2, s2, o2 = cr.pack([torch.from_numpy(i).cuda() for i in small])
+        _, st = _batched_on(h, p2, s2, o2, 1)
+        assert st.tuning_from_cache == 0, "another key used the entry"
+        cur = cr._Tuning()
+        assert cr.lib().cr_get_tuning(h, 2, ctypes.byref(cur)) == cr.CR_OK
+        assert cr.lib().cr_set_tuning(h, 2, ctypes.byref(cur)) == cr.CR_OK
+        got, st = _batched_on(h, packed, shapes, offs, 1)
+        assert st.tuning_from_cache == 0, "the cache overrode cr_set_tuning"
+        same_batch(got, want, "after cr_set_tuning")
+    finally:
+        cr.lib().cr_destroy(h)
