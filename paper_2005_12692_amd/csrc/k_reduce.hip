@@ -117,6 +117,16 @@ __device__ inline void wave_push(uint32_t* list, unsigned long long* n, bool act
 template <typename T>
 __device__ __forceinline__ T sel3(int i, T a, T b, T c) { return i == 0 ? a : (i == 1 ? b : c); }
 
+// x / d for x < 2^30 and 1 <= d < 2^22, with rd = 1.0 / d: the product in
+// double precision is within 2^-22 of x / d, so its integer part is the
+// quotient or one below it (only when x / d is an integer); one remainder
+// check corrects that.  Cheaper than a 32-bit integer division.
+__device__ __forceinline__ uint32_t udiv_rcp(uint32_t x, uint32_t d, double rd) {
+  uint32_t q = (uint32_t)((double)x * rd);
+  if (x - q * d >= d) ++q;
+  return q;
+}
+
 __device__ __forceinline__ uint32_t ord_of(float v) {
   uint32_t bits;
   __builtin_memcpy(&bits, &v, 4);
@@ -198,6 +208,7 @@ __device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64
   const uint32_t K1 = (uint32_t)d.K[1], K2 = (uint32_t)d.K[2];
   const int64_t ps0 = (int64_t)d.n[1] * d.n[2], ps1 = d.n[2];
   const uint32_t ks0 = K1 * K2, ks1 = K2;
+  const double rK1 = 1.0 / (double)K1, rK2 = 1.0 / (double)K2;
   RegCol<TC> C;
 #pragma unroll
   for (int i = 0; i < TC; ++i) C.w[i] = 0;
@@ -261,8 +272,8 @@ __device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64
     }
     const uint64_t e = C.w[0];
     const uint32_t kidx = skey_kidx(R.L, e);
-    const uint32_t kx = kidx % K2, t1 = kidx / K2;
-    const uint32_t ky = t1 % K1, kz = t1 / K1;
+    const uint32_t t1 = udiv_rcp(kidx, K2, rK2), kx = kidx - t1 * K2;
+    const uint32_t kz = udiv_rcp(t1, K1, rK1), ky = t1 - kz * K1;
     if ((e >> (R.L.ib + 32 + R.L.kb)) != 1 || skey_img(R.L, e) != im || kz >= (uint32_t)d.K[0] ||
         ((kz & 1) + (ky & 1) + (kx & 1)) != 1) {
       raise_flag(R.st, &R.st->internal);
@@ -496,6 +507,24 @@ __device__ __forceinline__ void p_load(WState& W, const uint64_t* src, uint32_t 
 // LDS slot ps, with no branches on the data.
 __device__ __forceinline__ void p_insert3(const WaveBufs& S, WState& W, uint64_t k0, uint64_t k1, uint64_t k2,
                                           int lane) {
+  {
+    // The common case: the three keys (the rest of the boundary of the square
+    // paired with the pivot just removed) all lie above P's top.  They cannot
+    // be in P, so they go on top in ascending order, with no exchange through
+    // LDS.  Slots beyond np are never read.
+    uint64_t a = k0, b = k1, c = k2;
+    if (a > b) { const uint64_t t = a; a = b; b = t; }
+    if (b > c) { const uint64_t t = b; b = c; c = t; }
+    if (a > b) { const uint64_t t = a; a = b; b = t; }
+    const uint32_t n = W.np;
+    if (a > p_top(W) && n + 3 <= PCAP) {
+      const uint32_t l0 = (uint32_t)lane, l1 = (uint32_t)lane + 64;
+      W.p0 = l0 == n ? a : (l0 == n + 1 ? b : (l0 == n + 2 ? c : W.p0));
+      W.p1 = l1 == n ? a : (l1 == n + 1 ? b : (l1 == n + 2 ? c : W.p1));
+      W.np = n + 3;
+      return;
+    }
+  }
   const bool in0 = (uint32_t)lane < W.np, in1 = (uint32_t)lane + 64 < W.np;
   const bool h0 = (wballot(in0 && W.p0 == k0) | wballot(in1 && W.p1 == k0)) != 0;
   const bool h1 = (wballot(in0 && W.p0 == k1) | wballot(in1 && W.p1 == k1)) != 0;
@@ -974,6 +1003,54 @@ struct WaveOps {
   }
 };
 
+// The geometry of one image that the load group of an edge needs.
+struct EdgeGeom {
+  int kb;                              // bits of the key's index field
+  uint32_t K0, K1, K2;                 // Khalimsky extents z, y, x
+  double rK1, rK2;                     // their reciprocals
+  uint32_t n0, n1, n2, ps0, ps1;       // pixel extents and strides
+  const float* img;                    // the image's pixels
+  const uint8_t* eapp;                 // its edges' apparent codes
+  const uint64_t* owner;               // its edges' owner words
+};
+// What a lane loads for edge e in role r (the value only once it is used):
+// roles 0 and 1 the edge's endpoints, 2..9 the far vertices of the four
+// squares around it (role 2 + 4h + 2s + o: the other axis h, side s, endpoint
+// o; other roles and vertices off the image read the anchor); every role the
+// edge's apparent code and owner word.
+struct LoadGroup {
+  float praw;
+  uint32_t code;
+  uint64_t ow;
+};
+__device__ __forceinline__ LoadGroup load_group(const EdgeGeom& G, uint64_t e, uint32_t r) {
+  const uint32_t kidx = (uint32_t)(e & ((1ull << G.kb) - 1));
+  const uint32_t t1 = udiv_rcp(kidx, G.K2, G.rK2), kx = kidx - t1 * G.K2;
+  const uint32_t kz = udiv_rcp(t1, G.K1, G.rK1), ky = t1 - kz * G.K1;
+  const int ax = (kz & 1) ? 0 : ((ky & 1) ? 1 : 2);
+  const int b0 = ax == 0 ? 1 : 0, b1 = ax == 2 ? 1 : 2;  // the two other axes
+  // not an edge of the image (a broken invariant, reported where e is used as
+  // a pivot): read in-range addresses only
+  const bool edge = kz < G.K0 && ((kz & 1) + (ky & 1) + (kx & 1)) == 1;
+  const uint32_t cz = edge ? kz >> 1 : 0, cy = edge ? ky >> 1 : 0, cx = edge ? kx >> 1 : 0;
+  const uint32_t pax = sel3(ax, G.ps0, G.ps1, 1u);
+  const uint32_t anchor = cz * G.ps0 + cy * G.ps1 + cx;
+  const uint32_t slot = 3 * anchor + (uint32_t)ax;
+  const uint32_t rq = r - 2;
+  const bool rfar = r >= 2 && r < 10;
+  const int bb = (rq & 4) ? b1 : b0;
+  const int rsg = (rq & 2) ? 1 : -1;
+  const uint32_t vb = sel3(bb, cz, cy, cx) + (uint32_t)rsg;  // wraps below 0
+  const bool pix_ok = edge && (r < 2 || (rfar && vb < sel3(bb, G.n0, G.n1, G.n2)));
+  const uint32_t pofs = ((r == 1 || (rfar && (rq & 1))) ? pax : 0u) +
+                        (rfar ? (uint32_t)(rsg * (int32_t)sel3(bb, G.ps0, G.ps1, 1u)) : 0u);
+  LoadGroup g;
+  g.praw = G.img[pix_ok ? anchor + pofs : anchor];
+  g.code = G.eapp[slot];
+  g.ow = G.owner[slot];
+  return g;
+}
+
 // Stores the column P ^ F ^ U ^ T as one arena list and records it for column
 // c with pivot key pv: with a claim word, c is proposed for that pivot;
 // without one (pv = YIELDED) c is appended to the next round's long list.
@@ -1038,18 +1115,14 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
   const uint32_t n0 = (uint32_t)d.n[0], n1 = (uint32_t)d.n[1], n2 = (uint32_t)d.n[2];
   const uint32_t ps0 = n1 * n2, ps1 = n2;
   const uint32_t ks0 = K1 * K2, ks1 = K2;
+  const double rK1 = 1.0 / (double)K1, rK2 = 1.0 / (double)K2;
   const float* imgp = cold(R)->img + d.pix_off;
   const uint8_t* eappp = cold(R)->eapp + 3 * d.pix_off;
   const uint64_t* ownp = cold(R)->owner + 3 * d.pix_off;
   const uint64_t kpre = make_skey(R.L, 1, im, 0, 0);  // the dimension and image fields of an edge key
-  // lane roles in the load group: 0 and 1 the edge's endpoints, 2..9 the far
-  // vertices of the four squares around it (lane 2 + 4h + 2s + o: the other
-  // axis h, side s, endpoint o)
-  const uint32_t lq = (uint32_t)lane - 2;
-  const bool lfar = lane >= 2 && lane < 10;
-  const bool lhi = (lq & 4) != 0;
-  const bool lodd = (lq & 1) != 0;
-  const int lsg = (lq & 2) ? 1 : -1;
+  const EdgeGeom G{R.L.kb, (uint32_t)d.K[0], K1, K2, rK1, rK2, n0, n1, n2, ps0, ps1, imgp, eappp, ownp};
+  LoadGroup pf{0.0f, 0xFFu, NO_OWNER};  // the prefetched load groups and their three edges
+  uint64_t pk0 = 0, pk1 = 0, pk2 = 0;
   {
     const uint64_t off = uni64(cold(R)->col_ptr[c]);
     const uint32_t len = uni((uint32_t)R.arena[off]);
@@ -1088,40 +1161,37 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
     }
     // the pivot edge: Khalimsky coordinates, axis, anchor pixel
     const uint32_t kidx = skey_kidx(R.L, e);
-    const uint32_t kx = kidx % K2, t1 = kidx / K2;
-    const uint32_t ky = t1 % K1, kz = t1 / K1;
+    const uint32_t t1 = udiv_rcp(kidx, K2, rK2), kx = kidx - t1 * K2;
+    const uint32_t kz = udiv_rcp(t1, K1, rK1), ky = t1 - kz * K1;
     if ((e >> R.L.kb >> 32) != (kpre >> R.L.kb >> 32) || kz >= (uint32_t)d.K[0] ||
         ((kz & 1) + (ky & 1) + (kx & 1)) != 1) {  // not an edge of this image: a broken invariant
       if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->internal);
       return;
     }
     const int ax = (kz & 1) ? 0 : ((ky & 1) ? 1 : 2);
-    const int b0 = ax == 0 ? 1 : 0, b1 = ax == 2 ? 1 : 2;  // the two other axes
-    const uint32_t cz = kz >> 1, cy = ky >> 1, cx = kx >> 1;
-    const uint32_t pax = sel3(ax, ps0, ps1, 1u);
+    const int b1 = ax == 2 ? 1 : 2;  // the larger of the two other axes
     const uint32_t kax = sel3(ax, ks0, ks1, 1u);
-    const uint32_t anchor = cz * ps0 + cy * ps1 + cx;
-    const uint32_t slot = 3 * anchor + (uint32_t)ax;
-    // one group of loads: this lane's vertex (lanes past 9, and vertices off
-    // the image, read the anchor), the apparent code and the owner word (the
-    // same address in every lane)
-    const int bb = lhi ? b1 : b0;
-    const uint32_t vb = sel3(bb, cz, cy, cx) + (uint32_t)lsg;  // wraps below 0
-    const bool pix_ok = lane < 2 || (lfar && vb < sel3(bb, n0, n1, n2));
-    const uint32_t pofs = ((lane == 1 || (lfar && lodd)) ? pax : 0u) +
-                          (lfar ? (uint32_t)(lsg * (int32_t)sel3(bb, ps0, ps1, 1u)) : 0u);
-    const float praw = imgp[pix_ok ? anchor + pofs : anchor];
-    const uint32_t code = uni((uint32_t)eappp[slot]);
-    const uint64_t ow = uni64(ownp[slot]);
-    const float pv = (praw != praw) ? INFINITY : canon(praw);
+    const uint32_t slot = 3 * ((kz >> 1) * ps0 + (ky >> 1) * ps1 + (kx >> 1)) + (uint32_t)ax;
+    // the load group of e: prefetched with the previous apparent addition when
+    // e is one of the three edges it brought in (lanes 16 g .. 16 g + 15 hold
+    // edge g's), else loaded now (lanes 0 .. 15)
+    const int hit = e == pk0 ? 0 : (e == pk1 ? 1 : (e == pk2 ? 2 : -1));
+    uint32_t lb = 0;
+    LoadGroup lg = pf;
+    if (hit >= 0) lb = 16u * (uint32_t)hit;
+    else lg = load_group(G, e, (uint32_t)lane);
+    const uint32_t code = uni((uint32_t)__builtin_amdgcn_readlane((int)lg.code, (int)lb));
+    const uint64_t ow = rdlane64(lg.ow, lb);
+    const float pv = (lg.praw != lg.praw) ? INFINITY : canon(lg.praw);
+    pk0 = pk1 = pk2 = 0;
     w_count(W.adds, 1, lane);
     if (code != 0xFF) {
       // apparent partner s: its boundary is e and three older edges
       const int pb = (int)(code >> 1);
       const int sg = (code & 1) ? 1 : -1;
-      const int q = 2 + ((pb == b1) ? 4 : 0) + (sg > 0 ? 2 : 0);
-      const float v0 = rdlane_f(pv, 0), v1 = rdlane_f(pv, 1);
-      const float w0 = rdlane_f(pv, (uint32_t)q), w1 = rdlane_f(pv, (uint32_t)q + 1);
+      const uint32_t q = lb + 2 + ((pb == b1) ? 4 : 0) + (sg > 0 ? 2 : 0);
+      const float v0 = rdlane_f(pv, lb), v1 = rdlane_f(pv, lb + 1);
+      const float w0 = rdlane_f(pv, q), w1 = rdlane_f(pv, q + 1);
       const uint32_t kb = (uint32_t)((int)sel3(pb, ks0, ks1, 1u) * sg);
       const uint64_t kw = kpre | ((uint64_t)ord_of(fmaxf(w0, w1)) << R.L.kb) | (kidx + 2 * kb);
       const uint64_t ka0 = kpre | ((uint64_t)ord_of(fmaxf(v0, w0)) << R.L.kb) | (kidx - kax + kb);
@@ -1131,6 +1201,15 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
         return;
       }
       w_pop(W, where, lane);
+      // the next pivot is often one of these three edges: start their loads
+      // now, to arrive while they are inserted and the next pivot is found
+      {
+        const uint32_t g = (uint32_t)lane < 32 ? (uint32_t)lane >> 4 : 2u;
+        pf = load_group(G, g == 0 ? kw : (g == 1 ? ka0 : ka1), (uint32_t)lane & 15u);
+        pk0 = kw;
+        pk1 = ka0;
+        pk2 = ka1;
+      }
       if (!O::insert3(R, S, W, kw, ka0, ka1, lane)) return;
       continue;
     }
