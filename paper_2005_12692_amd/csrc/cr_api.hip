@@ -313,7 +313,7 @@ Plan make_plan(const Problem& pb, uint64_t arena_entries, bool side_h0 = false) 
   p.cleared = take(vol ? p.e_cap : 0);
   p.claim = take(vol ? 8 * 3 * pb.P : 0);
   for (int i = 0; i < 4; ++i) p.list[i] = take(vol ? 4 * p.e_cap : 0);
-  p.eapp = take(vol ? 3 * pb.P : 0);
+  p.eapp = take(vol ? 4 * pb.P : 0);
   if (vol && side_h0) p.T0 = take(8 * (pb.P + pb.nimg + 64));
   p.total = o;
   return p;

@@ -13,7 +13,7 @@ struct RedCtx {
   const uint64_t* skeys;
   const unsigned long long* dim_count;
   const uint8_t* cleared;  // per square rank: 1 = birth of degree 2 (zero column)
-  const uint8_t* eapp;     // per edge slot: apparent partner square (2 * axis + dir), 0xFF if none
+  const uint8_t* eapp;     // per edge (4 * anchor pixel + axis): apparent partner square (2 * axis + dir), 0xFF if none
   uint64_t* owner;         // per edge (3 * anchor pixel + axis of the edge): (owning column << 32) |
                            // arena offset of that column's stored list; NO_OWNER if none
   uint64_t* claim;         // per edge: claim_word(round, column) of the leftmost proposer in the latest

@@ -30,8 +30,9 @@
 //    cofacet of s (older in the reversed order), or to the image's exterior
 //    node when s lies on the boundary.  This is the same forest for the dual
 //    union-find of the top dimension.
-// and, for the degree-1 reduction of a volume, eapp[3 * pixel + axis] of every
-// edge: 2 * axis + (direction > 0) of its apparent partner square, 0xFF if none.
+// and, for the degree-1 reduction of a volume, eapp[4 * pixel + axis] of every
+// edge (axis 0 z, 1 y, 2 x; one 32-bit store per pixel): 2 * axis + (direction
+// > 0) of its apparent partner square, 0xFF if none.
 #include "cr_internal.h"
 
 namespace cr {
@@ -143,6 +144,13 @@ __device__ __forceinline__ void codes_all(const Rec& own, const Rec& mz, const R
 
 __device__ __forceinline__ uint32_t code_of(uint32_t word, int t) { return (word >> (3 * t)) & 7u; }
 
+// Bit 3 t set iff field t (3 bits) of the code word w equals c (c < 7; a
+// missing code is 7 and never matches).
+__device__ __forceinline__ uint32_t eq_code(uint32_t w, uint32_t c) {
+  const uint32_t v = w ^ (c * 0x249249u);
+  return ~(v | (v >> 1) | (v >> 2)) & 0x249249u;
+}
+
 template <int RW>
 struct StencilLds {
   uint4 recA[RW][64];  // record fields 0, 1, 4, 5 (read by the row above: cells without a y extent)
@@ -218,54 +226,73 @@ __global__ __launch_bounds__(64 * RW) void k_stencil(
 
   // Classifies the cells anchored at (plane zc, y, x) from the codes of this
   // pixel (E0, F0), of the pixels one step down each axis (latest-facet words
-  // Fm*) and one step up (earliest-cofacet words Ep*).  Writes the links and
-  // returns the survivor mask; keys[] receives the survivors' keys.
+  // Fm*) and one step up (earliest-cofacet words Ep*).  Every type at once: a
+  // code word holds eight 3-bit fields, and eq_code marks the fields equal to
+  // a direction with bit 3 t, so a pairing condition is a shift and an AND of
+  // such marks (the field of type t | A sits 3 A bits above that of t).
+  // Writes the links and the edges' partner codes; returns the survivor mask,
+  // bit 3 t for type t.
   auto classify = [&](int zc, const Rec& R, uint32_t E0, uint32_t F0, uint32_t Fmz, uint32_t Fmy, uint32_t Fmx,
-                      uint32_t Epz, uint32_t Epy, uint32_t Epx, uint64_t* keys) -> uint32_t {
-    const int64_t pix = d.pix_off + (int64_t)zc * rowpix + (int64_t)y * n2 + x;
-    const uint32_t kbase = ((uint32_t)(2 * zc) * K1 + (uint32_t)(2 * y)) * K2 + (uint32_t)(2 * x);
-    uint32_t mask = 0;
-    // branch-free: every quantity is computed for every cell type and selected
+                      uint32_t Epz, uint32_t Epy, uint32_t Epx) -> uint32_t {
+    const int32_t pix = (int32_t)(d.pix_off + (int64_t)zc * rowpix + (int64_t)y * n2 + x);
+    const int32_t st_z = (int32_t)rowpix, st_y = n2;
+    // earliest cofacet of (p, t) in direction d: eE[d]; latest facet of (p, u): eF[d]
+    const uint32_t eE0 = eq_code(E0, 0), eE1 = eq_code(E0, 1), eE2 = eq_code(E0, 2);
+    const uint32_t eE3 = eq_code(E0, 3), eE4 = eq_code(E0, 4), eE5 = eq_code(E0, 5);
+    const uint32_t eF0 = eq_code(F0, 0), eF1 = eq_code(F0, 1), eF2 = eq_code(F0, 2);
+    const uint32_t eF3 = eq_code(F0, 3), eF4 = eq_code(F0, 4), eF5 = eq_code(F0, 5);
+    // (p, t) with its earliest cofacet t | A above it (+a: same anchor, whose
+    // latest facet must be -a) or below it (-a: anchor p - e_a, whose latest
+    // facet must be +a)
+    const uint32_t pf = (eE5 & (eF0 >> 12)) | (eE0 & (eq_code(Fmz, 5) >> 12)) |  // z
+                        (eE4 & (eF1 >> 6)) | (eE1 & (eq_code(Fmy, 4) >> 6)) |    // y
+                        (eE3 & (eF2 >> 3)) | (eE2 & (eq_code(Fmx, 3) >> 3));     // x
+    // (p, u) with its latest facet u - B below it (-b: same anchor, whose
+    // earliest cofacet must be +b) or above it (+b: anchor p + e_b, whose
+    // earliest cofacet must be -b)
+    const uint32_t pc = (eF0 & (eE5 << 12)) | (eF5 & (eq_code(Epz, 0) << 12)) |  // z
+                        (eF1 & (eE4 << 6)) | (eF4 & (eq_code(Epy, 1) << 6)) |    // y
+                        (eF2 & (eE3 << 3)) | (eF3 & (eq_code(Epx, 2) << 3));     // x
+    uint32_t exists = 0;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const bool exists = R.v[t] != NONE;
-      // as the facet of its earliest cofacet (code e, along axis a)
-      const uint32_t e = t == 7 ? 7u : code_of(E0, t);
-      const uint32_t a = e < 3 ? e : (e < 6 ? 5 - e : 0u);
-      const uint32_t u = (uint32_t)t | (4u >> a);
-      const uint32_t lfw = e >= 3 ? F0 : (a == 0 ? Fmz : (a == 1 ? Fmy : Fmx));
-      const bool pf = e != 7 && ((lfw >> (3 * u)) & 7u) == (e >= 3 ? a : 5 - a);
-      // as the cofacet of its latest facet (code f, along axis b)
-      const uint32_t f = t == 0 ? 7u : code_of(F0, t);
-      const uint32_t b = f < 3 ? f : (f < 6 ? 5 - f : 0u);
-      const uint32_t sv = (uint32_t)t ^ (4u >> b);
-      const uint32_t ecw = f < 3 ? E0 : (b == 0 ? Epz : (b == 1 ? Epy : Epx));
-      const bool pc = f != 7 && ((ecw >> (3 * sv)) & 7u) == (f < 3 ? 5 - b : b);
-      const bool paired = pf || pc;
-      if (t == 0) {  // vertex: link to the other end of its edge
-        const int64_t step = a == 0 ? rowpix : (a == 1 ? (int64_t)n2 : 1);
-        vlink[pix] = pf ? (int32_t)(e >= 3 ? pix + step : pix - step) : -1;
-      }
-      if (t == TOP && exists) {  // top cell: link to the other cofacet of its facet, or the exterior
-        const int64_t step = b == 0 ? rowpix : (b == 1 ? (int64_t)n2 : 1);
-        const int nb = b == 0 ? n0 : (b == 1 ? n1 : n2);
-        const int pb = b == 0 ? zc : (b == 1 ? y : x);
-        const bool ext = f < 3 ? pb < 1 : pb + 2 >= nb;
-        tlink[pix] = pc ? (ext ? -(im + 2) : (int32_t)(f < 3 ? pix - step : pix + step)) : -1;
-      }
-      if (NDIM == 3 && popc3(t) == 1) {
-        if (eapp && exists)
-          eapp[3 * pix + (t == 4 ? 0 : (t == 2 ? 1 : 2))] = pf ? (uint8_t)(2 * a + (e >= 3 ? 1u : 0u)) : (uint8_t)0xFF;
-      }
-      const uint32_t kidx = kbase + ((t & 4) ? K1 * K2 : 0u) + ((t & 2) ? K2 : 0u) + (uint32_t)(t & 1);
-      keys[t] = make_skey(L, popc3(t), im, R.v[t], kidx);
-      mask |= (exists && !paired) ? (1u << t) : 0u;
+    for (int t = 0; t < 8; ++t) exists |= R.v[t] != NONE ? (1u << (3 * t)) : 0u;
+    // axis of a direction code (0 z, 1 y, 2 x), read from a table so that it
+    // compiles to selects rather than branches
+    auto axis_of = [](uint32_t c) { return (0x012210u >> (4 * c)) & 3u; };
+    // vertex: link to the other end of its edge
+    {
+      const uint32_t e = E0 & 7u, a = axis_of(e);
+      const int32_t step = a == 0 ? st_z : (a == 1 ? st_y : 1);
+      const int32_t to = e >= 3 ? pix + step : pix - step;
+      vlink[pix] = (pf & 1u) ? to : -1;
     }
-    return mask;
+    // top cell: link to the other cofacet of its latest facet, or the exterior
+    {
+      const uint32_t f = (F0 >> (3 * TOP)) & 7u, b = axis_of(f);
+      const int32_t step = b == 0 ? st_z : (b == 1 ? st_y : 1);
+      const int pb = b == 0 ? zc : (b == 1 ? y : x);
+      const int nb = b == 0 ? n0 : (b == 1 ? n1 : n2);
+      const bool ext = f < 3 ? pb < 1 : pb + 2 >= nb;
+      const int32_t to = ext ? -(im + 2) : (f < 3 ? pix - step : pix + step);
+      const int32_t link = ((pc >> (3 * TOP)) & 1u) ? to : -1;
+      if (R.v[TOP] != NONE) tlink[pix] = link;
+    }
+    // the partner squares of the three edges (byte axis: 0 z, 1 y, 2 x) as
+    // 2 * axis + (direction > 0), 0xFF if none: one word per pixel
+    if (NDIM == 3 && eapp) {
+      // direction code d -> 2 * axis + (d >= 3): 0, 2, 4, 5, 3, 1
+      auto part = [&](int t) -> uint32_t {
+        const uint32_t e = (E0 >> (3 * t)) & 7u;
+        return ((pf >> (3 * t)) & 1u) ? ((0x135420u >> (4 * e)) & 15u) : 0xFFu;
+      };
+      reinterpret_cast<uint32_t*>(eapp)[pix] = part(4) | (part(2) << 8) | (part(1) << 16) | 0xFF000000u;
+    }
+    return exists & ~(pf | pc);
   };
 
-  // Appends the survivors of this step with one atomic per workgroup.
-  auto flush = [&](uint32_t mask, const uint64_t* keys) {
+  // Appends the survivors of this step (mask bit 3 t for type t) with one
+  // atomic per workgroup.
+  auto flush = [&](int zc, const Rec& R, uint32_t mask) {
     const uint32_t cnt = (uint32_t)__popc(mask);
     uint32_t pre = 0, tot = 0;
 #pragma unroll
@@ -282,21 +309,25 @@ __global__ __launch_bounds__(64 * RW) void k_stencil(
         S.woff[w] = run;
         run += S.wcnt[w];
       }
-      S.wbase = run ? atomicAdd(surv_count, (unsigned long long)run) : 0ull;
+      const unsigned long long base = run ? atomicAdd(surv_count, (unsigned long long)run) : 0ull;
+      if (base + run > surv_cap) raise_flag(st, &st->overflow, OVF_SURVIVORS);  // what fits is kept
+      S.wbase = base;
     }
     __syncthreads();
+    if (!mask) return;
     unsigned long long pos = S.wbase + S.woff[row] + pre;
+    const unsigned long long lim = surv_cap;
+    const uint32_t kbase = ((uint32_t)(2 * zc) * K1 + (uint32_t)(2 * y)) * K2 + (uint32_t)(2 * x);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      if (mask & (1u << t)) {
-        if (pos < surv_cap) surv[pos] = keys[t];
-        else raise_flag(st, &st->overflow, OVF_SURVIVORS);
+      if ((mask >> (3 * t)) & 1u) {
+        const uint32_t kidx = kbase + ((t & 4) ? K1 * K2 : 0u) + ((t & 2) ? K2 : 0u) + (uint32_t)(t & 1);
+        if (pos < lim) surv[pos] = make_skey(L, popc3(t), im, R.v[t], kidx);
         ++pos;
       }
     }
   };
 
-  uint64_t keys[8];
   if constexpr (NDIM == 2) {
     uint32_t f, fy;
     load_plane(0, &f, &fy);
@@ -314,8 +345,8 @@ __global__ __launch_bounds__(64 * RW) void k_stencil(
     const uint32_t Epy = row < RW - 1 ? S.cw[0][row + 1][lane].x : NO_CODES;
     const uint32_t Fmx = lane_up1(F), Epx = lane_down1(E);
     uint32_t mask = 0;
-    if (inner) mask = classify(0, R0, E, F, NO_CODES, Fmy, Fmx, NO_CODES, Epy, Epx, keys);
-    flush(mask, keys);
+    if (inner) mask = classify(0, R0, E, F, NO_CODES, Fmy, Fmx, NO_CODES, Epy, Epx);
+    flush(0, R0, mask);
   } else {
     const int zend = z0 + ZC < n0 ? z0 + ZC : n0;
     // rolling state: planar values of plane kk+1, records of planes kk-1..kk+1,
@@ -354,12 +385,12 @@ __global__ __launch_bounds__(64 * RW) void k_stencil(
         const uint32_t Fmy = row > 0 ? S.cw[zc & 1][row - 1][lane].y : NO_CODES;
         const uint32_t Epy = row < RW - 1 ? S.cw[zc & 1][row + 1][lane].x : NO_CODES;
         const uint32_t Fmx = lane_up1(Fc), Epx = lane_down1(Ec);
-        if (inner) mask = classify(zc, Rm, Ec, Fc, Fcm, Fmy, Fmx, E, Epy, Epx, keys);
+        if (inner) mask = classify(zc, Rm, Ec, Fc, Fcm, Fmy, Fmx, E, Epy, Epx);
       }
       Fcm = Fc;
       Ec = E;
       Fc = F;
-      flush(mask, keys);  // also the barrier before the next step's record exchange
+      flush(kk - 1, Rm, mask);  // also the barrier before the next step's record exchange
     }
   }
   if (__ballot(nan) && lane == 0) {

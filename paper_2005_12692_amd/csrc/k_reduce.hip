@@ -44,6 +44,11 @@ __device__ inline int64_t edge_slot(const ImgDesc& d, const int c[3]) {
   const int axis = (c[0] & 1) ? 0 : ((c[1] & 1) ? 1 : 2);
   return 3 * anchor_pixel(d, c) + axis;
 }
+// The byte of an edge in the stencil's partner codes: four per anchor pixel.
+__device__ inline int64_t eapp_slot(const ImgDesc& d, const int c[3]) {
+  const int axis = (c[0] & 1) ? 0 : ((c[1] & 1) ? 1 : 2);
+  return 4 * anchor_pixel(d, c) + axis;
+}
 
 __device__ inline void sort_small(uint64_t* a, int n) {
   for (int i = 1; i < n; ++i) {
@@ -76,7 +81,7 @@ __device__ inline int sq_boundary(const RedCtx& R, int im, const ImgDesc& d, con
 // latest facet of s, as recorded by the stencil pass -- writes the boundary of
 // s into bnd and returns its length; returns 0 otherwise.
 __device__ inline int apparent_bnd(const RedCtx& R, int im, const ImgDesc& d, const int ec[3], uint64_t bnd[4]) {
-  const uint8_t code = R.eapp[edge_slot(d, ec)];
+  const uint8_t code = R.eapp[eapp_slot(d, ec)];
   if (code == 0xFF) return 0;
   int t[3] = {ec[0], ec[1], ec[2]};
   t[code >> 1] += (code & 1) ? 1 : -1;
@@ -282,7 +287,7 @@ __device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64
     const int ax = (kz & 1) ? 0 : ((ky & 1) ? 1 : 2);
     const int64_t anchor = pixel_index(d, (int)(kz >> 1), (int)(ky >> 1), (int)(kx >> 1));
     const int64_t slot = 3 * anchor + ax;
-    const uint8_t code = R.eapp[slot];
+    const uint8_t code = R.eapp[4 * anchor + ax];
     const uint64_t ow = R.owner[slot];
     if (code != 0xFF) {  // the apparent partner s of e: its boundary is e and three older edges
       if (C.n + 2 > (uint32_t)TC) {
@@ -1010,7 +1015,7 @@ struct EdgeGeom {
   double rK1, rK2;                     // their reciprocals
   uint32_t n0, n1, n2, ps0, ps1;       // pixel extents and strides
   const float* img;                    // the image's pixels
-  const uint8_t* eapp;                 // its edges' apparent codes
+  const uint8_t* eapp;                 // its edges' apparent codes (4 bytes per anchor pixel)
   const uint64_t* owner;               // its edges' owner words
 };
 // What a lane loads for edge e in role r (the value only once it is used):
@@ -1046,7 +1051,7 @@ __device__ __forceinline__ LoadGroup load_group(const EdgeGeom& G, uint64_t e, u
                         (rfar ? (uint32_t)(rsg * (int32_t)sel3(bb, G.ps0, G.ps1, 1u)) : 0u);
   LoadGroup g;
   g.praw = G.img[pix_ok ? anchor + pofs : anchor];
-  g.code = G.eapp[slot];
+  g.code = G.eapp[4 * anchor + (uint32_t)ax];
   g.ow = G.owner[slot];
   return g;
 }
@@ -1117,7 +1122,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
   const uint32_t ks0 = K1 * K2, ks1 = K2;
   const double rK1 = 1.0 / (double)K1, rK2 = 1.0 / (double)K2;
   const float* imgp = cold(R)->img + d.pix_off;
-  const uint8_t* eappp = cold(R)->eapp + 3 * d.pix_off;
+  const uint8_t* eappp = cold(R)->eapp + 4 * d.pix_off;
   const uint64_t* ownp = cold(R)->owner + 3 * d.pix_off;
   const uint64_t kpre = make_skey(R.L, 1, im, 0, 0);  // the dimension and image fields of an edge key
   const EdgeGeom G{R.L.kb, (uint32_t)d.K[0], K1, K2, rK1, rK2, n0, n1, n2, ps0, ps1, imgp, eappp, ownp};
