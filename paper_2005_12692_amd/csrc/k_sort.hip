@@ -1,18 +1,17 @@
 // LSD radix sort of 64-bit keys (key only), 8-bit digits.
 //
 // The number of keys lives in device memory, so the sort can be enqueued before
-// the count is known (and captured in a graph).
-//   hist_all   -- one read of the keys gives the digit histograms of every pass
-//                 (per-block partial counts, reduced by offsets);
-//   offsets    -- per pass, the exclusive start of every digit's bucket;
-// then per digit position, over tiles of 4096 keys:
+// the count is known (and captured in a graph).  Per digit position, over
+// tiles of 4096 keys:
 //   count      -- per tile and digit, the number of keys;
-//   scan_tiles -- per digit, those counts become the global position of each
-//                 tile's first key of that digit;
-//   scatter    -- each tile is ranked by digit with wavefront ballots (stable:
-//                 wavefront, step, then lane order), sorted by digit in LDS and
-//                 written out in runs of equal digits, so the stores are
-//                 contiguous.
+//   scan_tiles -- per digit, those counts become the position of each tile's
+//                 first key of that digit among the keys of that digit, and the
+//                 digit's total is recorded;
+//   scatter    -- each workgroup first turns the 256 totals into the start of
+//                 every digit's bucket (a scan of 256 values), then ranks each
+//                 tile by digit with wavefront ballots (stable: wavefront, step,
+//                 then lane order), sorts it by digit in LDS and writes it out
+//                 in runs of equal digits, so the stores are contiguous.
 #include "cr_internal.h"
 
 namespace cr {
@@ -21,50 +20,10 @@ constexpr int ST = 256;               // threads of a pass workgroup
 constexpr int SKEYS = 16;             // keys per thread per tile
 constexpr int STILE = ST * SKEYS;     // keys per tile
 constexpr int SWAVES = ST / 64;
-constexpr int HB = 512;               // workgroups of the histogram kernel
 constexpr int SGRID = 1024;           // persistent workgroups of a pass
-constexpr int MAX_PASSES = 8;
 
 __device__ __forceinline__ uint64_t n_keys(const unsigned long long* n_ptr, uint64_t cap) {
   return *n_ptr < cap ? *n_ptr : cap;
-}
-
-__global__ __launch_bounds__(ST) void k_sort_hist_all(const uint64_t* __restrict__ keys,
-                                                      const unsigned long long* __restrict__ n_ptr, uint64_t cap,
-                                                      int passes, uint32_t* __restrict__ part) {
-  __shared__ uint32_t h[MAX_PASSES][256];
-  const int tid = threadIdx.x, b = blockIdx.x;
-  for (int p = 0; p < MAX_PASSES; ++p) h[p][tid] = 0;
-  __syncthreads();
-  const uint64_t n = n_keys(n_ptr, cap);
-  const uint64_t chunk = (n + HB - 1) / HB;
-  const uint64_t lo = (uint64_t)b * chunk;
-  const uint64_t hi = lo + chunk < n ? lo + chunk : n;
-  for (uint64_t i = lo + tid; i < hi; i += ST) {
-    const uint64_t k = keys[i];
-    for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255], 1u);
-  }
-  __syncthreads();
-  for (int p = 0; p < passes; ++p) part[((size_t)p * 256 + tid) * HB + b] = h[p][tid];
-}
-
-// offs[p * 256 + d] = number of keys whose digit p is below d.  One workgroup per pass.
-__global__ __launch_bounds__(256) void k_sort_offsets(const uint32_t* __restrict__ part, uint32_t* __restrict__ offs) {
-  __shared__ uint32_t wsum[4];
-  const int p = blockIdx.x, d = threadIdx.x, lane = d & 63, w = d >> 6;
-  const uint32_t* src = part + ((size_t)p * 256 + d) * HB;
-  uint32_t tot = 0;
-  for (int b = 0; b < HB; ++b) tot += src[b];
-  uint32_t incl = tot;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t up = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += up;
-  }
-  if (lane == 63) wsum[w] = incl;
-  __syncthreads();
-  uint32_t before = 0;
-  for (int i = 0; i < w; ++i) before += wsum[i];
-  offs[p * 256 + d] = before + incl - tot;
 }
 
 // Ranks the keys of one tile by digit: wavefront w takes keys [w*1024, (w+1)*1024)
@@ -131,18 +90,18 @@ __global__ __launch_bounds__(ST) void k_sort_count(const uint64_t* __restrict__ 
   }
 }
 
-// Per digit d (one workgroup each): counts[d * ntiles + t] becomes the global
-// position of tile t's first key of digit d (offs[d] plus the earlier tiles).
+// Per digit d (one workgroup each): counts[d * ntiles + t] becomes the number
+// of keys of digit d in the tiles before t, and tot[d] the digit's total.
 __global__ __launch_bounds__(256) void k_sort_scan_tiles(uint32_t* __restrict__ counts,
                                                          const unsigned long long* __restrict__ n_ptr, uint64_t cap,
-                                                         const uint32_t* __restrict__ offs) {
+                                                         uint32_t* __restrict__ tot) {
   __shared__ uint32_t wsum[4];
   __shared__ uint32_t carry_s;
   const int d = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint64_t n = n_keys(n_ptr, cap);
   const uint64_t ntiles = (n + STILE - 1) / STILE;
   uint32_t* col = counts + (uint64_t)d * ntiles;
-  if (tid == 0) carry_s = offs[d];
+  if (tid == 0) carry_s = 0;
   __syncthreads();
   constexpr int PER = 8;
   for (uint64_t base = 0; base < ntiles; base += 256 * PER) {
@@ -173,17 +132,34 @@ __global__ __launch_bounds__(256) void k_sort_scan_tiles(uint32_t* __restrict__ 
     if (tid == 255) carry_s = run;
     __syncthreads();
   }
+  if (tid == 0) tot[d] = carry_s;
 }
 
 // One pass: each tile is ranked again, sorted by digit in LDS and written out
 // in runs of equal digits at the positions from k_sort_scan_tiles.
 __global__ __launch_bounds__(ST) void k_sort_scatter(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
                                                      const unsigned long long* __restrict__ n_ptr, uint64_t cap,
-                                                     int shift, const uint32_t* __restrict__ pos) {
+                                                     int shift, const uint32_t* __restrict__ pos,
+                                                     const uint32_t* __restrict__ tot) {
   __shared__ SortLds S;
+  __shared__ uint32_t bucket[256];  // start of each digit's bucket
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint64_t n = n_keys(n_ptr, cap);
   const uint64_t ntiles = (n + STILE - 1) / STILE;
+  {
+    const uint32_t t = tot[tid];
+    uint32_t incl = t;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t up = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += up;
+    }
+    if (lane == 63) S.wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int i = 0; i < w; ++i) before += S.wsum[i];
+    bucket[tid] = before + incl - t;
+    __syncthreads();
+  }
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     for (int i = 0; i < SWAVES; ++i) S.cnt[i][tid] = 0;
     __syncthreads();
@@ -207,7 +183,7 @@ __global__ __launch_bounds__(ST) void k_sort_scatter(const uint64_t* __restrict_
       if (lane >= off) incl += up;
     }
     if (lane == 63) S.wsum[w] = incl;
-    S.gpos[d] = pos[(uint64_t)d * ntiles + tile];
+    S.gpos[d] = bucket[d] + pos[(uint64_t)d * ntiles + tile];
     __syncthreads();
     uint32_t before = 0;
     for (int i = 0; i < w; ++i) before += S.wsum[i];
@@ -235,10 +211,10 @@ __global__ __launch_bounds__(ST) void k_sort_scatter(const uint64_t* __restrict_
   }
 }
 
-// Scratch of launch_sort: partial histograms, digit offsets, per-tile counts.
+// Scratch of launch_sort: per-tile counts and the digit totals.
 size_t sort_scratch_bytes(uint64_t cap) {
   const uint64_t tiles = (cap + STILE - 1) / STILE + 1;
-  return 4ull * MAX_PASSES * 256 * HB + 4ull * MAX_PASSES * 256 + 4ull * tiles * 256 + 256;
+  return 4ull * 256 + 4ull * tiles * 256 + 256;
 }
 
 // Sorts keys[0..min(*n, cap)) ascending on bits [0, bits); tmp is scratch of the same
@@ -246,19 +222,16 @@ size_t sort_scratch_bytes(uint64_t cap) {
 uint64_t* launch_sort(uint64_t* keys, uint64_t* tmp, const unsigned long long* n_ptr, uint64_t cap, int bits,
                       void* scratch, hipStream_t stream) {
   const int passes = (bits + 7) / 8;
-  uint32_t* part = static_cast<uint32_t*>(scratch);
-  uint32_t* offs = part + (size_t)MAX_PASSES * 256 * HB;
-  uint32_t* counts = offs + MAX_PASSES * 256 + 64;
+  uint32_t* tot = static_cast<uint32_t*>(scratch);
+  uint32_t* counts = tot + 256;
   const uint64_t max_tiles = (cap + STILE - 1) / STILE;
   const int grid = (int)(max_tiles < (uint64_t)SGRID ? (max_tiles ? max_tiles : 1) : (uint64_t)SGRID);
-  k_sort_hist_all<<<HB, ST, 0, stream>>>(keys, n_ptr, cap, passes, part);
-  k_sort_offsets<<<passes, 256, 0, stream>>>(part, offs);
   uint64_t* a = keys;
   uint64_t* b = tmp;
   for (int p = 0; p < passes; ++p) {
     k_sort_count<<<grid, ST, 0, stream>>>(a, n_ptr, cap, 8 * p, counts);
-    k_sort_scan_tiles<<<256, 256, 0, stream>>>(counts, n_ptr, cap, offs + p * 256);
-    k_sort_scatter<<<grid, ST, 0, stream>>>(a, b, n_ptr, cap, 8 * p, counts);
+    k_sort_scan_tiles<<<256, 256, 0, stream>>>(counts, n_ptr, cap, tot);
+    k_sort_scatter<<<grid, ST, 0, stream>>>(a, b, n_ptr, cap, 8 * p, counts, tot);
     uint64_t* t = a;
     a = b;
     b = t;
