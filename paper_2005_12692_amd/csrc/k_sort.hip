@@ -2,16 +2,20 @@
 //
 // The number of keys lives in device memory, so the sort can be enqueued before
 // the count is known (and captured in a graph).  Per digit position, over
-// tiles of 4096 keys:
-//   count      -- per tile and digit, the number of keys;
-//   scan_tiles -- per digit, those counts become the position of each tile's
-//                 first key of that digit among the keys of that digit, and the
-//                 digit's total is recorded;
-//   scatter    -- each workgroup first turns the 256 totals into the start of
-//                 every digit's bucket (a scan of 256 values), then ranks each
-//                 tile by digit with wavefront ballots (stable: wavefront, step,
-//                 then lane order), sorts it by digit in LDS and writes it out
-//                 in runs of equal digits, so the stores are contiguous.
+// tiles of 4096 keys, with the per-tile digit counts stored tile-major (one
+// contiguous row of 256 counts per tile, so every kernel reads and writes them
+// in whole rows):
+//   count      -- per tile, the number of keys of each digit;
+//   scan_block -- per block of SBT tiles and digit, the counts become the
+//                 number of keys of that digit in the block's earlier tiles,
+//                 and the block's totals are recorded;
+//   scan_top   -- one workgroup: the block totals become the keys of each
+//                 digit in the earlier blocks, and the digit totals the start
+//                 of every digit's bucket;
+//   scatter    -- each tile is ranked by digit with wavefront ballots (stable:
+//                 wavefront, step, then lane order), sorted by digit in LDS
+//                 and written out in runs of equal digits, so the stores are
+//                 contiguous.
 #include "cr_internal.h"
 
 namespace cr {
@@ -21,6 +25,7 @@ constexpr int SKEYS = 16;             // keys per thread per tile
 constexpr int STILE = ST * SKEYS;     // keys per tile
 constexpr int SWAVES = ST / 64;
 constexpr int SGRID = 1024;           // persistent workgroups of a pass
+constexpr int SBT = 64;               // tiles per block of the count scan
 
 __device__ __forceinline__ uint64_t n_keys(const unsigned long long* n_ptr, uint64_t cap) {
   return *n_ptr < cap ? *n_ptr : cap;
@@ -66,7 +71,7 @@ __device__ __forceinline__ void rank_tile(SortLds& S, const uint64_t* __restrict
   }
 }
 
-// Per tile and digit: the number of keys, stored digit-major: counts[d * ntiles + tile].
+// Per tile and digit: the number of keys, counts[tile * 256 + d].
 __global__ __launch_bounds__(ST) void k_sort_count(const uint64_t* __restrict__ in,
                                                    const unsigned long long* __restrict__ n_ptr, uint64_t cap,
                                                    int shift, uint32_t* __restrict__ counts) {
@@ -85,54 +90,68 @@ __global__ __launch_bounds__(ST) void k_sort_count(const uint64_t* __restrict__ 
     __syncthreads();
     uint32_t tot = 0;
     for (int i = 0; i < SWAVES; ++i) tot += S.cnt[i][tid];
-    counts[(uint64_t)tid * ntiles + tile] = tot;
+    counts[tile * 256 + (uint64_t)tid] = tot;
     __syncthreads();
   }
 }
 
-// Per digit d (one workgroup each): counts[d * ntiles + t] becomes the number
-// of keys of digit d in the tiles before t, and tot[d] the digit's total.
-__global__ __launch_bounds__(256) void k_sort_scan_tiles(uint32_t* __restrict__ counts,
+// Per block b of SBT tiles (one workgroup each, thread d for digit d):
+// counts[t * 256 + d] becomes the number of keys of digit d in the block's
+// tiles before t, and bsum[b * 256 + d] the block's total of digit d.
+__global__ __launch_bounds__(256) void k_sort_scan_block(uint32_t* __restrict__ counts,
                                                          const unsigned long long* __restrict__ n_ptr, uint64_t cap,
-                                                         uint32_t* __restrict__ tot) {
-  __shared__ uint32_t wsum[4];
-  __shared__ uint32_t carry_s;
-  const int d = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+                                                         uint32_t* __restrict__ bsum) {
   const uint64_t n = n_keys(n_ptr, cap);
   const uint64_t ntiles = (n + STILE - 1) / STILE;
-  uint32_t* col = counts + (uint64_t)d * ntiles;
-  if (tid == 0) carry_s = 0;
-  __syncthreads();
-  constexpr int PER = 8;
-  for (uint64_t base = 0; base < ntiles; base += 256 * PER) {
-    uint32_t v[PER];
-    uint32_t sum = 0;
+  const uint64_t t0 = (uint64_t)blockIdx.x * SBT;
+  if (t0 >= ntiles) return;
+  const uint64_t t1 = t0 + SBT < ntiles ? t0 + SBT : ntiles;
+  const uint32_t nt = (uint32_t)(t1 - t0);
+  uint32_t* c = counts + t0 * 256 + threadIdx.x;
+  uint32_t v[SBT];  // all loads first, so that they are in flight together
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const uint64_t i = base + (uint64_t)tid * PER + k;
-      v[k] = i < ntiles ? col[i] : 0u;
-      sum += v[k];
-    }
-    uint32_t incl = sum;
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t up = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += up;
-    }
-    if (lane == 63) wsum[w] = incl;
-    __syncthreads();
-    uint32_t run = carry_s + incl - sum;
-    for (int i = 0; i < w; ++i) run += wsum[i];
+  for (int i = 0; i < SBT; ++i) v[i] = (uint32_t)i < nt ? c[(uint64_t)i * 256] : 0u;
+  uint32_t run = 0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const uint64_t i = base + (uint64_t)tid * PER + k;
-      if (i < ntiles) col[i] = run;
-      run += v[k];
-    }
-    __syncthreads();
-    if (tid == 255) carry_s = run;
-    __syncthreads();
+  for (int i = 0; i < SBT; ++i) {
+    if ((uint32_t)i < nt) c[(uint64_t)i * 256] = run;
+    run += v[i];
   }
-  if (tid == 0) tot[d] = carry_s;
+  bsum[(uint64_t)blockIdx.x * 256 + threadIdx.x] = run;
+}
+
+// One workgroup, thread d for digit d: bsum[b * 256 + d] becomes the number of
+// keys of digit d in the blocks before b, and bucket[d] the start of digit d's
+// bucket (the keys of all smaller digits).
+__global__ __launch_bounds__(256) void k_sort_scan_top(uint32_t* __restrict__ bsum,
+                                                       const unsigned long long* __restrict__ n_ptr, uint64_t cap,
+                                                       uint32_t* __restrict__ bucket) {
+  __shared__ uint32_t wsum[4];
+  const int d = threadIdx.x, lane = d & 63, w = d >> 6;
+  const uint64_t n = n_keys(n_ptr, cap);
+  const uint64_t nblocks = ((n + STILE - 1) / STILE + SBT - 1) / SBT;
+  constexpr int BATCH = 16;  // loads in flight together
+  uint32_t run = 0;
+  for (uint64_t b0 = 0; b0 < nblocks; b0 += BATCH) {
+    uint32_t v[BATCH];
+#pragma unroll
+    for (int i = 0; i < BATCH; ++i) v[i] = b0 + i < nblocks ? bsum[(b0 + i) * 256 + d] : 0u;
+#pragma unroll
+    for (int i = 0; i < BATCH; ++i) {
+      if (b0 + i < nblocks) bsum[(b0 + i) * 256 + d] = run;
+      run += v[i];
+    }
+  }
+  uint32_t incl = run;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t up = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += up;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int i = 0; i < w; ++i) before += wsum[i];
+  bucket[d] = before + incl - run;
 }
 
 // One pass: each tile is ranked again, sorted by digit in LDS and written out
@@ -140,26 +159,13 @@ __global__ __launch_bounds__(256) void k_sort_scan_tiles(uint32_t* __restrict__ 
 __global__ __launch_bounds__(ST) void k_sort_scatter(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
                                                      const unsigned long long* __restrict__ n_ptr, uint64_t cap,
                                                      int shift, const uint32_t* __restrict__ pos,
-                                                     const uint32_t* __restrict__ tot) {
+                                                     const uint32_t* __restrict__ bsum,
+                                                     const uint32_t* __restrict__ bucket) {
   __shared__ SortLds S;
-  __shared__ uint32_t bucket[256];  // start of each digit's bucket
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint64_t n = n_keys(n_ptr, cap);
   const uint64_t ntiles = (n + STILE - 1) / STILE;
-  {
-    const uint32_t t = tot[tid];
-    uint32_t incl = t;
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t up = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += up;
-    }
-    if (lane == 63) S.wsum[w] = incl;
-    __syncthreads();
-    uint32_t before = 0;
-    for (int i = 0; i < w; ++i) before += S.wsum[i];
-    bucket[tid] = before + incl - t;
-    __syncthreads();
-  }
+  const uint32_t start = bucket[tid];  // digit tid's bucket
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     for (int i = 0; i < SWAVES; ++i) S.cnt[i][tid] = 0;
     __syncthreads();
@@ -183,7 +189,7 @@ __global__ __launch_bounds__(ST) void k_sort_scatter(const uint64_t* __restrict_
       if (lane >= off) incl += up;
     }
     if (lane == 63) S.wsum[w] = incl;
-    S.gpos[d] = bucket[d] + pos[(uint64_t)d * ntiles + tile];
+    S.gpos[d] = start + bsum[(tile / SBT) * 256 + (uint64_t)d] + pos[tile * 256 + (uint64_t)d];
     __syncthreads();
     uint32_t before = 0;
     for (int i = 0; i < w; ++i) before += S.wsum[i];
@@ -211,10 +217,11 @@ __global__ __launch_bounds__(ST) void k_sort_scatter(const uint64_t* __restrict_
   }
 }
 
-// Scratch of launch_sort: per-tile counts and the digit totals.
+// Scratch of launch_sort: per-tile counts and per-block totals.
 size_t sort_scratch_bytes(uint64_t cap) {
   const uint64_t tiles = (cap + STILE - 1) / STILE + 1;
-  return 4ull * 256 + 4ull * tiles * 256 + 256;
+  const uint64_t blocks = (tiles + SBT - 1) / SBT + 1;
+  return 4ull * 256 + 4ull * 256 * blocks + 4ull * tiles * 256 + 256;
 }
 
 // Sorts keys[0..min(*n, cap)) ascending on bits [0, bits); tmp is scratch of the same
@@ -222,16 +229,20 @@ size_t sort_scratch_bytes(uint64_t cap) {
 uint64_t* launch_sort(uint64_t* keys, uint64_t* tmp, const unsigned long long* n_ptr, uint64_t cap, int bits,
                       void* scratch, hipStream_t stream) {
   const int passes = (bits + 7) / 8;
-  uint32_t* tot = static_cast<uint32_t*>(scratch);
-  uint32_t* counts = tot + 256;
   const uint64_t max_tiles = (cap + STILE - 1) / STILE;
+  const uint64_t max_blocks = (max_tiles + SBT - 1) / SBT;
+  uint32_t* bucket = static_cast<uint32_t*>(scratch);
+  uint32_t* bsum = bucket + 256;
+  uint32_t* counts = bsum + 256 * (max_blocks + 1);
   const int grid = (int)(max_tiles < (uint64_t)SGRID ? (max_tiles ? max_tiles : 1) : (uint64_t)SGRID);
+  const int bgrid = (int)(max_blocks ? max_blocks : 1);
   uint64_t* a = keys;
   uint64_t* b = tmp;
   for (int p = 0; p < passes; ++p) {
     k_sort_count<<<grid, ST, 0, stream>>>(a, n_ptr, cap, 8 * p, counts);
-    k_sort_scan_tiles<<<256, 256, 0, stream>>>(counts, n_ptr, cap, tot);
-    k_sort_scatter<<<grid, ST, 0, stream>>>(a, b, n_ptr, cap, 8 * p, counts, tot);
+    k_sort_scan_block<<<bgrid, 256, 0, stream>>>(counts, n_ptr, cap, bsum);
+    k_sort_scan_top<<<1, 256, 0, stream>>>(bsum, n_ptr, cap, bucket);
+    k_sort_scatter<<<grid, ST, 0, stream>>>(a, b, n_ptr, cap, 8 * p, counts, bsum, bucket);
     uint64_t* t = a;
     a = b;
     b = t;
