@@ -84,9 +84,18 @@ __global__ __launch_bounds__(ST) void k_sort_count(const uint64_t* __restrict__ 
     __syncthreads();
     const uint64_t t0 = tile * STILE;
     const uint32_t tcount = (uint32_t)(n - t0 < (uint64_t)STILE ? n - t0 : (uint64_t)STILE);
-    uint64_t key[SKEYS];
-    uint32_t rank[SKEYS];
-    rank_tile(S, in, t0, tcount, shift, key, rank);
+    {  // only the histogram: one LDS add per key into the wavefront's counts
+      const int lane = tid & 63, w = tid >> 6;
+      uint32_t dig[SKEYS];
+#pragma unroll
+      for (int j = 0; j < SKEYS; ++j) {
+        const uint32_t li = (uint32_t)(w * (SKEYS * 64) + j * 64 + lane);
+        dig[j] = li < tcount ? (uint32_t)(in[t0 + li] >> shift) & 255u : 256u;
+      }
+#pragma unroll
+      for (int j = 0; j < SKEYS; ++j)
+        if (dig[j] < 256u) atomicAdd(&S.cnt[w][dig[j]], 1u);
+    }
     __syncthreads();
     uint32_t tot = 0;
     for (int i = 0; i < SWAVES; ++i) tot += S.cnt[i][tid];
