@@ -600,6 +600,10 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     if (const char* v = getenv("CR_NARROW_MIN")) R.narrow_min = (uint32_t)strtoul(v, nullptr, 10);
     if (const char* v = getenv("CR_GROUP_MAX")) R.group_max = (uint32_t)strtoul(v, nullptr, 10);
     if (const char* v = getenv("CR_WAVE_YIELD")) R.wave_yield = (uint32_t)strtoul(v, nullptr, 10);
+    // a round of at most two columns has nothing to run beside its longest
+    // column, which then does not yield (256^3 degree 1 62.0 -> 60.3 ms;
+    // larger thresholds measured erratic: 4 and 16 slower, 8 faster)
+    if (const char* v = getenv("CR_YIELD_FEW")) R.yield_few = (uint32_t)strtoul(v, nullptr, 10);
     if (const char* v = getenv("CR_GROUP_CAP")) {
       const unsigned long f = strtoul(v, nullptr, 10);
       R.group_cap = (uint32_t)(f < FRONT_CAP_MIN ? FRONT_CAP_MIN : (f > 4096 ? 4096 : f));

@@ -37,6 +37,7 @@ struct RedCtx {
   uint32_t group_cap;      // keys of the group mode's front list
   uint32_t wave_yield;     // a wave- or group-mode column stores itself and continues in the next round
                            // after this many additions in one round (0: never)
+  uint32_t yield_few;      // ... except in a round of at most this many columns
   uint32_t* yield_list;    // the next round's long list and its count (set per round)
   unsigned long long* yield_count;
   uint32_t round;          // the round of this launch

@@ -1102,10 +1102,12 @@ __device__ __forceinline__ void store_column(const RedCtx& R, const WaveBufs& S,
 // Reduces column c for one round: until its pivot has no owner to its left,
 // then stores it and proposes it for its pivot; or, after wave_yield additions,
 // stores it unfinished for the next round, so that one long column does not
-// hold back the columns of every other image at the round's end.
+// hold back the columns of every other image at the round's end.  In a round
+// of few columns (`few`: at most yield_few) there is nothing to run beside a
+// long column, so it does not yield.
 template <class O>
 __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c, uint64_t off2,
-                                              int lane) {
+                                              int lane, bool few) {
   const int im = (int)uni((uint32_t)skey_img(R.L, uni64(cold(R)->skeys[off2 + c])));  // every edge lies in this image
   ImgDesc d = cold(R)->imgs[im];
 #pragma unroll
@@ -1148,7 +1150,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
       tail_set(W.T, src, len, lane);
     }
   }
-  const uint32_t ylim = uni(O::wave_yield(R) ? O::wave_yield(R) : 0xFFFFFFFFu);
+  const uint32_t ylim = uni(few || !O::wave_yield(R) ? 0xFFFFFFFFu : O::wave_yield(R));
   uint64_t out_piv = YIELDED;   // what is stored when the loop ends: the pivot and its
   uint64_t* claim_at = nullptr;  // claim word, or YIELDED and none after wave_yield additions
   for (uint32_t it = 0;; ++it) {
@@ -1263,6 +1265,7 @@ __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uin
   const uint64_t nl = uni64(*n_l), ns0 = uni64(*n_s);
   const uint64_t ns = ns0 <= R.wave_short ? ns0 : 0;
   if (nl + ns <= R.group_max || (nl + ns >= R.narrow_min) != (C::XN == NarrowCfg::XN)) return;
+  const bool few = nl + ns <= R.yield_few;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint64_t* base = lds_words + (size_t)wv * wave_lds_words<C>(front_cap);
   WaveBufs S;
@@ -1283,7 +1286,7 @@ __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uin
     li = rdlane64(li, 0);
     if (li >= nl + ns || aborted(R.st)) break;
     const uint32_t c = uni(li < nl ? list_l[li] : list_s[li - nl]);
-    reduce_column<WaveOps<C>>(R, S, W, c, off2, lane);
+    reduce_column<WaveOps<C>>(R, S, W, c, off2, lane, few);
     wsync();
   }
   if (lane == 0 && W.adds) {  // lane 0 holds the counts
@@ -1675,6 +1678,7 @@ __global__ __launch_bounds__(64 * GNW) void k_red_round_group(RedCtx R, const ui
   const uint64_t nl = uni64(*n_l), ns0 = uni64(*n_s);
   const uint64_t ns = ns0 <= R.wave_short ? ns0 : 0;
   if (nl + ns == 0 || nl + ns > R.group_max) return;
+  const bool few = nl + ns <= R.yield_few;
   const int lane = threadIdx.x & 63;
   WaveBufs S;
   S.cap = front_cap;
@@ -1703,7 +1707,7 @@ __global__ __launch_bounds__(64 * GNW) void k_red_round_group(RedCtx R, const ui
     li = rdlane64(li, 0);
     if (li >= nl + ns || aborted(R.st)) break;
     const uint32_t c = uni(li < nl ? list_l[li] : list_s[li - nl]);
-    reduce_column<GroupOps>(R, S, W, c, off2, lane);
+    reduce_column<GroupOps>(R, S, W, c, off2, lane, few);
     wsync();
   }
   if (lane == 0) G->desc.op = G_END;
@@ -1856,7 +1860,7 @@ __global__ __launch_bounds__(64 * WPB) void k_red_finish(RedCtx R, uint32_t* __r
       li = rdlane64(li, 0);
       if (li >= nt + nb || aborted(R.st)) break;
       const uint32_t c = uni(li < nb ? lb[li] : lt[li - nb]);
-      reduce_column<FinishOps<C>>(R, S, W, c, off2, lane);
+      reduce_column<FinishOps<C>>(R, S, W, c, off2, lane, true);
       wsync();
     }
     __threadfence();
@@ -1923,6 +1927,7 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.group_max = 1024;
   R.group_cap = 2048;
   R.wave_yield = 0;
+  R.yield_few = 2;
   R.yield_list = nullptr;
   R.yield_count = nullptr;
   R.round = 0;
