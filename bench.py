@@ -66,14 +66,14 @@ def stencil_bytes(shape, survivors_total: int) -> int:
 def stencil_side_bytes(shape, edge_codes: bool) -> int:
     """Bytes the stencil writes besides the survivor keys, for the later stages:
     the vertex-forest link of every pixel (4 B), the dual-forest link of every
-    top cell (4 B) and, for a volume's degree-1 reduction, the partner code of
-    each of the three edges anchored at a pixel (1 B each)."""
+    top cell (4 B) and, for a volume's degree-1 reduction, the partner codes of
+    the three edges anchored at a pixel (one 4 B word per pixel)."""
     P = 1
     C = 1
     for n in shape:
         P *= n
         C *= n - 1
-    return 4 * P + 4 * C + (3 * P if edge_codes else 0)
+    return 4 * P + 4 * C + (4 * P if edge_codes else 0)
 
 
 def sort_bytes(n_keys: int, bits: int) -> int:
@@ -501,7 +501,7 @@ def main():
                      "side_output_bytes": stencil_side_bytes((n, n, n), True), "ms": stages["stencil"],
                      "issue": issue_rate("k_stencil_256cube_traffic.md", stages["stencil"]),
                      "cold": {"ms": cold["stencil"], "achieved": c_achieved, "frac": c_achieved / HBM_PEAK_GBS}},
-        "roofline_sort": {"bound": "hbm", "kernel": "cell sort, %d 8-bit passes (count + scan + scatter)"
+        "roofline_sort": {"bound": "hbm", "kernel": "cell sort, %d 8-bit passes (count + block scan + top scan + scatter)"
                           % ((sort_bits + 7) // 8), "achieved": s_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": s_achieved / HBM_PEAK_GBS, "traffic": profiled_traffic("k_sort_256cube_traffic.md"),
                           "algorithmic_bytes": sbytes,
