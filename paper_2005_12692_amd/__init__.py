@@ -357,6 +357,12 @@ def _empty_out(n_rows: int, nimg: int, device) -> BatchedDiagram:
                           torch.empty(nimg, dtype=torch.int32, device=device))
 
 
+def empty_batched_output(n_rows: int, n_images: int, device) -> BatchedDiagram:
+    """Output buffers for a batched call of n_images with room for n_rows rows
+    (uninitialised), e.g. for persistence_batched_noalloc or check=False."""
+    return _empty_out(n_rows, n_images, device)
+
+
 def _out_args(out: BatchedDiagram):
     p = lambda t: ctypes.c_void_p(t.data_ptr())
     return [p(out.dim), p(out.birth), p(out.death), p(out.birth_pixel), p(out.death_pixel), out.dim.shape[0],
