@@ -102,8 +102,11 @@ typedef struct cr_diagram {
  * stream), then allocates `out` and enqueues the final copy on `stream`.  A
  * volume with maxdim >= 1 also waits while the degree-1 reduction runs: its
  * rounds are enqueued in batches of four and the host reads the count of
- * columns still active one batch behind (an event wait per batch, about 18 on
- * a 256^3 volume; the GPU is never left idle by them).  If the reduction's
+ * columns still active one batch behind (an event wait per batch, about 4 on a
+ * 256^3 volume; the GPU is never left idle by them), until a round has at most
+ * 4096 columns (256 in a call of 8 or more volumes; CR_ASYNC_MAX in the
+ * environment overrides it, 0 = never); the columns left are then reduced in
+ * one launch without rounds (the asynchronous tail).  If the reduction's
  * column arena (the stored columns) overflows, the whole pipeline is rerun with
  * a larger arena, at most three times (cr_stats.arena_reruns counts reruns);
  * CR_ARENA_ENTRIES in the environment fixes the first attempt's arena.
@@ -133,8 +136,10 @@ void cr_diagram_free(cr_context* ctx, cr_diagram* d);
  *                   for every image, CR_ERR_OUT_OF_MEMORY (the column arena of
  *                   the degree-1 reduction ran out) or CR_ERR_INTERNAL.
  * Pixel indices index `packed`.  Never synchronises and never stops short of a
- * complete reduction: it enqueues a fixed budget of reduction rounds, then one
- * workgroup that runs the rounds still needed, if any, to the end.  When the
+ * complete reduction: it enqueues a fixed budget of reduction rounds (rounds
+ * return at once once the columns are few enough for the asynchronous tail, or
+ * none are left), then the tail, which reduces the columns still left to the
+ * end in one launch.  When the
  * device-side row count exceeds capacity the rows beyond it are dropped and
  * the total in pair_offsets[n_images] tells the capacity needed.  The column
  * arena holds max(the context's arena, 16 entries per pixel) 64-bit entries;
@@ -247,7 +252,7 @@ typedef struct cr_stats {
   int64_t arena_used;   /* 64-bit entries of column storage used by the reduction */
   int64_t red_adds;     /* column additions performed by the reduction */
   int64_t red_merged;   /* list entries read by those additions */
-  int64_t red_rounds;   /* rounds of the degree-1 reduction (plain call) */
+  int64_t red_rounds;   /* rounds of the degree-1 reduction before its asynchronous tail (plain call) */
   int64_t arena_reruns; /* plain calls on this context that reran with a larger column arena */
   int64_t scratch_bytes; /* device scratch the context owns now (0 until a call needs it) */
   int64_t tuning_from_cache; /* 1 if the last batched call ran with a CR_TUNE_CACHE entry */
@@ -285,7 +290,8 @@ typedef struct cr_tuning {
                            batched call it applies to the first 64 rounds only. */
   int32_t group_max;    /* ... a round of at most this many long columns runs one workgroup
                            per column; 0 = automatic (256 for a call of 8 or more volumes,
-                           else 1024) */
+                           else 1024).  Rounds small enough for the asynchronous tail do
+                           not run at all. */
   int32_t narrow_min;   /* ... a round of at least this many long columns runs the narrow
                            wavefront configuration; 0 = automatic (2048 for a call of 8 or
                            more volumes, else 8192) */

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <algorithm>
 #include <cstdlib>
+#include <cstddef>
 #include <cstdio>
 #include <fstream>
 #include <functional>
@@ -42,7 +43,6 @@ void launch_img_offsets(const uint32_t* cnt, const uint32_t* img_status, const S
                         int nimg, int64_t* offsets, int32_t* status, hipStream_t s);
 void launch_backward(const int64_t* bpix, const int64_t* dpix, const float* gb, const float* gd, int64_t n,
                      float* grad, int64_t n_pixels, uint32_t* bad, hipStream_t s);
-void launch_check_empty(const unsigned long long* count, Status* st, hipStream_t s);
 void launch_lifetime(const int32_t* dim, const float* birth, const float* death, const int64_t* loc, int64_t n,
                      float* out, int64_t n_pixels, int skip_missing, uint32_t* bad, hipStream_t s);
 void launch_pixel_coords(const int64_t* pixel, int64_t n, int64_t base, const int64_t ext[3], int32_t* xyz,
@@ -215,8 +215,9 @@ uint64_t noalloc_arena(const Problem& pb) {
   return env ? env : std::max<uint64_t>(1ull << 16, ARENA_PER_PIXEL * pb.P);
 }
 
-// counters block: surv_count, dim_count[4], cand_count, arena_top, lists[4], wave work counter
-enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* six words */, C_WORK = 13, C_WORDS = 14 };
+// counters block: surv_count, dim_count[4], cand_count, arena_top, lists[4], wave work counter,
+// arena offset at the start of the asynchronous tail
+enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* six words */, C_WORK = 13, C_BASE = 14, C_WORDS = 15 };
 
 // A 1D signal lies on one line of the grid (Sec. 2): it runs as a 1 x n image,
 // with the 2D launch parameters.
@@ -370,22 +371,22 @@ void mark(cr_context* ctx, int i, hipStream_t s) {
   if (ctx->timing) (void)hipEventRecord(ctx->ev[i], s);
 }
 
-// Rounds of the degree-1 reduction.  With host synchronisation allowed (plain
-// call) the host checks the active count every ROUND_BATCH rounds; otherwise a
-// fixed budget of rounds is enqueued (rounds with an empty list return at once),
-// followed by one workgroup that runs whatever rounds remain to the end (the
-// finisher; it returns at once when the budget sufficed).  Columns that yield
-// (wave_yield) take more rounds, so within the budget they yield only in the
-// first YIELD_ROUNDS rounds; the rest run every column to its end as without
-// yields.
+// Rounds of the degree-1 reduction, then its asynchronous tail.  With host
+// synchronisation allowed (plain call) the host checks every ROUND_BATCH rounds
+// whether the rounds are over (no column left, or a round left to the tail);
+// otherwise a fixed budget of rounds is enqueued (rounds return at once when
+// their lists are empty or were left to the tail).  The tail then reduces
+// whatever is left, in one launch (it returns at once when nothing is).
+// Columns that yield (wave_yield) take more rounds, so within the budget they
+// yield only in the first YIELD_ROUNDS rounds.
 constexpr int ROUND_BATCH = 4;
 constexpr int ROUND_BUDGET = 128;
 constexpr int YIELD_ROUNDS = 64;
 constexpr int ROUND_LIMIT = 4096;
 
 // side_start, if given, is called once after the first SIDE_AFTER rounds have
-// been enqueued (or when the reduction ends sooner), to start work beside the
-// latency-bound later rounds.
+// been enqueued (or when the rounds end sooner), to start work beside the
+// latency-bound later rounds and the tail.
 constexpr int SIDE_AFTER = 20;
 
 cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts,
@@ -393,16 +394,16 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
   ctx->rounds = 0;
   if (!ctx->sync_allowed) {
     // CR_ROUND_BUDGET / CR_YIELD_ROUNDS override the budget (e.g. small, so that
-    // the finishing workgroup does most of the reduction of a small batch)
+    // the tail does most of the reduction of a small batch)
     const int budget = (int)std::max<uint64_t>(1, std::min<uint64_t>(env_u64("CR_ROUND_BUDGET", ROUND_BUDGET), 1 << 16));
     const int yields = (int)std::min<uint64_t>(env_u64("CR_YIELD_ROUNDS", YIELD_ROUNDS), (uint64_t)budget);
     launch_h1_rounds(RGRID, R, lists, counts, 0, budget, yields, s);
-    launch_h1_finish(R, lists, counts, budget, s);  // the rounds beyond the budget, if any
+    launch_h1_async(R, lists, counts, budget, s);
     return CR_OK;
   }
   // Batches of rounds are enqueued one ahead of the check: the counts left by
   // batch k-1 are read while batch k runs, so the GPU does not idle during the
-  // host's round trip; a finished reduction leaves batch k's rounds empty.
+  // host's round trip; rounds after the end return at once.
   cr_status rc = ensure_stage(ctx, 64);
   if (rc != CR_OK) return rc;
   for (hipEvent_t& e : ctx->round_ev)
@@ -413,6 +414,7 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
     side_started = true;
     return side_start();
   };
+  int round_end = ROUND_LIMIT;
   for (int k = 0; k * ROUND_BATCH < ROUND_LIMIT; ++k) {
     const int r = k * ROUND_BATCH;
     launch_h1_rounds(RGRID, R, lists, counts, r, ROUND_BATCH, ROUND_LIMIT, s);
@@ -423,21 +425,25 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
     const int cur = (r + ROUND_BATCH) % 3;  // the count pair the next round reads
     char* slot = ctx->host_stage + 32 * (k & 1);
     HIP_TRY(hipMemcpyAsync(slot, counts + 2 * cur, 16, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(slot + 16, &R.st->abort, 4, hipMemcpyDeviceToHost, s));
+    static_assert(offsetof(Status, tail_round) == offsetof(Status, abort) + 4, "abort and tail_round are adjacent");
+    HIP_TRY(hipMemcpyAsync(slot + 16, &R.st->abort, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(ctx->round_ev[k & 1], s));
     if (k == 0) continue;
     HIP_TRY(hipEventSynchronize(ctx->round_ev[(k - 1) & 1]));
     const char* prev = ctx->host_stage + 32 * ((k - 1) & 1);
     unsigned long long left[2] = {0, 0};
-    uint32_t ab = 0;
+    uint32_t ab[2] = {0, 0};
     std::memcpy(left, prev, 16);
-    std::memcpy(&ab, prev + 16, 4);
+    std::memcpy(ab, prev + 16, 8);
     ctx->rounds = r;
-    if ((left[0] == 0 && left[1] == 0) || ab) return start_side();
+    if ((left[0] == 0 && left[1] == 0) || ab[0] || ab[1]) {
+      round_end = r + ROUND_BATCH;
+      break;
+    }
   }
   rc = start_side();
   if (rc != CR_OK) return rc;
-  launch_check_empty(counts + 2 * (ROUND_LIMIT % 3), R.st, s);
+  launch_h1_async(R, lists, counts, round_end, s);
   return CR_OK;
 }
 
@@ -604,6 +610,14 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     // column, which then does not yield (256^3 degree 1 62.0 -> 60.3 ms;
     // larger thresholds measured erratic: 4 and 16 slower, 8 faster)
     if (const char* v = getenv("CR_YIELD_FEW")) R.yield_few = (uint32_t)strtoul(v, nullptr, 10);
+    // rounds of at most this many columns are left to the asynchronous tail
+    // (CR_ASYNC_MAX overrides; 0 keeps rounds to the end).  Measured: the 256^3
+    // volume 64.0 ms without the tail, 59.8 / 58.9 / 59.3 ms with 2048 / 4096 /
+    // 8192; the 32 x 128^3 batch 47.9 ms without, 44.2 / 45.3 / 56.1 ms with
+    // 256 / 1024 / 4096 (its tail holds the columns of many volumes)
+    R.async_max = many ? 256u : 4096u;
+    if (const char* v = getenv("CR_ASYNC_MAX")) R.async_max = (uint32_t)strtoul(v, nullptr, 10);
+    R.async_base = &cnt[C_BASE];
     if (const char* v = getenv("CR_GROUP_CAP")) {
       const unsigned long f = strtoul(v, nullptr, 10);
       R.group_cap = (uint32_t)(f < FRONT_CAP_MIN ? FRONT_CAP_MIN : (f > 4096 ? 4096 : f));

@@ -40,7 +40,8 @@ struct Status {
   uint32_t internal;       // an invariant of the algorithm failed (bug guard)
   uint32_t iter_cap;       // a bounded loop hit its iteration cap
   uint32_t abort;          // set together with any of the above: stop early
-  uint32_t pad;
+  uint32_t tail_round;     // degree-1 reduction: 1 + the round whose columns went to the
+                           // asynchronous tail (0: none yet)
   unsigned long long adds; // column additions performed by the reduction
   unsigned long long merged;  // list entries read by those additions
 };

@@ -41,6 +41,10 @@ struct RedCtx {
   uint32_t* yield_list;    // the next round's long list and its count (set per round)
   unsigned long long* yield_count;
   uint32_t round;          // the round of this launch
+  uint32_t async_max;      // a round (after the first) of at most this many columns, and every
+                           // later one, is left to the asynchronous tail (0: never)
+  unsigned long long* async_base;  // arena offset at the start of the tail (lists from there on
+                                   // were written during it)
 };
 
 // Proposal word of column c in round r: the round in the high half (a later
@@ -71,10 +75,10 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
 // Columns yield after R.wave_yield additions only in rounds below yield_rounds.
 void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round0,
                       int nrounds, int yield_rounds, hipStream_t s);
-// One workgroup that runs the rounds from round0 on (lists and counts as
-// above) until a round has no columns: the end of a reduction enqueued with a
-// fixed budget of rounds.
-void launch_h1_finish(const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round0, hipStream_t s);
+// The asynchronous tail: every column still listed after the rounds -- those of
+// the round recorded in R.st->tail_round, else of round round_end (the round
+// after the last one enqueued) -- reduced to its end without round barriers.
+void launch_h1_async(const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round_end, hipStream_t s);
 void launch_h1_emit(int grid, const RedCtx& R, const EmitCtx& E, hipStream_t s);
 
 }  // namespace cr

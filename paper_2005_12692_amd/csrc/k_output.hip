@@ -140,15 +140,6 @@ __global__ void k_pixel_coords(const int64_t* __restrict__ pixel, int64_t n, int
   }
 }
 
-// Raises the iteration flag if a pair of reduction lists is still non-empty.
-__global__ void k_check_empty(const unsigned long long* count, Status* st) {
-  if (count[0] || count[1]) raise_flag(st, &st->iter_cap);
-}
-
-void launch_check_empty(const unsigned long long* count, Status* st, hipStream_t s) {
-  k_check_empty<<<1, 1, 0, s>>>(count, st);
-}
-
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   if (!n) return;
   uint64_t blocks = (n + 255) / 256;

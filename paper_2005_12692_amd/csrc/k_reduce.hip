@@ -348,6 +348,16 @@ __device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64
   }
 }
 
+// Whether a round's kernels leave its columns to the asynchronous tail: a
+// round after the first with at most async_max columns (its commit records it
+// in st->tail_round), and every round after that one.  ct: the round's counts.
+__device__ __forceinline__ bool in_tail(const RedCtx& R, const unsigned long long* ct, int first) {
+  if (first || R.async_max == 0) return false;
+  if (R.st->tail_round) return true;
+  const uint64_t n = ct[0] + ct[1];
+  return n > 0 && n <= R.async_max;
+}
+
 // Thread-mode round.  Round 0 runs every column that is not cleared; later
 // rounds run the short-column list unless it is short enough for wave mode.
 template <int TC>
@@ -357,7 +367,7 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
                                                    unsigned long long* __restrict__ n_short_next,
                                                    uint32_t* __restrict__ long_next,
                                                    unsigned long long* __restrict__ n_long_next) {
-  if (aborted(R.st)) return;
+  if (aborted(R.st) || in_tail(R, n_list, first)) return;
   const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
   const uint64_t n = first ? R.dim_count[2] : *n_list;
   if (n == 0 || (!first && n <= R.wave_short)) return;
@@ -808,9 +818,17 @@ __device__ __forceinline__ uint64_t w_alloc(const RedCtx& R, uint64_t n, int lan
   return rdlane64(off, 0);
 }
 
+// Waits for this wavefront's outstanding vector memory operations.  Registers
+// loaded from global memory in a loop body are otherwise taken as possibly in
+// flight wherever the loop reads them, and the compiler waits there for every
+// load issued since -- in the pivot search, for the loads started ahead for
+// the next pivot, which then save nothing.
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0xF70); }  // vmcnt(0)
+
 __device__ __forceinline__ void tail_window(Tail& t, int lane) {
   t.b = t.n > 64 ? t.n - 64 : 0;
   t.w = (t.b + (uint32_t)lane < t.n) ? t.v[t.b + lane] : 0;
+  wait_vm();  // read at once by the pivot search
 }
 __device__ __forceinline__ void tail_set(Tail& t, const uint64_t* v, uint32_t n, int lane) {
   t.v = v;
@@ -967,6 +985,9 @@ __device__ __forceinline__ float rdlane_f(float v, uint32_t i) {
 // column and a workgroup per column.
 template <class C>
 struct WaveOps {
+  static constexpr bool kAsync = false;  // the asynchronous tail (claims by compare-and-swap)
+  // whether the list at this arena offset was stored during the asynchronous tail
+  __device__ static bool fresh(const RedCtx&, uint32_t) { return false; }
   __device__ static bool leader(int lane) { return lane == 0; }
   // the round of this launch and the additions after which a column yields
   __device__ static uint32_t round(const RedCtx& R) { return cold(R)->round; }
@@ -1059,23 +1080,25 @@ __device__ __forceinline__ LoadGroup load_group(const EdgeGeom& G, uint64_t e, u
 // Stores the column P ^ F ^ U ^ T as one arena list and records it for column
 // c with pivot key pv: with a claim word, c is proposed for that pivot;
 // without one (pv = YIELDED) c is appended to the next round's long list.
+// In the asynchronous tail (O::kAsync) nothing is recorded: the caller claims
+// the pivot.  Returns the list's arena offset, ~0 on failure.
 template <class O>
-__device__ __forceinline__ void store_column(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c,
-                                             uint64_t pv, uint64_t* claim_at, int lane) {
+__device__ __forceinline__ uint64_t store_column(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c,
+                                                 uint64_t pv, uint64_t* claim_at, int lane) {
   uint64_t off;
   uint32_t len;
   if (W.nf == 0 && W.U.n == 0 && W.T.n == 0) {  // the column is P
     off = O::alloc(R, S, (uint64_t)W.np + 1, lane);
-    if (off == ~0ull) return;
+    if (off == ~0ull) return off;
     p_stage(W, R.arena + off + 1, lane);
     len = W.np;
   } else {
-    if (!O::flush_p(R, S, W, lane)) return;
-    if (W.U.n && W.T.n && !O::push_front(R, S, W, lane)) return;
+    if (!O::flush_p(R, S, W, lane)) return ~0ull;
+    if (W.U.n && W.T.n && !O::push_front(R, S, W, lane)) return ~0ull;
     const Tail& G = W.T.n ? W.T : W.U;  // at most one of them is left with F
     const Tail& H = W.T.n ? W.U : W.T;
     off = O::alloc(R, S, (uint64_t)W.nf + G.n + H.n + 1, lane);
-    if (off == ~0ull) return;
+    if (off == ~0ull) return off;
     if (H.n) {
       len = O::merge_gg(S, G.v, G.n, H.v, H.n, R.arena + off + 1, lane);
     } else if (G.n) {
@@ -1087,17 +1110,34 @@ __device__ __forceinline__ void store_column(const RedCtx& R, const WaveBufs& S,
   }
   if (O::leader(lane)) {
     R.arena[off] = len;
-    const auto* K = cold(R);
-    K->col_ptr[c] = off;
-    K->piv[c] = pv;
-    if (claim_at) {
-      atomicMax(reinterpret_cast<unsigned long long*>(claim_at), claim_word(O::round(R), c));
-    } else {
-      const unsigned long long i = atomicAdd(K->yield_count, 1ull);
-      K->yield_list[i] = c;
+    if (!O::kAsync) {
+      const auto* K = cold(R);
+      K->col_ptr[c] = off;
+      K->piv[c] = pv;
+      if (claim_at) {
+        atomicMax(reinterpret_cast<unsigned long long*>(claim_at), claim_word(O::round(R), c));
+      } else {
+        const unsigned long long i = atomicAdd(K->yield_count, 1ull);
+        K->yield_list[i] = c;
+      }
     }
   }
+  return off;
 }
+
+// Where a column reduction starts: its stored list, and optionally the owner
+// word of one edge known better than a load of it could (hint_e = 0: none),
+// whose list this workgroup wrote itself when hint_own is set.
+struct ColStart {
+  uint64_t off, hint_e, hint_ow;
+  bool hint_own;
+};
+// How it ended (asynchronous tail): the pivot, the owner word seen for it (no
+// owner, or an owner not to the left) and that owner word's address.
+struct ColEnd {
+  uint64_t e, ow;
+  uint64_t* slot;
+};
 
 // Reduces column c for one round: until its pivot has no owner to its left,
 // then stores it and proposes it for its pivot; or, after wave_yield additions,
@@ -1105,9 +1145,13 @@ __device__ __forceinline__ void store_column(const RedCtx& R, const WaveBufs& S,
 // hold back the columns of every other image at the round's end.  In a round
 // of few columns (`few`: at most yield_few) there is nothing to run beside a
 // long column, so it does not yield.
+//
+// Returns the stored list's arena offset, ~0 when the reduction stopped on an
+// error (a flag is raised).
 template <class O>
-__device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c, uint64_t off2,
-                                              int lane, bool few) {
+__device__ __forceinline__ uint64_t reduce_column(const RedCtx& R, const WaveBufs& S, WState& W, uint32_t c,
+                                                  uint64_t off2, int lane, bool few, ColStart from,
+                                                  ColEnd* end = nullptr) {
   const int im = (int)uni((uint32_t)skey_img(R.L, uni64(cold(R)->skeys[off2 + c])));  // every edge lies in this image
   ImgDesc d = cold(R)->imgs[im];
 #pragma unroll
@@ -1131,7 +1175,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
   LoadGroup pf{0.0f, 0xFFu, NO_OWNER};  // the prefetched load groups and their three edges
   uint64_t pk0 = 0, pk1 = 0, pk2 = 0;
   {
-    const uint64_t off = uni64(cold(R)->col_ptr[c]);
+    const uint64_t off = uni64(from.off);
     const uint32_t len = uni((uint32_t)R.arena[off]);
     const uint64_t* src = R.arena + off + 1;
     W.np = 0;
@@ -1139,6 +1183,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
     tail_set(W.U, src, 0, lane);
     if (len <= PCAP) {  // into P
       p_load(W, src, len, lane);
+      wait_vm();
       W.nf = 0;
       tail_set(W.T, src, 0, lane);
     } else if (len <= S.cap) {
@@ -1153,18 +1198,20 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
   const uint32_t ylim = uni(few || !O::wave_yield(R) ? 0xFFFFFFFFu : O::wave_yield(R));
   uint64_t out_piv = YIELDED;   // what is stored when the loop ends: the pivot and its
   uint64_t* claim_at = nullptr;  // claim word, or YIELDED and none after wave_yield additions
+  uint64_t out_ow = NO_OWNER;
+  const uint64_t hint_e = uni64(from.hint_e), hint_ow = uni64(from.hint_ow);
   for (uint32_t it = 0;; ++it) {
     if (it >= RED_ITER_CAP) {
       if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->iter_cap);
-      return;
+      return ~0ull;
     }
-    if ((it & 63) == 63 && O::aborted(R, S)) return;
+    if ((it & 63) == 63 && O::aborted(R, S)) return ~0ull;
     if (it >= ylim) break;
     int where = 0;
     const uint64_t e = w_pivot(S, W, lane, &where);
     if (e == 0) {  // a zero column: impossible after clearing
       if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->internal);
-      return;
+      return ~0ull;
     }
     // the pivot edge: Khalimsky coordinates, axis, anchor pixel
     const uint32_t kidx = skey_kidx(R.L, e);
@@ -1173,7 +1220,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
     if ((e >> R.L.kb >> 32) != (kpre >> R.L.kb >> 32) || kz >= (uint32_t)d.K[0] ||
         ((kz & 1) + (ky & 1) + (kx & 1)) != 1) {  // not an edge of this image: a broken invariant
       if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->internal);
-      return;
+      return ~0ull;
     }
     const int ax = (kz & 1) ? 0 : ((ky & 1) ? 1 : 2);
     const int b1 = ax == 2 ? 1 : 2;  // the larger of the two other axes
@@ -1188,7 +1235,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
     if (hit >= 0) lb = 16u * (uint32_t)hit;
     else lg = load_group(G, e, (uint32_t)lane);
     const uint32_t code = uni((uint32_t)__builtin_amdgcn_readlane((int)lg.code, (int)lb));
-    const uint64_t ow = rdlane64(lg.ow, lb);
+    const uint64_t ow = e == hint_e ? hint_ow : rdlane64(lg.ow, lb);
     const float pv = (lg.praw != lg.praw) ? INFINITY : canon(lg.praw);
     pk0 = pk1 = pk2 = 0;
     w_count(W.adds, 1, lane);
@@ -1205,7 +1252,7 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
       const uint64_t ka1 = kpre | ((uint64_t)ord_of(fmaxf(v1, w1)) << R.L.kb) | (kidx + kax + kb);
       if (kw >= e || ka0 >= e || ka1 >= e) {  // e must be the latest facet of s
         if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->internal);
-        return;
+        return ~0ull;
       }
       w_pop(W, where, lane);
       // the next pivot is often one of these three edges: start their loads
@@ -1217,12 +1264,16 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
         pk1 = ka0;
         pk2 = ka1;
       }
-      if (!O::insert3(R, S, W, kw, ka0, ka1, lane)) return;
+      if (!O::insert3(R, S, W, kw, ka0, ka1, lane)) return ~0ull;
       continue;
     }
     const int32_t o = ow == NO_OWNER ? -1 : (int32_t)(ow >> 32);
     if (o >= 0 && (uint32_t)o < c) {  // add the column of o (its top key is e)
       const uint64_t* q = R.arena + (uint32_t)ow;
+      // a list stored during the asynchronous tail, by a workgroup that may run
+      // on another XCD: see its writes (the owner word was released after them)
+      if (O::fresh(R, (uint32_t)ow) && !(from.hint_own && e == hint_e))
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       const uint64_t head = q[lane];  // length word and the first 63 keys
       const uint32_t len = (uint32_t)rdlane64(head, 0);
       const uint32_t m = len - 1;     // keys below e
@@ -1232,20 +1283,29 @@ __device__ __forceinline__ void reduce_column(const RedCtx& R, const WaveBufs& S
         wsync();
         w_p_add(S, W, S.hx, m, lane);
       } else if (!O::owner_add(R, S, W, q + 1, m, lane)) {
-        return;
+        return ~0ull;
       }
       continue;
     }
-    if ((uint32_t)o == c) {
+    // an active column owns nothing; in the tail an owner word read with a
+    // plain load may be stale, which the claim's compare-and-swap corrects
+    if ((uint32_t)o == c && !O::kAsync) {
       if (lane == 0) raise_flag(cold(R)->st, &cold(R)->st->internal);
-      return;
+      return ~0ull;
     }
     // store P ^ F ^ U ^ T and propose c for e
     out_piv = e;
-    claim_at = &cold(R)->claim[3 * d.pix_off + slot];
+    out_ow = ow;
+    claim_at = O::kAsync ? const_cast<uint64_t*>(ownp) + slot : &cold(R)->claim[3 * d.pix_off + slot];
     break;
   }
-  store_column<O>(R, S, W, c, out_piv, claim_at, lane);
+  const uint64_t off = store_column<O>(R, S, W, c, out_piv, claim_at, lane);
+  if (end) {
+    end->e = out_piv;
+    end->ow = out_ow;
+    end->slot = claim_at;
+  }
+  return off;
 }
 
 // Wave-mode round over the long-column list (and the short list when it has at
@@ -1261,7 +1321,7 @@ __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uin
                                                              const unsigned long long* __restrict__ n_l,
                                                              uint32_t front_cap) {
   extern __shared__ __align__(16) uint64_t lds_words[];
-  if (aborted(R.st)) return;
+  if (aborted(R.st) || in_tail(R, n_s, 0)) return;
   const uint64_t nl = uni64(*n_l), ns0 = uni64(*n_s);
   const uint64_t ns = ns0 <= R.wave_short ? ns0 : 0;
   if (nl + ns <= R.group_max || (nl + ns >= R.narrow_min) != (C::XN == NarrowCfg::XN)) return;
@@ -1286,7 +1346,7 @@ __global__ __launch_bounds__(64 * WPB) void k_red_round_wave(RedCtx R, const uin
     li = rdlane64(li, 0);
     if (li >= nl + ns || aborted(R.st)) break;
     const uint32_t c = uni(li < nl ? list_l[li] : list_s[li - nl]);
-    reduce_column<WaveOps<C>>(R, S, W, c, off2, lane, few);
+    reduce_column<WaveOps<C>>(R, S, W, c, off2, lane, few, ColStart{cold(R)->col_ptr[c], 0, 0, false});
     wsync();
   }
   if (lane == 0 && W.adds) {  // lane 0 holds the counts
@@ -1317,7 +1377,7 @@ constexpr uint32_t GXN = 4 * GNW * 64 * GP_TAIL;  // stage words: one ring of fo
 static_assert(2 * 4 * GNW * 64 * GP_GG == GXN, "the two rings of an arena-arena merge fill the stage");
 constexpr uint32_t GPRIV = PCAP + 64 + PCAP;  // the leader's ps, hx, po
 
-enum GOp : uint32_t { G_END = 0, G_MERGE_LDS, G_MERGE_TAIL, G_MERGE_TAIL_LDS, G_MERGE_GG, G_COPY_IN, G_COPY_OUT };
+enum GOp : uint32_t { G_END = 0, G_MERGE_LDS, G_MERGE_TAIL, G_MERGE_TAIL_LDS, G_MERGE_GG, G_COPY_IN, G_COPY_OUT, G_FENCE };
 // An operation for the whole group: LDS operands are word offsets from the
 // start of the group's LDS, arena operands are addresses.
 struct GDesc {
@@ -1517,6 +1577,11 @@ __device__ __noinline__ uint32_t g_run(const WaveBufs& S, uint32_t op, uint32_t 
       rb.advance(ib);
     });
   }
+  if (op == G_FENCE) {  // every wavefront's global stores have reached the L2 (vmcnt(0))
+    __builtin_amdgcn_s_waitcnt(0xF70);
+    __syncthreads();
+    return 0;
+  }
   if (op == G_COPY_IN) {
     const uint64_t* src = reinterpret_cast<const uint64_t*>(a);
     for (uint32_t i = threadIdx.x; i < na; i += GNW * 64) L[out + i] = src[i];
@@ -1627,6 +1692,8 @@ __device__ __forceinline__ bool g_insert3(const RedCtx& R, const WaveBufs& S, WS
 
 // The leader's side of the column steps.
 struct GroupOps {
+  static constexpr bool kAsync = false;
+  __device__ static bool fresh(const RedCtx&, uint32_t) { return false; }
   __device__ static bool leader(int lane) { return lane == 0; }
   __device__ static uint32_t round(const RedCtx& R) { return cold(R)->round; }
   __device__ static uint32_t wave_yield(const RedCtx& R) { return cold(R)->wave_yield; }
@@ -1675,6 +1742,7 @@ __global__ __launch_bounds__(64 * GNW) void k_red_round_group(RedCtx R, const ui
                                                              const unsigned long long* __restrict__ n_l,
                                                              uint32_t front_cap) {
   extern __shared__ __align__(16) uint64_t lds_words[];
+  if (in_tail(R, n_s, 0)) return;
   const uint64_t nl = uni64(*n_l), ns0 = uni64(*n_s);
   const uint64_t ns = ns0 <= R.wave_short ? ns0 : 0;
   if (nl + ns == 0 || nl + ns > R.group_max) return;
@@ -1707,7 +1775,7 @@ __global__ __launch_bounds__(64 * GNW) void k_red_round_group(RedCtx R, const ui
     li = rdlane64(li, 0);
     if (li >= nl + ns || aborted(R.st)) break;
     const uint32_t c = uni(li < nl ? list_l[li] : list_s[li - nl]);
-    reduce_column<GroupOps>(R, S, W, c, off2, lane, few);
+    reduce_column<GroupOps>(R, S, W, c, off2, lane, few, ColStart{cold(R)->col_ptr[c], 0, 0, false});
     wsync();
   }
   if (lane == 0) G->desc.op = G_END;
@@ -1780,6 +1848,10 @@ __global__ void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t, cons
                              int first, uint32_t* next_t, uint32_t* next_b, unsigned long long* __restrict__ n_next,
                              unsigned long long* __restrict__ n_clear) {
   if (aborted(R.st)) return;
+  if (in_tail(R, n_t, first)) {  // nothing proposed; the counts stay for the tail
+    if (blockIdx.x == 0 && threadIdx.x == 0 && R.st->tail_round == 0) R.st->tail_round = R.round + 1;
+    return;
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     n_clear[0] = 0;
     n_clear[1] = 0;
@@ -1791,83 +1863,141 @@ __global__ void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t, cons
                (uint64_t)gridDim.x * blockDim.x, next_t, next_b, n_next);
 }
 
-// ---- the end of a batched reduction ------------------------------------------
+// ---- the asynchronous tail -------------------------------------------------------
 //
-// A batched call cannot ask the host how many rounds remain, so it enqueues a
-// fixed budget of rounds and then this kernel: one workgroup that runs the
-// rounds still needed (none, usually) to the end.  Each round it reduces every
-// listed column one wavefront at a time without yields (wave mode, wide
-// configuration), then commits them, until a round's lists are empty.  The
-// round number and the yield limit of the columns come from here instead of
-// the kernel arguments.
-constexpr uint32_t FINISH_ROUND_CAP = 4096;  // as the plain call's round limit
-constexpr uint32_t FINISH_FRONT_CAP = 2048;  // front list of the finisher (leaves LDS for its own words)
-__shared__ uint32_t fin_round_lds;
-__shared__ unsigned long long fin_work_lds;
+// In rounds of few columns, every round waits for its longest column, and a
+// column that lost a claim waits for the next round.  The tail reduces the
+// columns still listed without rounds: each workgroup (eight wavefronts, as in
+// group mode) takes a listed column and reduces it to its end -- adding, while
+// the pivot is owned by a column to its left, that column's stored list -- and
+// then claims the pivot's owner word with a compare-and-swap:
+//   * the word was free: the column owns the pivot;
+//   * it held a column to the right: the column owns it, and the displaced one
+//     (parked as an owner until then, so active nowhere else) is reduced next
+//     by the same workgroup, starting with the new owner's list;
+//   * it changed meanwhile to a column to the left: the column adds that one
+//     and goes on.
+// An owner word only ever names a column holding that pivot, and its list (a
+// sum of columns no further right, immutable) is a valid addition for every
+// column to the right of it; a claim fails only when another one succeeded.  So
+// the tail ends in a reduced matrix with the pivots of the sequential
+// reduction, in any order of events.  Owner words are read with plain loads
+// while reducing: a stale one costs at most a failed claim, whose returned word
+// is then used instead.  A list stored during the tail reaches the device's
+// L2 (every wavefront waits for its stores) and is written back from there
+// (release) before its owner word is swapped in, and a reader acquires before
+// reading it.
+__shared__ uint32_t async_base_lds;
 
-template <class C>
-struct FinishOps : WaveOps<C> {
-  __device__ static uint32_t round(const RedCtx&) { return fin_round_lds; }
+struct AsyncOps : GroupOps {
+  static constexpr bool kAsync = true;
   __device__ static uint32_t wave_yield(const RedCtx&) { return 0u; }
+  __device__ static bool fresh(const RedCtx&, uint32_t off) { return off >= async_base_lds; }
 };
 
+// The arena offset where the tail starts.
+__global__ void k_red_async_base(RedCtx R) { *R.async_base = *R.arena_top; }
+
 // R must stay the first parameter (see cold()).
-template <class C>
-__global__ __launch_bounds__(64 * WPB) void k_red_finish(RedCtx R, uint32_t* __restrict__ l0, uint32_t* __restrict__ l1,
-                                                        uint32_t* __restrict__ l2, uint32_t* __restrict__ l3,
-                                                        unsigned long long* __restrict__ counts, uint32_t round0,
-                                                        uint32_t front_cap) {
+__global__ __launch_bounds__(64 * GNW) void k_red_async(RedCtx R, const uint32_t* __restrict__ l0,
+                                                       const uint32_t* __restrict__ l1,
+                                                       const uint32_t* __restrict__ l2,
+                                                       const uint32_t* __restrict__ l3,
+                                                       const unsigned long long* __restrict__ counts,
+                                                       uint32_t round_end, uint32_t front_cap) {
   extern __shared__ __align__(16) uint64_t lds_words[];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint64_t* base = lds_words + (size_t)wv * wave_lds_words<C>(front_cap);
+  // what every thread reads before the split into leader and helpers must be
+  // the same for all of them: words that no kernel running now writes
+  const uint32_t tr = R.st->tail_round;
+  const uint32_t r = tr ? tr - 1 : round_end;  // the round whose lists are left
+  const unsigned long long* ct = counts + 2 * (r % 3);
+  const uint64_t ns = uni64(ct[0]), nl = uni64(ct[1]);
+  if (ns + nl == 0) return;
+  const uint32_t* list_s = (r & 1) ? l2 : l0;
+  const uint32_t* list_l = (r & 1) ? l3 : l1;
+  const int lane = threadIdx.x & 63;
   WaveBufs S;
   S.cap = front_cap;
-  S.F0 = base;
-  S.F1 = base + S.cap;
-  S.X = base + 2 * (size_t)S.cap;
-  S.ps = S.X + C::XN;
-  S.hx = S.X;
-  S.po = nullptr;
+  S.F0 = lds_words;
+  S.F1 = S.F0 + S.cap;
+  S.X = S.F1 + S.cap;
+  S.ps = S.X + GXN;
+  S.hx = S.ps + PCAP;
+  S.po = S.hx + 64;
+  GroupShared* G = gshared(S);
+  if (threadIdx.x >= 64) {  // helpers, as in group mode
+    for (;;) {
+      __syncthreads();
+      const uint32_t op = uni(G->desc.op);
+      if (op == G_END) return;
+      g_run(S, op, uni(G->desc.na), uni(G->desc.nb), uni64(G->desc.a), uni64(G->desc.b), uni64(G->desc.out), lane);
+    }
+  }
+  if (lane == 0) async_base_lds = (uint32_t)*R.async_base;
+  wsync();
   const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
   WState W;
   W.adds = 0;
   W.merged = 0;
-  for (uint32_t r = round0;; ++r) {
-    __syncthreads();
-    unsigned long long* ct = counts + 2 * (r % 3);
-    unsigned long long* cnx = counts + 2 * ((r + 1) % 3);
-    unsigned long long* cclr = counts + 2 * ((r + 2) % 3);
-    const uint64_t nt = uni64(__hip_atomic_load(ct, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    const uint64_t nb = uni64(__hip_atomic_load(ct + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    if (nt + nb == 0 || aborted(R.st)) break;
-    if (r - round0 >= FINISH_ROUND_CAP) {
-      if (threadIdx.x == 0) raise_flag(R.st, &R.st->iter_cap);
+  constexpr uint32_t NONE = 0xFFFFFFFFu;
+  uint32_t c = NONE;
+  ColStart from{0, 0, 0, false};
+  for (;;) {
+    if (c == NONE) {  // the next listed column
+      unsigned long long li = 0;
+      if (lane == 0) li = atomicAdd(R.work, 1ull);
+      li = rdlane64(li, 0);
+      if (li >= nl + ns || aborted(R.st)) break;
+      c = uni(li < nl ? list_l[li] : list_s[li - nl]);
+      from = ColStart{uni64(R.col_ptr[c]), 0, 0, false};
+    }
+    ColEnd end{0, 0, nullptr};
+    const uint64_t off = reduce_column<AsyncOps>(R, S, W, c, off2, lane, true, from, &end);
+    if (off == ~0ull) break;  // a raised flag: the call reports it
+    if (end.slot == nullptr) {  // cannot happen: the tail's columns do not yield
+      if (lane == 0) raise_flag(R.st, &R.st->internal);
       break;
     }
-    __syncthreads();  // every thread has read the counts before they are cleared below
-    if (threadIdx.x == 0) {
-      fin_round_lds = r;
-      fin_work_lds = 0;
-      cclr[0] = 0;  // the pair the round after next fills
-      cclr[1] = 0;
+    g_issue(S, G_FENCE, 0, 0, 0, 0, 0, lane);
+    const uint64_t mine = ((uint64_t)c << 32) | off;
+    uint64_t old = 0;
+    uint32_t lost = 0;
+    if (lane == 0) {
+      __hip_atomic_store(&R.piv[c], end.e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&R.col_ptr[c], off, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint64_t seen = end.ow;
+      for (;;) {
+        uint64_t cur = seen;
+        // release: the list (and piv, col_ptr) before the word; acquire where a
+        // list named by the returned word is read
+        if (__hip_atomic_compare_exchange_strong(end.slot, &cur, mine, __ATOMIC_RELEASE, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)) {
+          old = seen;
+          break;
+        }
+        if (cur != NO_OWNER && (uint32_t)(cur >> 32) < c) {  // a column to the left got there first
+          old = cur;
+          lost = 1;
+          break;
+        }
+        seen = cur;
+      }
     }
-    __syncthreads();
-    const uint32_t* lt = (r & 1) ? l2 : l0;
-    const uint32_t* lb = (r & 1) ? l3 : l1;
-    for (;;) {
-      unsigned long long li = 0;
-      if (lane == 0) li = atomicAdd(&fin_work_lds, 1ull);
-      li = rdlane64(li, 0);
-      if (li >= nt + nb || aborted(R.st)) break;
-      const uint32_t c = uni(li < nb ? lb[li] : lt[li - nb]);
-      reduce_column<FinishOps<C>>(R, S, W, c, off2, lane, true);
-      wsync();
+    old = uni64(rdlane64(old, 0));
+    lost = uni((uint32_t)__builtin_amdgcn_readlane((int)lost, 0));
+    if (lost) {  // add that column (the pivot's word is known) and go on
+      from = ColStart{off, end.e, old, false};
+    } else if (old != NO_OWNER) {  // reduce the displaced column next, from its stored list
+      if ((uint32_t)old >= async_base_lds) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const uint32_t j = (uint32_t)(old >> 32);
+      from = ColStart{(uint32_t)old, end.e, mine, true};
+      c = j;
+    } else {
+      c = NONE;
     }
-    __threadfence();
-    __syncthreads();
-    commit_range(R, r, lt, nt, lb, nb, 0, threadIdx.x, blockDim.x, (r & 1) ? l0 : l2, (r & 1) ? l1 : l3, cnx);
-    __threadfence();
   }
+  if (lane == 0) G->desc.op = G_END;
+  __syncthreads();
   if (lane == 0 && W.adds) {
     atomicAdd(&R.st->adds, W.adds);
     atomicAdd(&R.st->merged, W.merged);
@@ -1931,6 +2061,8 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.yield_list = nullptr;
   R.yield_count = nullptr;
   R.round = 0;
+  R.async_max = 0;
+  R.async_base = nullptr;
   return R;
 }
 
@@ -1992,18 +2124,20 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
   }
 }
 
-void launch_h1_finish(const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round0, hipStream_t s) {
-  // the column state lives in the arena between rounds, so the finisher's front
-  // capacity need not be the wave kernels'
-  const uint32_t fcap = R.front_cap < FINISH_FRONT_CAP ? R.front_cap : FINISH_FRONT_CAP;
-  const size_t lds = WPB * 8 * wave_lds_words<WideCfg>(fcap);
-  static size_t lds_set = 0;
-  if (lds_set < lds) {
-    (void)hipFuncSetAttribute((const void*)k_red_finish<WideCfg>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    lds_set = lds;
+void launch_h1_async(const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round_end, hipStream_t s) {
+  int dev = 0, ncu = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const uint32_t gcap = R.group_cap < FRONT_CAP_GROUP_MAX ? R.group_cap : FRONT_CAP_GROUP_MAX;
+  const size_t glds = group_lds_bytes(gcap);
+  static size_t glds_set = 0;
+  if (glds_set < glds) {
+    (void)hipFuncSetAttribute((const void*)k_red_async, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds);
+    glds_set = glds;
   }
-  k_red_finish<WideCfg><<<1, 64 * WPB, lds, s>>>(R, lists[0], lists[1], lists[2], lists[3], counts, (uint32_t)round0,
-                                                 fcap);
+  k_red_async_base<<<1, 1, 0, s>>>(R);
+  k_red_async<<<ncu, 64 * GNW, glds, s>>>(R, lists[0], lists[1], lists[2], lists[3], counts, (uint32_t)round_end,
+                                          gcap);
 }
 
 void launch_h1_emit(int grid, const RedCtx& R, const EmitCtx& E, hipStream_t s) {

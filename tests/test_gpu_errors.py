@@ -8,7 +8,7 @@
   CR_ERR_OUT_OF_MEMORY with out->n == 0 and nothing allocated;
 * NaN anywhere gives CR_ERR_NAN_INPUT;
 * the batched call runs a reduction that outlasts its fixed budget of rounds to
-  the end (the finishing workgroup), reports an exhausted column arena for
+  the end (the asynchronous tail), reports an exhausted column arena for
   every image, and marks exactly the images whose rows exceed the capacity.
 """
 import ctypes
@@ -93,7 +93,7 @@ def _per_image(d, offs, i):
 
 @pytest.mark.parametrize("budget", ["1", "3"])
 def test_batched_runs_past_the_round_budget(budget, monkeypatch):
-    """With a budget of one or three rounds, the finishing workgroup runs the
+    """With a budget of one or three rounds, the asynchronous tail runs the
     rest of the reduction: every image equals the oracle's diagram, in the
     eager call and in two graph replays."""
     vols = _batch_volumes()

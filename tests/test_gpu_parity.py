@@ -162,23 +162,29 @@ def test_deterministic_repeat():
 
 
 WAVE_ENV = ("CR_LONG_LEN", "CR_YIELD_ITERS", "CR_WAVE_SHORT", "CR_FRONT_CAP", "CR_MID_CAP", "CR_NARROW_MIN",
-            "CR_NARROW_CAP", "CR_GROUP_MAX", "CR_GROUP_CAP", "CR_WAVE_YIELD")
+            "CR_NARROW_CAP", "CR_GROUP_MAX", "CR_GROUP_CAP", "CR_WAVE_YIELD", "CR_ASYNC_MAX")
 
 
 @pytest.mark.parametrize("setting", [
     # every column to wave mode after two additions; narrow configuration with a
     # tiny front list; wave columns stored and resumed every 3 additions
-    ("0", "2", "0", "4032", "8192", "0", "128", "0", "4096", "3"),
-    ("8", "8", "0", "4032", "8192", "1000000000", "256", "0", "4096", "0"),  # wide configuration only
+    ("0", "2", "0", "4032", "8192", "0", "128", "0", "4096", "3", "0"),
+    ("8", "8", "0", "4032", "8192", "1000000000", "256", "0", "4096", "0", "0"),  # wide configuration only
     # whole rounds in wave mode, tiny front and middle lists
-    ("0", "1", "1000000", "128", "300", "1000000000", "320", "0", "4096", "1"),
-    ("0", "1", "1000000", "128", "300", "0", "320", "0", "4096", "5"),
+    ("0", "1", "1000000", "128", "300", "1000000000", "320", "0", "4096", "1", "0"),
+    ("0", "1", "1000000", "128", "300", "0", "320", "0", "4096", "5", "0"),
     # the middle list folded into the tail at every push; all three configurations
-    ("4", "4", "64", "200", "0", "64", "200", "16", "128", "2"),
+    ("4", "4", "64", "200", "0", "64", "200", "16", "128", "2", "0"),
     # a workgroup per column in every wave-mode round: small lists, then the defaults
-    ("0", "1", "1000000", "128", "300", "1000000000", "256", "1000000000", "128", "1"),
-    ("0", "2", "0", "1024", "0", "1000000000", "256", "1000000000", "200", "0"),
-    ("16", "1024", "4096", "1024", "8192", "8192", "256", "1000000000", "4096", "16"),
+    ("0", "1", "1000000", "128", "300", "1000000000", "256", "1000000000", "128", "1", "0"),
+    ("0", "2", "0", "1024", "0", "1000000000", "256", "1000000000", "200", "0", "0"),
+    ("16", "1024", "4096", "1024", "8192", "8192", "256", "1000000000", "4096", "16", "0"),
+    # the asynchronous tail: after the first round (small lists, so that every
+    # merge runs in it), and after rounds of wave mode once at most 8 or 64
+    # columns are left
+    ("0", "1", "1000000", "128", "300", "1000000000", "256", "1000000000", "128", "1", "1000000000"),
+    ("0", "2", "0", "4032", "8192", "0", "128", "0", "4096", "3", "64"),
+    ("4", "4", "64", "200", "0", "64", "200", "16", "128", "2", "8"),
 ])
 def test_wave_mode_forced(setting):
     """Volumes whose columns are handed to the wavefront-per-column mode after a
@@ -219,12 +225,16 @@ def _mode_volumes():
 
 @pytest.mark.parametrize("setting", [
     # (long_len, yield_iters, wave_short, front_cap, mid_cap, narrow_min, narrow_cap, group_max, group_cap,
-    #  wave_yield)
-    None,                                                                                 # the defaults
-    ("0", "4", "1000000", "128", "256", "1000000000", "256", "1000000000", "128", "1"),   # group mode, small lists
-    ("0", "4", "1000000", "128", "0", "0", "128", "0", "4096", "7"),                      # narrow mode, small lists
-    ("8", "64", "1000000", "128", "512", "1000000000", "256", "0", "4096", "3"),          # wide mode, small lists
-    ("32", "16", "0", "4032", "100000", "1000000000", "256", "1000000000", "4096", "0"),  # large lists, group mode
+    #  wave_yield, async_max)
+    None,                                                                                      # the defaults
+    ("0", "4", "1000000", "128", "256", "1000000000", "256", "1000000000", "128", "1", "0"),   # group mode, small lists
+    ("0", "4", "1000000", "128", "0", "0", "128", "0", "4096", "7", "0"),                      # narrow mode, small lists
+    ("8", "64", "1000000", "128", "512", "1000000000", "256", "0", "4096", "3", "0"),          # wide mode, small lists
+    ("32", "16", "0", "4032", "100000", "1000000000", "256", "1000000000", "4096", "0", "0"),  # large lists, group mode
+    # the asynchronous tail after the first round, small lists; after wide-mode
+    # rounds with at most 32 columns left
+    ("0", "4", "1000000", "128", "256", "1000000000", "256", "1000000000", "128", "1", "1000000000"),
+    ("8", "64", "1000000", "128", "512", "1000000000", "256", "0", "4096", "3", "32"),
 ])
 def test_reduction_modes_larger(setting):
     """Volumes of 10^5 to 10^6 pixels with many long columns, each reduction mode forced
