@@ -98,9 +98,13 @@ cr_tuning default_tuning(int ndim) {
   t.grid = 2048;
   t.long_len = 32;
   t.yield_iters = 1024;
-  t.wave_short = 4096;
+  // with the asynchronous tail taking the last, latency-bound part of degree 1,
+  // shorter rounds pay before it: the 256^3 volume 58.7 ms per step with
+  // (wave_yield, wave_short) = (128, 4096), 55.0 with (64, 16384), 54.3 with
+  // (48, 65536); the 32-volume batch 44.4, 45.0, 46.6 ms
+  t.wave_short = 16384;
   t.front_cap = 1024;
-  t.wave_yield = 128;
+  t.wave_yield = 64;
   t.group_max = 0;   // automatic (by the number of images)
   t.narrow_min = 0;
   (void)ndim;
@@ -1438,9 +1442,9 @@ cr_status cr_autotune_batched(cr_context* ctx, int n_images, const float* packed
     if (coord == 1) vals = {512, 1024, 2048, 4096, 8192};
     if (coord == 2) vals = {512, 1024, 2048, 4032};
     if (coord == 3) vals = {8, 16, 32};
-    if (coord == 4) vals = {0, 4096, 65536, 1 << 30};
+    if (coord == 4) vals = {0, 4096, 16384, 65536, 1 << 30};
     if (coord == 5) vals = {16, 128, 1024};
-    if (coord == 6) vals = {0, 64, 128, 512};
+    if (coord == 6) vals = {0, 32, 64, 128};
     if (coord == 7) vals = {0, 128, 256, 1024};
     if (coord == 8) vals = {0, 2048, 8192};
     for (int v : vals) {
