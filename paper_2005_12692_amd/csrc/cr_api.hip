@@ -389,8 +389,8 @@ constexpr int YIELD_ROUNDS = 64;
 constexpr int ROUND_LIMIT = 4096;
 
 // side_start, if given, is called once after the first SIDE_AFTER rounds have
-// been enqueued (or when the rounds end sooner), to start work beside the
-// latency-bound later rounds and the tail.
+// been enqueued (or right after the tail when the rounds end sooner), to start
+// work beside the latency-bound later rounds and the tail.
 constexpr int SIDE_AFTER = 20;
 
 cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts,
@@ -445,10 +445,10 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
       break;
     }
   }
-  rc = start_side();
-  if (rc != CR_OK) return rc;
+  // the tail first: its workgroups (one per CU) are dispatched before the side
+  // stream's degree-0 kernels, which fill the remaining wave slots beside them
   launch_h1_async(R, lists, counts, round_end, s);
-  return CR_OK;
+  return start_side();
 }
 
 // Copies the image descriptors and stencil tiles of ctx->prob into scratch.
@@ -554,8 +554,9 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     if (!ctx->side) HIP_TRY(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
     if (!ctx->fork_ev) HIP_TRY(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
     if (!ctx->join_ev) HIP_TRY(hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
+    // the fork event is recorded before the reduction (degree 0 needs only the
+    // sorted cells), the side work enqueued later, when fork_h0 is called
     fork_h0 = [&]() -> cr_status {
-      HIP_TRY(hipEventRecord(ctx->fork_ev, s));
       HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
       mark(ctx, EV_H0S, ctx->side);
       launch_h0(tu.grid, skeys, &cnt[C_DIM], d_imgs, L, vlink, at<uint64_t>(ctx, p.T0), neg, E, st, ctx->side);
@@ -636,6 +637,7 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     }
     uint32_t* lists[4] = {at<uint32_t>(ctx, p.list[0]), at<uint32_t>(ctx, p.list[1]), at<uint32_t>(ctx, p.list[2]),
                           at<uint32_t>(ctx, p.list[3])};
+    if (side_h0) HIP_TRY(hipEventRecord(ctx->fork_ev, s));
     cr_status rrc = run_rounds(ctx, R, lists, &cnt[C_LIST], s, fork_h0);
     if (rrc != CR_OK) return rrc;
     launch_h1_emit(tu.grid, R, E, s);

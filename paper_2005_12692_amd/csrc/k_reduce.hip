@@ -1849,10 +1849,14 @@ __global__ void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t, cons
                              unsigned long long* __restrict__ n_clear) {
   if (aborted(R.st)) return;
   if (in_tail(R, n_t, first)) {  // nothing proposed; the counts stay for the tail
-    if (blockIdx.x == 0 && threadIdx.x == 0 && R.st->tail_round == 0) R.st->tail_round = R.round + 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && R.st->tail_round == 0) {
+      R.st->tail_round = R.round + 1;
+      *R.async_base = *R.arena_top;
+    }
     return;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *R.async_base = *R.arena_top;  // the tail's, should it start after this round
     n_clear[0] = 0;
     n_clear[1] = 0;
     R.work[0] = 0;
@@ -1894,9 +1898,6 @@ struct AsyncOps : GroupOps {
   __device__ static uint32_t wave_yield(const RedCtx&) { return 0u; }
   __device__ static bool fresh(const RedCtx&, uint32_t off) { return off >= async_base_lds; }
 };
-
-// The arena offset where the tail starts.
-__global__ void k_red_async_base(RedCtx R) { *R.async_base = *R.arena_top; }
 
 // R must stay the first parameter (see cold()).
 __global__ __launch_bounds__(64 * GNW) void k_red_async(RedCtx R, const uint32_t* __restrict__ l0,
@@ -2135,7 +2136,6 @@ void launch_h1_async(const RedCtx& R, uint32_t* lists[4], unsigned long long* co
     (void)hipFuncSetAttribute((const void*)k_red_async, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds);
     glds_set = glds;
   }
-  k_red_async_base<<<1, 1, 0, s>>>(R);
   k_red_async<<<ncu, 64 * GNW, glds, s>>>(R, lists[0], lists[1], lists[2], lists[3], counts, (uint32_t)round_end,
                                           gcap);
 }
