@@ -220,8 +220,9 @@ uint64_t noalloc_arena(const Problem& pb) {
 }
 
 // counters block: surv_count, dim_count[4], cand_count, arena_top, lists[4], wave work counter,
-// arena offset at the start of the asynchronous tail
-enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* six words */, C_WORK = 13, C_BASE = 14, C_WORDS = 15 };
+// arena offset at the start of the asynchronous tail, columns in the first round's spatial order
+enum { C_SURV = 0, C_DIM = 1, C_CAND = 5, C_ARENA = 6, C_LIST = 7 /* six words */, C_WORK = 13, C_BASE = 14, C_SPATIAL = 15,
+       C_WORDS = 16 };
 
 // A 1D signal lies on one line of the grid (Sec. 2): it runs as a 1 x n image,
 // with the 2D launch parameters.
@@ -637,6 +638,16 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
     }
     uint32_t* lists[4] = {at<uint32_t>(ctx, p.list[0]), at<uint32_t>(ctx, p.list[1]), at<uint32_t>(ctx, p.list[2]),
                           at<uint32_t>(ctx, p.list[3])};
+    // the first round's columns in spatial order: their keys sorted by (image,
+    // Khalimsky index) in the two halves of T, free once degree 2 is done
+    // (256^3 volume: the first round 3.35 -> 2.82 ms for ~0.25 ms of keys and
+    // four sort passes; CR_SPATIAL=0 keeps rank order)
+    if (env_u64("CR_SPATIAL", 1)) {
+      const uint64_t half = (pb.P + pb.nimg + 64) / 2;
+      launch_h1_spatial_keys(tu.grid, R, T, half, &cnt[C_SPATIAL], s);
+      R.spatial = launch_sort(T, T + half, &cnt[C_SPATIAL], half, L.ib + L.kb, hist, s);
+      R.n_spatial = &cnt[C_SPATIAL];
+    }
     if (side_h0) HIP_TRY(hipEventRecord(ctx->fork_ev, s));
     cr_status rrc = run_rounds(ctx, R, lists, &cnt[C_LIST], s, fork_h0);
     if (rrc != CR_OK) return rrc;

@@ -369,13 +369,15 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
                                                    unsigned long long* __restrict__ n_long_next) {
   if (aborted(R.st) || in_tail(R, n_list, first)) return;
   const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
-  const uint64_t n = first ? R.dim_count[2] : *n_list;
+  // the first round takes the columns in the spatial order when it was built
+  const uint64_t nsp = first && R.spatial ? *R.n_spatial : 0;
+  const uint64_t n = first ? (nsp ? nsp : R.dim_count[2]) : *n_list;
   if (n == 0 || (!first && n <= R.wave_short)) return;
   unsigned long long adds = 0;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     if (aborted(R.st)) break;
-    const uint32_t c = first ? (uint32_t)i : list[i];
-    if (first && R.cleared[c]) continue;
+    const uint32_t c = first ? (nsp ? (uint32_t)(R.spatial[i] >> 32) : (uint32_t)i) : list[i];
+    if (first && !nsp && R.cleared[c]) continue;
     reduce_round_reg<TC>(R, c, first != 0, off2, short_next, n_short_next, long_next, n_long_next, &adds);
   }
   if (adds) atomicAdd(&R.st->adds, adds);
@@ -1801,6 +1803,7 @@ __device__ inline void commit_range(const RedCtx& R, uint32_t round, const uint3
                                     uint64_t stride, uint32_t* next_t, uint32_t* next_b,
                                     unsigned long long* __restrict__ n_next) {
   const uint64_t nr = (nt + nb + 63) & ~63ull;
+  const bool sp = first && R.spatial && *R.n_spatial;  // then nt is the spatial count
   for (uint64_t i = i0; i < nr; i += stride) {
     bool again_short = false, again_long = false;
     uint32_t again = 0;
@@ -1808,8 +1811,8 @@ __device__ inline void commit_range(const RedCtx& R, uint32_t round, const uint3
       uint32_t c;
       bool skip = false;
       if (i < nt) {
-        c = first ? (uint32_t)i : list_t[i];
-        skip = first && R.cleared[c];
+        c = first ? (sp ? (uint32_t)(R.spatial[i] >> 32) : (uint32_t)i) : list_t[i];
+        skip = first && !sp && R.cleared[c];
       } else {
         c = list_b[i - nt];
       }
@@ -1861,7 +1864,7 @@ __global__ void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t, cons
     n_clear[1] = 0;
     R.work[0] = 0;
   }
-  const uint64_t nt = first ? R.dim_count[2] : *n_t;
+  const uint64_t nt = first ? (R.spatial && *R.n_spatial ? *R.n_spatial : R.dim_count[2]) : *n_t;
   const uint64_t nb = first ? 0 : *n_b;
   commit_range(R, R.round, list_t, nt, list_b, nb, first, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x,
                (uint64_t)gridDim.x * blockDim.x, next_t, next_b, n_next);
@@ -2064,6 +2067,8 @@ RedCtx make_redctx(const float* img, const ImgDesc* imgs, Layout L, const uint64
   R.round = 0;
   R.async_max = 0;
   R.async_base = nullptr;
+  R.spatial = nullptr;
+  R.n_spatial = nullptr;
   return R;
 }
 
@@ -2138,6 +2143,42 @@ void launch_h1_async(const RedCtx& R, uint32_t* lists[4], unsigned long long* co
   }
   k_red_async<<<ncu, 64 * GNW, glds, s>>>(R, lists[0], lists[1], lists[2], lists[3], counts, (uint32_t)round_end,
                                           gcap);
+}
+
+// The first round's spatial order: threads that reduce squares next to each
+// other in the grid read the same cache lines of pixels, partner codes and
+// owner words, where in rank order (by value) they read scattered ones.
+__global__ void k_red_spatial_keys(RedCtx R, uint64_t* __restrict__ out, uint64_t cap,
+                                   unsigned long long* __restrict__ n_out) {
+  if (aborted(R.st)) return;
+  const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
+  const uint64_t n2 = R.dim_count[2];
+  if (n2 > cap || R.L.ib + R.L.kb > 32) return;
+  const uint64_t nr = (n2 + 63) & ~63ull;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nr; i += (uint64_t)gridDim.x * blockDim.x) {
+    const bool live = i < n2 && !R.cleared[i];
+    uint64_t key = 0;
+    if (live) {
+      const uint64_t k = R.skeys[off2 + i];
+      key = (i << 32) | ((uint64_t)skey_img(R.L, k) << R.L.kb) | skey_kidx(R.L, k);
+    }
+    const uint64_t mask = __ballot(live);
+    if (!mask) continue;
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(n_out, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (live) {
+      const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+      out[base + __popcll(mask & lt)] = key;
+    }
+  }
+}
+
+void launch_h1_spatial_keys(int grid, const RedCtx& R, uint64_t* out, uint64_t cap, unsigned long long* n_out,
+                            hipStream_t s) {
+  k_red_spatial_keys<<<grid, 256, 0, s>>>(R, out, cap, n_out);
 }
 
 void launch_h1_emit(int grid, const RedCtx& R, const EmitCtx& E, hipStream_t s) {
