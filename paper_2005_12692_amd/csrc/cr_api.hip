@@ -640,7 +640,7 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
                           at<uint32_t>(ctx, p.list[3])};
     // the first round's columns in spatial order: their keys sorted by (image,
     // Khalimsky index) in the two halves of T, free once degree 2 is done
-    // (256^3 volume: the first round 3.35 -> 2.82 ms for ~0.25 ms of keys and
+    // (256^3 volume: the first round 3.35 -> 2.82 ms for ~0.2 ms of keys and
     // four sort passes; CR_SPATIAL=0 keeps rank order)
     if (env_u64("CR_SPATIAL", 1)) {
       const uint64_t half = (pb.P + pb.nimg + 64) / 2;

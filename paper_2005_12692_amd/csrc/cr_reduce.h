@@ -46,8 +46,9 @@ struct RedCtx {
   unsigned long long* async_base;  // arena offset at the start of the tail (lists from there on
                                    // were written during it)
   const uint64_t* spatial;         // the first round's columns in the order of their squares in the
-  const unsigned long long* n_spatial;  // grid (column << 32 | image and index), and their count;
-                                        // count 0 (or no array): rank order
+  const unsigned long long* n_spatial;  // grid (column << 32 | image and index; cleared ones last,
+                                        // their field all ones) and their count; count 0 (or no
+                                        // array): rank order
 };
 
 // Proposal word of column c in round r: the round in the high half (a later
@@ -83,10 +84,11 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
 // after the last one enqueued) -- reduced to its end without round barriers.
 void launch_h1_async(const RedCtx& R, uint32_t* lists[4], unsigned long long* counts, int round_end, hipStream_t s);
 void launch_h1_emit(int grid, const RedCtx& R, const EmitCtx& E, hipStream_t s);
-// Keys (column << 32 | image << kb | Khalimsky index) of the columns that are not
-// cleared, appended to out (count n_out, which must be 0), unless there are more
-// than cap squares or the image and index fields exceed 32 bits (then nothing is
-// written).  Sorted by their low 32 bits they give the first round a spatial order.
+// Keys (column << 32 | image << kb | Khalimsky index) of every column, at
+// out[column] (a cleared column's low field all ones), and n_out = their number,
+// or 0 when there are more than cap squares or the image and index fields
+// exceed 32 bits.  Sorted by their low 32 bits they give the first round a
+// spatial order.
 void launch_h1_spatial_keys(int grid, const RedCtx& R, uint64_t* out, uint64_t cap, unsigned long long* n_out,
                             hipStream_t s);
 

@@ -348,6 +348,11 @@ __device__ void reduce_round_reg(const RedCtx& R, uint32_t c, bool first, uint64
   }
 }
 
+// Whether a key of the spatial order is a cleared column's.
+__device__ __forceinline__ bool spatial_none(const RedCtx& R, uint64_t key) {
+  return (key & 0xFFFFFFFFull) == (1ull << (R.L.ib + R.L.kb)) - 1;
+}
+
 // Whether a round's kernels leave its columns to the asynchronous tail: a
 // round after the first with at most async_max columns (its commit records it
 // in st->tail_round), and every round after that one.  ct: the round's counts.
@@ -376,7 +381,9 @@ __global__ __launch_bounds__(256) void k_red_round(RedCtx R, const uint32_t* __r
   unsigned long long adds = 0;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     if (aborted(R.st)) break;
-    const uint32_t c = first ? (nsp ? (uint32_t)(R.spatial[i] >> 32) : (uint32_t)i) : list[i];
+    const uint64_t sk = nsp ? R.spatial[i] : 0;
+    if (nsp && spatial_none(R, sk)) continue;  // cleared (they sort last)
+    const uint32_t c = first ? (nsp ? (uint32_t)(sk >> 32) : (uint32_t)i) : list[i];
     if (first && !nsp && R.cleared[c]) continue;
     reduce_round_reg<TC>(R, c, first != 0, off2, short_next, n_short_next, long_next, n_long_next, &adds);
   }
@@ -1795,62 +1802,32 @@ __device__ inline int64_t pivot_slot(const RedCtx& R, uint64_t e) {
   return edge_slot(d, ec);
 }
 
-// The commit of the listed columns [i0, nt + nb) with stride `stride` (whole
-// wavefronts): the leftmost proposer of each pivot in round `round` becomes its
-// owner; losers and displaced owners are appended to the next round's lists.
-__device__ inline void commit_range(const RedCtx& R, uint32_t round, const uint32_t* __restrict__ list_t, uint64_t nt,
-                                    const uint32_t* __restrict__ list_b, uint64_t nb, int first, uint64_t i0,
-                                    uint64_t stride, uint32_t* next_t, uint32_t* next_b,
-                                    unsigned long long* __restrict__ n_next) {
-  const uint64_t nr = (nt + nb + 63) & ~63ull;
-  const bool sp = first && R.spatial && *R.n_spatial;  // then nt is the spatial count
-  for (uint64_t i = i0; i < nr; i += stride) {
-    bool again_short = false, again_long = false;
-    uint32_t again = 0;
-    if (i < nt + nb) {
-      uint32_t c;
-      bool skip = false;
-      if (i < nt) {
-        c = first ? (sp ? (uint32_t)(R.spatial[i] >> 32) : (uint32_t)i) : list_t[i];
-        skip = first && !sp && R.cleared[c];
-      } else {
-        c = list_b[i - nt];
-      }
-      const uint64_t e = skip ? YIELDED : R.piv[c];
-      if (e != YIELDED) {
-        const int64_t slot = pivot_slot(R, e);
-        bool push = true;
-        if (R.claim[slot] == claim_word(round, c)) {
-          const uint64_t old = R.owner[slot];
-          R.owner[slot] = ((uint64_t)c << 32) | R.col_ptr[c];
-          push = old != NO_OWNER;
-          again = (uint32_t)(old >> 32);
-        } else {
-          again = c;
-        }
-        if (push) {
-          const bool lng = R.arena[R.col_ptr[again]] > R.long_len;
-          again_long = lng;
-          again_short = !lng;
-        }
-      }
-    }
-    wave_push(next_t, n_next, again_short, again);
-    wave_push(next_b, n_next + 1, again_long, again);
-  }
-}
-
 // Commit: the leftmost proposer of each pivot becomes its owner; losers and
 // displaced owners go to the next round's lists (long stored columns to the
 // wave-mode list).  Yielded columns were already listed.
 // It also clears the counts the round after next will fill (nobody reads them
 // during this round) and the wave-mode column counter, so that no separate
 // launch is needed for them.
-__global__ void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t, const unsigned long long* __restrict__ n_t,
-                             const uint32_t* __restrict__ list_b, const unsigned long long* __restrict__ n_b,
-                             int first, uint32_t* next_t, uint32_t* next_b, unsigned long long* __restrict__ n_next,
-                             unsigned long long* __restrict__ n_clear) {
-  if (aborted(R.st)) return;
+// A workgroup collects what it appends in LDS and reserves room in a list with
+// one atomic per COMMIT_BUF entries: one atomic per wavefront on the two shared
+// counts serialised the first round's commit (~1.2 ms of 6.2M columns).
+constexpr int COMMIT_TPB = 256;    // threads per workgroup of the commit
+constexpr int COMMIT_BUF = 2048;   // entries of each LDS list buffer
+__global__ __launch_bounds__(COMMIT_TPB) void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t,
+                                                          const unsigned long long* __restrict__ n_t,
+                                                          const uint32_t* __restrict__ list_b,
+                                                          const unsigned long long* __restrict__ n_b, int first,
+                                                          uint32_t* next_t, uint32_t* next_b,
+                                                          unsigned long long* __restrict__ n_next,
+                                                          unsigned long long* __restrict__ n_clear) {
+  __shared__ uint32_t buf[2][COMMIT_BUF];
+  __shared__ uint32_t cnt[2];
+  __shared__ unsigned long long base[2];
+  __shared__ uint32_t stop;
+  // one reading of the abort flag for the whole workgroup (it has barriers)
+  if (threadIdx.x == 0) stop = aborted(R.st) ? 1u : 0u;
+  __syncthreads();
+  if (stop) return;
   if (in_tail(R, n_t, first)) {  // nothing proposed; the counts stay for the tail
     if (blockIdx.x == 0 && threadIdx.x == 0 && R.st->tail_round == 0) {
       R.st->tail_round = R.round + 1;
@@ -1864,10 +1841,59 @@ __global__ void k_red_commit(RedCtx R, const uint32_t* __restrict__ list_t, cons
     n_clear[1] = 0;
     R.work[0] = 0;
   }
-  const uint64_t nt = first ? (R.spatial && *R.n_spatial ? *R.n_spatial : R.dim_count[2]) : *n_t;
+  const bool sp = first && R.spatial && *R.n_spatial;  // then the spatial order is listed
+  const uint64_t nt = first ? (sp ? *R.n_spatial : R.dim_count[2]) : *n_t;
   const uint64_t nb = first ? 0 : *n_b;
-  commit_range(R, R.round, list_t, nt, list_b, nb, first, blockIdx.x * (uint64_t)blockDim.x + threadIdx.x,
-               (uint64_t)gridDim.x * blockDim.x, next_t, next_b, n_next);
+  if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * COMMIT_TPB;
+  const uint64_t nr = (nt + nb + COMMIT_TPB - 1) / COMMIT_TPB * COMMIT_TPB;  // the same passes for a whole workgroup
+  uint32_t* next[2] = {next_t, next_b};
+  for (uint64_t i0 = (uint64_t)blockIdx.x * COMMIT_TPB; i0 < nr; i0 += stride) {
+    const uint64_t i = i0 + threadIdx.x;
+    if (i < nt + nb) {
+      uint32_t c;
+      bool skip = false;
+      if (i < nt) {
+        const uint64_t sk = sp ? R.spatial[i] : 0;
+        c = first ? (sp ? (uint32_t)(sk >> 32) : (uint32_t)i) : list_t[i];
+        skip = first && (sp ? spatial_none(R, sk) : R.cleared[c] != 0);
+      } else {
+        c = list_b[i - nt];
+      }
+      const uint64_t e = skip ? YIELDED : R.piv[c];
+      if (e != YIELDED) {
+        const int64_t slot = pivot_slot(R, e);
+        bool push = true;
+        uint32_t again = c;
+        if (R.claim[slot] == claim_word(R.round, c)) {
+          const uint64_t old = R.owner[slot];
+          R.owner[slot] = ((uint64_t)c << 32) | R.col_ptr[c];
+          push = old != NO_OWNER;
+          again = (uint32_t)(old >> 32);
+        }
+        if (push) {
+          const int b = R.arena[R.col_ptr[again]] > R.long_len ? 1 : 0;
+          buf[b][atomicAdd(&cnt[b], 1u)] = again;
+        }
+      }
+    }
+    __syncthreads();
+    // empty a buffer that the next pass could overflow, and both after the last
+    const bool last = i0 + stride >= nr;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const uint32_t k = cnt[b];
+      if (k + COMMIT_TPB > (uint32_t)COMMIT_BUF || (last && k)) {
+        if (threadIdx.x == 0) base[b] = atomicAdd(&n_next[b], (unsigned long long)k);
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < k; j += COMMIT_TPB) next[b][base[b] + j] = buf[b][j];
+        __syncthreads();
+        if (threadIdx.x == 0) cnt[b] = 0;
+        __syncthreads();
+      }
+    }
+  }
 }
 
 // ---- the asynchronous tail -------------------------------------------------------
@@ -2126,7 +2152,8 @@ void launch_h1_rounds(int grid, const RedCtx& R, uint32_t* lists[4], unsigned lo
       k_red_round_wave<WideCfg><<<wgrid, 64 * WPB, lds, s>>>(Rr, lt, ct, lb, ct + 1, R.front_cap);
       k_red_round_group<<<ncu, 64 * GNW, glds, s>>>(Rr, lt, ct, lb, ct + 1, gcap);
     }
-    k_red_commit<<<grid, 256, 0, s>>>(Rr, lt, ct, lb, ct + 1, first, lists[2 * nxt], lists[2 * nxt + 1], cnx, cclr);
+    k_red_commit<<<grid, COMMIT_TPB, 0, s>>>(Rr, lt, ct, lb, ct + 1, first, lists[2 * nxt], lists[2 * nxt + 1], cnx,
+                                             cclr);
   }
 }
 
@@ -2148,33 +2175,28 @@ void launch_h1_async(const RedCtx& R, uint32_t* lists[4], unsigned long long* co
 // The first round's spatial order: threads that reduce squares next to each
 // other in the grid read the same cache lines of pixels, partner codes and
 // owner words, where in rank order (by value) they read scattered ones.
+// One key per column, in place (no compaction: a shared counter would serialise
+// the wavefronts); a cleared column gets the all-ones field, which no square
+// has (a Khalimsky index is below 2^kb - 1), so it sorts last and is skipped.
 __global__ void k_red_spatial_keys(RedCtx R, uint64_t* __restrict__ out, uint64_t cap,
                                    unsigned long long* __restrict__ n_out) {
   if (aborted(R.st)) return;
   const uint64_t off2 = R.dim_count[0] + R.dim_count[1];
   const uint64_t n2 = R.dim_count[2];
-  if (n2 > cap || R.L.ib + R.L.kb > 32) return;
-  const uint64_t nr = (n2 + 63) & ~63ull;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nr; i += (uint64_t)gridDim.x * blockDim.x) {
-    const bool live = i < n2 && !R.cleared[i];
-    uint64_t key = 0;
-    if (live) {
+  const bool fits = n2 <= cap && R.L.ib + R.L.kb <= 32;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = fits ? n2 : 0;
+  if (!fits) return;
+  const uint64_t none = (1ull << (R.L.ib + R.L.kb)) - 1;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n2; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t f = none;
+    if (!R.cleared[i]) {
       const uint64_t k = R.skeys[off2 + i];
-      key = (i << 32) | ((uint64_t)skey_img(R.L, k) << R.L.kb) | skey_kidx(R.L, k);
+      f = ((uint64_t)skey_img(R.L, k) << R.L.kb) | skey_kidx(R.L, k);
     }
-    const uint64_t mask = __ballot(live);
-    if (!mask) continue;
-    const int lane = __lane_id();
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(n_out, (unsigned long long)__popcll(mask));
-    base = __shfl(base, leader, 64);
-    if (live) {
-      const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-      out[base + __popcll(mask & lt)] = key;
-    }
+    out[i] = (i << 32) | f;
   }
 }
+
 
 void launch_h1_spatial_keys(int grid, const RedCtx& R, uint64_t* out, uint64_t cap, unsigned long long* n_out,
                             hipStream_t s) {
