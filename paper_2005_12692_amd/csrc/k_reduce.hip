@@ -588,15 +588,26 @@ __device__ __forceinline__ uint32_t w_excl_small(uint32_t v, uint32_t* total) {
   return pre;
 }
 
+// Pointers with an explicit address space.  In code compiled out of line the
+// compiler cannot see where a pointer came from and accesses it with flat
+// instructions, which are slower to LDS and count against both the LDS and the
+// vector memory counters (a wait for an LDS value then also waits for every
+// global load in flight); the merges below take their LDS and arena operands
+// through these instead.
+using lds64 = __attribute__((address_space(3))) uint64_t;
+using glb64 = __attribute__((address_space(1))) uint64_t;
+__device__ __forceinline__ lds64* to_lds(const uint64_t* p) { return (lds64*)(uint64_t*)p; }
+__device__ __forceinline__ glb64* to_glb(const uint64_t* p) { return (glb64*)(uint64_t*)p; }
+
 // A sorted list seen through an index map: a plain LDS array, or a window of
-// a ring of N slots (key i of the window is ring slot (base + i) mod N).
+// a ring of N slots in LDS (key i of the window is ring slot (base + i) mod N).
 struct Lin {
-  const uint64_t* p;
+  const lds64* p;
   __device__ __forceinline__ uint64_t operator[](uint32_t i) const { return p[i]; }
 };
 template <uint32_t N>
 struct RingN {
-  const uint64_t* p;
+  const lds64* p;
   uint32_t base;
   __device__ __forceinline__ uint64_t operator[](uint32_t i) const { return p[(base + i) & (N - 1)]; }
 };
@@ -623,9 +634,9 @@ __device__ __forceinline__ uint32_t mp_split(const AA& A, uint32_t na, const BB&
 struct SegResult {
   uint32_t written, ka, kb;
 };
-template <int P, class AA, class BB>
+template <int P, class AA, class BB, class O>
 __device__ __forceinline__ SegResult w_merge_seg(const AA& A, uint32_t na, const BB& B, uint32_t nb,
-                                                 uint32_t d, uint64_t* out, int lane) {
+                                                 uint32_t d, O* out, int lane) {
   const uint32_t dend = (uint32_t)(lane + 1) * P < d ? (uint32_t)(lane + 1) * P : d;
   const uint32_t ie = mp_split(A, na, B, nb, dend);
   uint32_t je = dend - ie;
@@ -675,8 +686,11 @@ __device__ __forceinline__ SegResult w_merge_seg(const AA& A, uint32_t na, const
 // out = A XOR B for sorted lists in LDS; out (LDS) distinct from both.  Out of
 // line (like the global merge) to keep the per-iteration code compact.
 template <int P>
-__device__ __noinline__ uint32_t w_xor_lds(const uint64_t* A, uint32_t na, const uint64_t* B, uint32_t nb,
-                                           uint64_t* out, int lane) {
+__device__ __noinline__ uint32_t w_xor_lds(const uint64_t* A_, uint32_t na, const uint64_t* B_, uint32_t nb,
+                                           uint64_t* out_, int lane) {
+  const lds64* A = to_lds(A_);
+  const lds64* B = to_lds(B_);
+  lds64* out = to_lds(out_);
   uint32_t ia = 0, ib = 0, o = 0;
   while (ia < na || ib < nb) {
     const uint32_t rem = (na - ia) + (nb - ib);
@@ -690,14 +704,22 @@ __device__ __noinline__ uint32_t w_xor_lds(const uint64_t* A, uint32_t na, const
   return o;
 }
 
-// out (arena) = T XOR F, T in the arena, F in LDS.  T is read through a ring
+// out = T XOR F, T in the arena, F in LDS, out in the arena (OUT_LDS false) or
+// in LDS (OUT_LDS true: an owner column merged into the front list).  T is read through a ring
 // of RING chunks in the stage: the chunks holding the next CHUNK keys are
 // resident, and the chunk after them is loaded into registers during each
 // merge step and stored into the ring when it is needed, so the load latency
 // overlaps the merging.
-template <class C>
-__device__ __noinline__ uint32_t w_merge_tail(uint64_t* X, const uint64_t* T, uint32_t nt, const uint64_t* F,
-                                              uint32_t nf, uint64_t* out, int lane) {
+template <class C, bool OUT_LDS>
+__device__ __noinline__ uint32_t w_merge_tail(uint64_t* X_, const uint64_t* T_, uint32_t nt, const uint64_t* F_,
+                                              uint32_t nf, uint64_t* out_, int lane) {
+  lds64* X = to_lds(X_);
+  const glb64* T = to_glb(T_);
+  const lds64* F = to_lds(F_);
+  auto out = [&] {
+    if constexpr (OUT_LDS) return to_lds(out_);
+    else return to_glb(out_);
+  }();
   constexpr int PER = C::PER;
   constexpr uint32_t CHUNK = C::CHUNK, RING = C::RING;
   const uint32_t nch = (nt + CHUNK - 1) / CHUNK;
@@ -710,7 +732,7 @@ __device__ __noinline__ uint32_t w_merge_tail(uint64_t* X, const uint64_t* T, ui
     }
   };
   auto store_chunk = [&](uint32_t c) {
-    uint64_t* slot = X + (c % RING) * CHUNK;
+    lds64* slot = X + (c % RING) * CHUNK;
 #pragma unroll
     for (int j = 0; j < PER; ++j) slot[j * 64 + lane] = pre[j];
   };
@@ -747,25 +769,28 @@ __device__ __noinline__ uint32_t w_merge_tail(uint64_t* X, const uint64_t* T, ui
 // out (arena) = A XOR B, both in the arena: as w_merge_tail, with the stage
 // split into one ring per input and chunks of half the size.
 template <class C>
-__device__ __noinline__ uint32_t w_merge_gg(uint64_t* X, const uint64_t* A, uint32_t na, const uint64_t* B,
-                                            uint32_t nb, uint64_t* out, int lane) {
+__device__ __noinline__ uint32_t w_merge_gg(uint64_t* X_, const uint64_t* A_, uint32_t na, const uint64_t* B_,
+                                            uint32_t nb, uint64_t* out_, int lane) {
+  const glb64* A = to_glb(A_);
+  const glb64* B = to_glb(B_);
+  glb64* out = to_glb(out_);
   constexpr uint32_t RING = C::RING;
   constexpr uint32_t HN = C::XN / 2;       // words of each ring
   constexpr uint32_t HCH = HN / RING;      // keys per chunk
   constexpr int HP = (int)(HCH / 64);      // merge positions per lane per step
-  uint64_t* XA = X;
-  uint64_t* XB = X + HN;
+  lds64* XA = to_lds(X_);
+  lds64* XB = XA + HN;
   const uint32_t nca = (na + HCH - 1) / HCH, ncb = (nb + HCH - 1) / HCH;
   uint64_t pa[HP], pb[HP];
-  auto load = [&](const uint64_t* src, uint32_t n, uint32_t nch, uint32_t c, uint64_t* pre) {
+  auto load = [&](const glb64* src, uint32_t n, uint32_t nch, uint32_t c, uint64_t* pre) {
 #pragma unroll
     for (int j = 0; j < HP; ++j) {
       const uint32_t i = c * HCH + (uint32_t)(j * 64 + lane);
       pre[j] = (c < nch && i < n) ? src[i] : 0ull;
     }
   };
-  auto store = [&](uint64_t* ring, uint32_t c, const uint64_t* pre) {
-    uint64_t* slot = ring + (c % RING) * HCH;
+  auto store = [&](lds64* ring, uint32_t c, const uint64_t* pre) {
+    lds64* slot = ring + (c % RING) * HCH;
 #pragma unroll
     for (int j = 0; j < HP; ++j) slot[j * 64 + lane] = pre[j];
   };
@@ -874,7 +899,7 @@ __device__ __forceinline__ bool w_push_front(const RedCtx& R, const WaveBufs& S,
   if (W.U.n + W.nf > cold(R)->mid_cap && !w_fold_mid<C>(R, S, W, lane)) return false;
   const uint64_t off = w_alloc(R, (uint64_t)W.U.n + W.nf, lane);
   if (off == ~0ull) return false;
-  const uint32_t len = uni(w_merge_tail<C>(S.X, W.U.v, W.U.n, fbuf(S, W.cur), W.nf, R.arena + off, lane));
+  const uint32_t len = uni(w_merge_tail<C, false>(S.X, W.U.v, W.U.n, fbuf(S, W.cur), W.nf, R.arena + off, lane));
   w_count(W.merged, W.U.n + W.nf, lane);
   W.nf = 0;
   tail_set(W.U, R.arena + off, len, lane);
@@ -914,7 +939,7 @@ __device__ __forceinline__ bool w_owner_add(const RedCtx& R, const WaveBufs& S, 
   }
   if (W.nf + m > S.cap && !w_push_front<C>(R, S, W, lane)) return false;
   w_count(W.merged, W.nf + m, lane);
-  W.nf = uni(w_merge_tail<C>(S.X, Q, m, fbuf(S, W.cur), W.nf, fbuf(S, W.cur ^ 1), lane));
+  W.nf = uni(w_merge_tail<C, true>(S.X, Q, m, fbuf(S, W.cur), W.nf, fbuf(S, W.cur ^ 1), lane));
   W.cur ^= 1;
   return true;
 }
@@ -1019,7 +1044,7 @@ struct WaveOps {
   }
   __device__ static uint32_t merge_tail(const WaveBufs& S, const uint64_t* T, uint32_t nt, const uint64_t* F,
                                         uint32_t nf, uint64_t* out, int lane) {
-    return uni(w_merge_tail<C>(S.X, T, nt, F, nf, out, lane));
+    return uni(w_merge_tail<C, false>(S.X, T, nt, F, nf, out, lane));  // out: the arena
   }
   __device__ static uint32_t merge_gg(const WaveBufs& S, const uint64_t* A, uint32_t na, const uint64_t* B,
                                       uint32_t nb, uint64_t* out, int lane) {
@@ -1434,8 +1459,8 @@ __device__ __forceinline__ uint32_t g_split(const AA& A, uint32_t na, const BB& 
 template <int P>
 struct GRing {
   static constexpr uint32_t CH = GNW * 64 * P;
-  uint64_t* slots;
-  const uint64_t* src;
+  lds64* slots;
+  const glb64* src;
   uint32_t n, nch, next;
   uint64_t pre[P];
   __device__ __forceinline__ uint64_t operator[](uint32_t i) const { return slots[i & (4 * CH - 1)]; }
@@ -1451,8 +1476,8 @@ struct GRing {
     for (int j = 0; j < P; ++j) slots[(c % 4) * CH + (uint32_t)j * (GNW * 64) + threadIdx.x] = pre[j];
   }
   __device__ __forceinline__ void init(uint64_t* sl, const uint64_t* s, uint32_t len) {
-    slots = sl;
-    src = s;
+    slots = to_lds(sl);
+    src = to_glb(s);
     n = len;
     nch = (len + CH - 1) / CH;
     load(0);
@@ -1473,16 +1498,17 @@ struct GRing {
   }
 };
 struct GLds {
-  const uint64_t* p;
+  const lds64* p;
   __device__ __forceinline__ uint64_t operator[](uint32_t i) const { return p[i]; }
 };
+using lds_gs = __attribute__((address_space(3))) GroupShared;
 
 // out = A XOR B by the whole workgroup, in steps of GNW * 64 * P positions;
 // pre(ia, ib) runs at the start of each step (the keys of A and B consumed so
 // far) to make what the step reads resident.  Returns the number written.
-template <int P, class AA, class BB, class Pre>
-__device__ __forceinline__ uint32_t g_merge(const AA& A, uint32_t na, const BB& B, uint32_t nb, uint64_t* out,
-                                            GroupShared* G, int lane, Pre pre) {
+template <int P, class AA, class BB, class O, class Pre>
+__device__ __forceinline__ uint32_t g_merge(const AA& A, uint32_t na, const BB& B, uint32_t nb, O* out, lds_gs* G,
+                                            int lane, Pre pre) {
   constexpr uint32_t D = GNW * 64 * P;
   const uint32_t wv = threadIdx.x >> 6;
   const uint32_t total = na + nb;
@@ -1565,26 +1591,28 @@ __device__ __forceinline__ uint32_t g_merge(const AA& A, uint32_t na, const BB& 
 // Runs operation d with the whole workgroup; returns the keys written.
 __device__ __noinline__ uint32_t g_run(const WaveBufs& S, uint32_t op, uint32_t na, uint32_t nb, uint64_t a,
                                        uint64_t b, uint64_t out, int lane) {
-  GroupShared* G = gshared(S);
-  uint64_t* L = S.F0;  // the start of the group's LDS
+  lds_gs* G = (lds_gs*)gshared(S);
+  lds64* L = to_lds(S.F0);  // the start of the group's LDS
   if (op == G_MERGE_LDS) {
     return g_merge<GP_LDS>(GLds{L + a}, na, GLds{L + b}, nb, L + out, G, lane, [](uint32_t, uint32_t) {});
   }
   if (op == G_MERGE_TAIL || op == G_MERGE_TAIL_LDS) {  // the output in the arena, or in LDS
     GRing<GP_TAIL> ra;
     ra.init(S.X, reinterpret_cast<const uint64_t*>(a), na);
-    return g_merge<GP_TAIL>(ra, na, GLds{L + b}, nb,
-                            op == G_MERGE_TAIL ? reinterpret_cast<uint64_t*>(out) : L + out, G, lane,
-                            [&](uint32_t ia, uint32_t) { ra.advance(ia); });
+    auto adv = [&](uint32_t ia, uint32_t) { ra.advance(ia); };
+    if (op == G_MERGE_TAIL)
+      return g_merge<GP_TAIL>(ra, na, GLds{L + b}, nb, to_glb(reinterpret_cast<uint64_t*>(out)), G, lane, adv);
+    return g_merge<GP_TAIL>(ra, na, GLds{L + b}, nb, L + out, G, lane, adv);
   }
   if (op == G_MERGE_GG) {
     GRing<GP_GG> ra, rb;
     ra.init(S.X, reinterpret_cast<const uint64_t*>(a), na);
     rb.init(S.X + GXN / 2, reinterpret_cast<const uint64_t*>(b), nb);
-    return g_merge<GP_GG>(ra, na, rb, nb, reinterpret_cast<uint64_t*>(out), G, lane, [&](uint32_t ia, uint32_t ib) {
-      ra.advance(ia);
-      rb.advance(ib);
-    });
+    return g_merge<GP_GG>(ra, na, rb, nb, to_glb(reinterpret_cast<uint64_t*>(out)), G, lane,
+                          [&](uint32_t ia, uint32_t ib) {
+                            ra.advance(ia);
+                            rb.advance(ib);
+                          });
   }
   if (op == G_FENCE) {  // every wavefront's global stores have reached the L2 (vmcnt(0))
     __builtin_amdgcn_s_waitcnt(0xF70);
@@ -1592,10 +1620,10 @@ __device__ __noinline__ uint32_t g_run(const WaveBufs& S, uint32_t op, uint32_t 
     return 0;
   }
   if (op == G_COPY_IN) {
-    const uint64_t* src = reinterpret_cast<const uint64_t*>(a);
+    const glb64* src = to_glb(reinterpret_cast<const uint64_t*>(a));
     for (uint32_t i = threadIdx.x; i < na; i += GNW * 64) L[out + i] = src[i];
   } else {  // G_COPY_OUT
-    uint64_t* dst = reinterpret_cast<uint64_t*>(out);
+    glb64* dst = to_glb(reinterpret_cast<uint64_t*>(out));
     for (uint32_t i = threadIdx.x; i < na; i += GNW * 64) dst[i] = L[a + i];
   }
   __syncthreads();
