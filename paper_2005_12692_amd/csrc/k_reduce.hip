@@ -25,7 +25,8 @@
 // proposer the owner; a column that loses, and an owner that was displaced,
 // stay active for the next round.  Every addition adds a column to its left, so
 // the rounds end in a reduced matrix with the unique pivots of the sequential
-// reduction.
+// reduction.  Once few columns are left, the asynchronous tail (below) reduces
+// them to the end without rounds, claiming pivots by compare-and-swap.
 //
 // Short columns are reduced one per thread; a column that grows long, or needs
 // many additions, continues in wave mode (one wavefront per column).  Stored
