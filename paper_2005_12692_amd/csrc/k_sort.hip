@@ -24,7 +24,8 @@ constexpr int ST = 256;               // threads of a pass workgroup
 constexpr int SKEYS = 16;             // keys per thread per tile
 constexpr int STILE = ST * SKEYS;     // keys per tile
 constexpr int SWAVES = ST / 64;
-constexpr int SGRID = 1024;           // persistent workgroups of a pass
+constexpr int SGRID = 1024;           // persistent workgroups of a scatter pass (four per CU: its LDS)
+constexpr int CGRID = 2048;           // ... of a count pass (small LDS: eight per CU)
 constexpr int SBT = 64;               // tiles per block of the count scan
 
 __device__ __forceinline__ uint64_t n_keys(const unsigned long long* n_ptr, uint64_t cap) {
@@ -72,10 +73,15 @@ __device__ __forceinline__ void rank_tile(SortLds& S, const uint64_t* __restrict
 }
 
 // Per tile and digit: the number of keys, counts[tile * 256 + d].
+// Its LDS is the per-wavefront counts only (4 KiB, not the scatter's tile), so
+// that more workgroups share a CU and more loads are in flight.
 __global__ __launch_bounds__(ST) void k_sort_count(const uint64_t* __restrict__ in,
                                                    const unsigned long long* __restrict__ n_ptr, uint64_t cap,
                                                    int shift, uint32_t* __restrict__ counts) {
-  __shared__ SortLds S;
+  struct CountLds {
+    uint32_t cnt[SWAVES][256];
+  };
+  __shared__ CountLds S;
   const int tid = threadIdx.x;
   const uint64_t n = n_keys(n_ptr, cap);
   const uint64_t ntiles = (n + STILE - 1) / STILE;
@@ -244,11 +250,12 @@ uint64_t* launch_sort(uint64_t* keys, uint64_t* tmp, const unsigned long long* n
   uint32_t* bsum = bucket + 256;
   uint32_t* counts = bsum + 256 * (max_blocks + 1);
   const int grid = (int)(max_tiles < (uint64_t)SGRID ? (max_tiles ? max_tiles : 1) : (uint64_t)SGRID);
+  const int cgrid = (int)(max_tiles < (uint64_t)CGRID ? (max_tiles ? max_tiles : 1) : (uint64_t)CGRID);
   const int bgrid = (int)(max_blocks ? max_blocks : 1);
   uint64_t* a = keys;
   uint64_t* b = tmp;
   for (int p = 0; p < passes; ++p) {
-    k_sort_count<<<grid, ST, 0, stream>>>(a, n_ptr, cap, 8 * p, counts);
+    k_sort_count<<<cgrid, ST, 0, stream>>>(a, n_ptr, cap, 8 * p, counts);
     k_sort_scan_block<<<bgrid, 256, 0, stream>>>(counts, n_ptr, cap, bsum);
     k_sort_scan_top<<<1, 256, 0, stream>>>(bsum, n_ptr, cap, bucket);
     k_sort_scatter<<<grid, ST, 0, stream>>>(a, b, n_ptr, cap, 8 * p, counts, bsum, bucket);

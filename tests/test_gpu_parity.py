@@ -207,6 +207,21 @@ def test_wave_mode_forced(setting):
             os.environ.pop(k, None)
 
 
+def test_first_round_in_rank_order(monkeypatch):
+    """The first round of the degree-1 reduction takes its columns in spatial
+    order by default; with CR_SPATIAL=0 it takes them in rank order (the
+    commit of the first round too): both give the oracle's diagram, with the
+    asynchronous tail off and on."""
+    cases = [(synth.blobs3d(40, 3), "blobs 40"), (synth.grf_seeded((30, 26, 34), 1.5, 6), "grf"),
+             (np.random.default_rng(9).integers(0, 4, size=(12, 13, 11)).astype(np.float32), "ties")]
+    for spatial in ("0", "1"):
+        for tail in ("0", "4096"):
+            monkeypatch.setenv("CR_SPATIAL", spatial)
+            monkeypatch.setenv("CR_ASYNC_MAX", tail)
+            for img, label in cases:
+                check(img, label=f"{label} spatial {spatial} tail {tail}")
+
+
 _MODE_VOLUMES = {}
 
 
