@@ -35,6 +35,8 @@
 // > 0) of its apparent partner square, 0xFF if none.
 #include "cr_internal.h"
 
+#include <cstdlib>
+
 namespace cr {
 
 constexpr uint32_t NONE = 0xFFFFFFFFu;  // key of a cell outside the image (above every value key)
@@ -159,15 +161,31 @@ struct StencilLds {
   uint32_t wcnt[RW];
   uint32_t woff[RW];
   unsigned long long wbase;
+  unsigned long long sbase[2];  // 3D: array offsets reserved for the two staging buffers
 };
+
+// 3D: survivor keys of a plane are staged in LDS (dynamic, two buffers of
+// stage_keys<RW>() keys) and written out one plane later.
+template <int RW>
+constexpr uint32_t stage_keys() { return 256u * RW; }
+
+// Inclusive prefix sum over lanes 0..15 (each row of 16 lanes on its own).
+__device__ __forceinline__ uint32_t row_scan16(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);  // row_shr:8
+  return x;
+}
 
 template <int NDIM, int RW, int ZC>
 __global__ __launch_bounds__(64 * RW) void k_stencil(
     const float* __restrict__ img, const ImgDesc* __restrict__ imgs, const int4* __restrict__ tiles,
     Layout L, uint64_t* __restrict__ surv, uint64_t surv_cap,
     unsigned long long* __restrict__ surv_count, int32_t* __restrict__ vlink, int32_t* __restrict__ tlink,
-    uint8_t* __restrict__ eapp, uint32_t* __restrict__ img_status, Status* __restrict__ st) {
+    uint8_t* __restrict__ eapp, uint32_t* __restrict__ img_status, Status* __restrict__ st, uint32_t stage_cap) {
   __shared__ StencilLds<RW> S;
+  extern __shared__ uint64_t stg[];  // 3D: 2 x stage_keys<RW>() staged survivor keys
   constexpr int TOP = NDIM == 3 ? 7 : 3;  // type of the top cell
   const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
   const int4 tile = tiles[blockIdx.x];
@@ -328,6 +346,84 @@ __global__ __launch_bounds__(64 * RW) void k_stencil(
     }
   };
 
+  // 3D form of flush: the survivors of a plane go to an LDS staging buffer,
+  // and thread 0 issues the workgroup's reservation without waiting for it;
+  // the next call (or drain) copies them out, coalesced, once the reservation
+  // has returned.  So no wavefront waits on the atomic's round trip, where
+  // flush holds the whole workgroup at a barrier for it on every plane.  A
+  // plane with more survivors than a buffer holds is written as in flush.
+  constexpr uint32_t STG = stage_keys<RW>();  // stage_cap <= STG keys are staged
+  unsigned long long res = 0;  // thread 0: the reservation of the staged plane
+  uint32_t prev = 0;           // keys staged by the previous call (0: none)
+  uint32_t pb = 0;             // staging buffer of this call
+  auto copy_out = [&](uint32_t b) {  // after a barrier that follows the write of S.sbase[b]
+    const unsigned long long base = S.sbase[b];
+    const uint64_t* src = stg + (size_t)b * STG;
+    for (uint32_t i = threadIdx.x; i < prev; i += 64 * RW)
+      if (base + i < surv_cap) surv[base + i] = src[i];
+  };
+  auto publish = [&]() {  // thread 0, before a barrier: the previous call's reservation
+    if (threadIdx.x == 0 && prev) {
+      S.sbase[pb ^ 1u] = res;
+      if (res + prev > surv_cap) raise_flag(st, &st->overflow, OVF_SURVIVORS);  // what fits is kept
+    }
+  };
+  auto flush_staged = [&](int zc, const Rec& R, uint32_t mask) {
+    const uint32_t cnt = (uint32_t)__popc(mask);
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int bit = 0; bit < 4; ++bit) {
+      const uint64_t bm = __ballot((cnt >> bit) & 1u);
+      pre += __builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u)) << bit;
+      tot += (uint32_t)__popcll(bm) << bit;
+    }
+    if (lane == 0) S.wcnt[row] = tot;
+    publish();
+    __syncthreads();
+    if (prev) copy_out(pb ^ 1u);
+    // the wavefronts' offsets within the plane and its total, by every wavefront
+    static_assert(RW <= 16, "one DPP row holds the wavefront counts");
+    const uint32_t incl = row_scan16(lane < RW ? S.wcnt[lane] : 0u);
+    const uint32_t run = (uint32_t)__builtin_amdgcn_readlane((int)incl, RW - 1);
+    const uint32_t woff = row ? (uint32_t)__builtin_amdgcn_readlane((int)incl, row - 1) : 0u;
+    const uint32_t kbase = ((uint32_t)(2 * zc) * K1 + (uint32_t)(2 * y)) * K2 + (uint32_t)(2 * x);
+    if (run > stage_cap) {  // too many to stage: reserve now and write them straight out
+      if (threadIdx.x == 0) {
+        const unsigned long long base = atomicAdd(surv_count, (unsigned long long)run);
+        if (base + run > surv_cap) raise_flag(st, &st->overflow, OVF_SURVIVORS);
+        S.wbase = base;
+      }
+      __syncthreads();
+      unsigned long long pos = S.wbase + woff + pre;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if ((mask >> (3 * t)) & 1u) {
+          const uint32_t kidx = kbase + ((t & 4) ? K1 * K2 : 0u) + ((t & 2) ? K2 : 0u) + (uint32_t)(t & 1);
+          if (pos < surv_cap) surv[pos] = make_skey(L, popc3(t), im, R.v[t], kidx);
+          ++pos;
+        }
+      }
+      prev = 0;
+      return;
+    }
+    if (threadIdx.x == 0 && run) res = atomicAdd(surv_count, (unsigned long long)run);  // read by the next call
+    uint64_t* dst = stg + (size_t)pb * STG + woff + pre;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if ((mask >> (3 * t)) & 1u) {
+        const uint32_t kidx = kbase + ((t & 4) ? K1 * K2 : 0u) + ((t & 2) ? K2 : 0u) + (uint32_t)(t & 1);
+        *dst++ = make_skey(L, popc3(t), im, R.v[t], kidx);
+      }
+    }
+    prev = run;
+    pb ^= 1u;
+  };
+  auto drain = [&]() {  // the last staged plane
+    publish();
+    __syncthreads();
+    if (prev) copy_out(pb ^ 1u);
+  };
+
   if constexpr (NDIM == 2) {
     uint32_t f, fy;
     load_plane(0, &f, &fy);
@@ -390,8 +486,9 @@ __global__ __launch_bounds__(64 * RW) void k_stencil(
       Fcm = Fc;
       Ec = E;
       Fc = F;
-      flush(kk - 1, Rm, mask);  // also the barrier before the next step's record exchange
+      flush_staged(kk - 1, Rm, mask);  // also the barrier before the next step's record exchange
     }
+    drain();
   }
   if (__ballot(nan) && lane == 0) {
     atomicOr(&img_status[im], 1u);
@@ -403,8 +500,21 @@ template <int NDIM, int RW, int ZC>
 void launch_stencil_t(int ntiles, const float* img, const ImgDesc* imgs, const int4* tiles, Layout L,
                       uint64_t* surv, uint64_t surv_cap, unsigned long long* surv_count, int32_t* vlink,
                       int32_t* tlink, uint8_t* eapp, uint32_t* img_status, Status* st, hipStream_t stream) {
-  k_stencil<NDIM, RW, ZC><<<ntiles, 64 * RW, 0, stream>>>(img, imgs, tiles, L, surv, surv_cap, surv_count, vlink,
-                                                          tlink, eapp, img_status, st);
+  // CR_STAGE_KEYS lowers the staging capacity (0: every plane is written straight out)
+  uint32_t stage_cap = stage_keys<RW>();
+  if (const char* v = getenv("CR_STAGE_KEYS")) {
+    const unsigned long c = strtoul(v, nullptr, 10);
+    if (c < stage_cap) stage_cap = (uint32_t)c;
+  }
+  const size_t dyn = NDIM == 3 ? 2 * stage_keys<RW>() * sizeof(uint64_t) : 0;
+  static bool attr_set = false;
+  if (dyn && !attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_stencil<NDIM, RW, ZC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)dyn);
+    attr_set = true;
+  }
+  k_stencil<NDIM, RW, ZC><<<ntiles, 64 * RW, dyn, stream>>>(img, imgs, tiles, L, surv, surv_cap, surv_count, vlink,
+                                                            tlink, eapp, img_status, st, stage_cap);
 }
 
 // Tile shapes: RW wavefronts (RW-2 interior rows of 62 pixels) and ZC planes.

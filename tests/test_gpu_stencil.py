@@ -36,3 +36,27 @@ def test_survivors_per_dimension(label, img):
     got = cr.stats()["survivors"]
     want = survivors_per_dim(img if img.ndim > 1 else img[None])
     assert got == want, f"{label}: GPU survivors per dimension {got}, apparent pairs leave {want}"
+
+
+@pytest.mark.parametrize("stage", ["0", "100", "700"])
+def test_survivor_staging(monkeypatch, stage):
+    """In a volume the stencil stages each plane's survivor keys in LDS and
+    writes them out one plane later; a plane with more survivors than the
+    staging holds is written straight out.  With the capacity lowered
+    (CR_STAGE_KEYS: 0 writes every plane straight out, 100 and 700 mix the two
+    ways from plane to plane) the survivor counts and the whole diagram still
+    equal the apparent-pair count and the oracle's diagram."""
+    import oracle
+    monkeypatch.setenv("CR_STAGE_KEYS", stage)
+    rng = np.random.default_rng(43)
+    for label, img in [("blobs 3D", synth.blobs3d(50, 6)),
+                       ("ties 3D", rng.integers(0, 5, (35, 30, 129)).astype(np.float32)),
+                       ("uniform 3D", rng.random((33, 40, 70), dtype=np.float32))]:
+        d = cr.persistence(torch.from_numpy(np.ascontiguousarray(img)).cuda())
+        assert cr.stats()["survivors"] == survivors_per_dim(img), f"{label} stage {stage}: survivor counts"
+        o = oracle.persistence(img)
+        for name, g, w in zip(("dim", "birth", "death", "birth_pixel", "death_pixel"), d,
+                              (o.dim, o.birth, o.death, o.birth_pixel, o.death_pixel)):
+            g = g.cpu().numpy()
+            assert g.shape == w.shape and np.array_equal(g.view(np.uint8), w.view(np.uint8)), \
+                f"{label} stage {stage}: field {name} differs from the oracle"
