@@ -389,9 +389,10 @@ constexpr int ROUND_BUDGET = 128;
 constexpr int YIELD_ROUNDS = 64;
 constexpr int ROUND_LIMIT = 4096;
 
-// side_start, if given, is called once after the first SIDE_AFTER rounds have
-// been enqueued (or right after the tail when the rounds end sooner), to start
-// work beside the latency-bound later rounds and the tail.
+// side_start, if given, is called once the first SIDE_AFTER rounds have been
+// enqueued and checked not to be the last (or right after the tail when the
+// rounds end sooner), to start work beside the latency-bound later rounds and
+// the tail.
 constexpr int SIDE_AFTER = 20;
 
 cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsigned long long* counts,
@@ -419,10 +420,28 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
     side_started = true;
     return side_start();
   };
+  // Batch k's read-back is enqueued only once batch k-1's has been checked, so
+  // that the tail, when that check ends the loop, follows the rounds directly:
+  // behind a read-back it would wait for the copy, whose kernel finds no free
+  // slot while the side stream's degree-0 merge fills the GPU (~0.85 ms on the
+  // 256^3 volume).
   int round_end = ROUND_LIMIT;
   for (int k = 0; k * ROUND_BATCH < ROUND_LIMIT; ++k) {
     const int r = k * ROUND_BATCH;
     launch_h1_rounds(RGRID, R, lists, counts, r, ROUND_BATCH, ROUND_LIMIT, s);
+    if (k > 0) {
+      HIP_TRY(hipEventSynchronize(ctx->round_ev[(k - 1) & 1]));
+      const char* prev = ctx->host_stage + 32 * ((k - 1) & 1);
+      unsigned long long left[2] = {0, 0};
+      uint32_t ab[2] = {0, 0};
+      std::memcpy(left, prev, 16);
+      std::memcpy(ab, prev + 16, 8);
+      ctx->rounds = r;
+      if ((left[0] == 0 && left[1] == 0) || ab[0] || ab[1]) {
+        round_end = r + ROUND_BATCH;
+        break;
+      }
+    }
     if (r + ROUND_BATCH >= SIDE_AFTER) {
       rc = start_side();
       if (rc != CR_OK) return rc;
@@ -433,18 +452,6 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
     static_assert(offsetof(Status, tail_round) == offsetof(Status, abort) + 4, "abort and tail_round are adjacent");
     HIP_TRY(hipMemcpyAsync(slot + 16, &R.st->abort, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(ctx->round_ev[k & 1], s));
-    if (k == 0) continue;
-    HIP_TRY(hipEventSynchronize(ctx->round_ev[(k - 1) & 1]));
-    const char* prev = ctx->host_stage + 32 * ((k - 1) & 1);
-    unsigned long long left[2] = {0, 0};
-    uint32_t ab[2] = {0, 0};
-    std::memcpy(left, prev, 16);
-    std::memcpy(ab, prev + 16, 8);
-    ctx->rounds = r;
-    if ((left[0] == 0 && left[1] == 0) || ab[0] || ab[1]) {
-      round_end = r + ROUND_BATCH;
-      break;
-    }
   }
   // the tail first: its workgroups (one per CU) are dispatched before the side
   // stream's degree-0 kernels, which fill the remaining wave slots beside them
