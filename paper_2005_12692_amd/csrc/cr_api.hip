@@ -437,7 +437,11 @@ cr_status run_rounds(cr_context* ctx, const RedCtx& R, uint32_t* lists[4], unsig
       std::memcpy(left, prev, 16);
       std::memcpy(ab, prev + 16, 8);
       ctx->rounds = r;
-      if ((left[0] == 0 && left[1] == 0) || ab[0] || ab[1]) {
+      // also once at most twice the tail's threshold is left: the batch just
+      // enqueued reaches the threshold (or the tail takes the lists its last
+      // round builds), and another batch would run as empty rounds
+      const uint64_t n_left = left[0] + left[1];
+      if (n_left == 0 || ab[0] || ab[1] || (R.async_max && n_left <= 2ull * R.async_max)) {
         round_end = r + ROUND_BATCH;
         break;
       }
