@@ -106,7 +106,8 @@ typedef struct cr_diagram {
  * 256^3 volume; the GPU is never left idle by them), until a round has at most
  * 4096 columns (256 in a call of 8 or more volumes; CR_ASYNC_MAX in the
  * environment overrides it, 0 = never); the columns left are then reduced in
- * one launch without rounds (the asynchronous tail).  If the reduction's
+ * one launch without rounds (the asynchronous tail), enqueued right behind the
+ * batch running when the count read shows at most twice that many.  If the reduction's
  * column arena (the stored columns) overflows, the whole pipeline is rerun with
  * a larger arena, at most three times (cr_stats.arena_reruns counts reruns);
  * CR_ARENA_ENTRIES in the environment fixes the first attempt's arena.
