@@ -48,6 +48,8 @@ void launch_lifetime(const int32_t* dim, const float* birth, const float* death,
 void launch_pixel_coords(const int64_t* pixel, int64_t n, int64_t base, const int64_t ext[3], int32_t* xyz,
                          uint32_t* bad, hipStream_t s);
 bool stencil_tile(int ndim, int variant, int ext[3]);
+void stencil_tile_row1(int ext[3]);
+constexpr int ROW1_VARIANT = 3;  // the stencil's one-row layout (see launch_apparent)
 
 }  // namespace cr
 
@@ -118,6 +120,7 @@ struct Problem {
   std::vector<ImgDesc> imgs;
   std::vector<int4> tiles;
   uint64_t P = 0, N = 0;  // totals over the batch
+  int tile = 0;           // stencil tile variant of the call (ROW1_VARIANT: every image one row)
   Layout L{};
 };
 
@@ -244,6 +247,12 @@ cr_status build_problem(Problem& pb, int nimg, const int64_t* pixel_offsets, con
   uint64_t maxN = 1, maxP = 1;
   int tile[3];
   if (!stencil_tile(pb.ndim, tile_variant, tile)) return fail(CR_ERR_INVALID_ARGUMENT, "bad stencil tile variant");
+  // images of one row (1D signals) take the one-row layout: a workgroup's
+  // wavefronts lie side by side along the row, not on rows outside the image
+  bool row1 = pb.ndim == 2;
+  for (int i = 0; i < nimg && row1; ++i) row1 = ndim == 1 || shapes[(int64_t)i * ndim] == 1;
+  pb.tile = row1 ? ROW1_VARIANT : tile_variant;
+  if (row1) stencil_tile_row1(tile);
   for (int i = 0; i < nimg; ++i) {
     int64_t n[3] = {1, 1, 1};
     for (int a = 0; a < ndim; ++a) {
@@ -528,7 +537,7 @@ cr_status enqueue_pipeline(cr_context* ctx, const float* image, hipStream_t s, u
   mark(ctx, EV_START, s);
   uint8_t* eapp = (pb.ndim == 3 && pb.maxdim >= 1) ? at<uint8_t>(ctx, p.eapp) : nullptr;
   const cr_tuning& tu = ctx->tune[pb.ndim];
-  launch_apparent(pb.ndim, tu.tile, (int)pb.tiles.size(), image, d_imgs, d_tiles, L, surv, p.surv_cap, &cnt[C_SURV],
+  launch_apparent(pb.ndim, pb.tile, (int)pb.tiles.size(), image, d_imgs, d_tiles, L, surv, p.surv_cap, &cnt[C_SURV],
                   vlink, tlink, eapp, img_status, st, s);
   mark(ctx, EV_STENCIL, s);
   void* hist = at<char>(ctx, p.hist);

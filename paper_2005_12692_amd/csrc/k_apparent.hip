@@ -178,7 +178,10 @@ __device__ __forceinline__ uint32_t row_scan16(uint32_t x) {
   return x;
 }
 
-template <int NDIM, int RW, int ZC>
+// ROW1 (images of one row, as 1D signals run): wavefront w takes pixels
+// x0 - 1 + 62 w .. of that row instead of row y0 - 1 + w, and every neighbour
+// across y is outside the image.
+template <int NDIM, int RW, int ZC, bool ROW1 = false>
 __global__ __launch_bounds__(64 * RW) void k_stencil(
     const float* __restrict__ img, const ImgDesc* __restrict__ imgs, const int4* __restrict__ tiles,
     Layout L, uint64_t* __restrict__ surv, uint64_t surv_cap,
@@ -193,10 +196,10 @@ __global__ __launch_bounds__(64 * RW) void k_stencil(
   const ImgDesc d = imgs[im];
   const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
   const int z0 = tile.y, y0 = tile.z, x0 = tile.w;
-  const int x = x0 - 1 + lane, y = y0 - 1 + row;
+  const int x = x0 - 1 + lane + (ROW1 ? 62 * row : 0), y = ROW1 ? y0 : y0 - 1 + row;
   const bool xin = x >= 0 && x < n2, x1in = x + 1 >= 0 && x + 1 < n2;
   const bool yin = y >= 0 && y < n1, y1in = y + 1 >= 0 && y + 1 < n1;
-  const bool inner = lane >= 1 && lane <= 62 && row >= 1 && row <= RW - 2 && xin && yin;
+  const bool inner = lane >= 1 && lane <= 62 && (ROW1 || (row >= 1 && row <= RW - 2)) && xin && yin;
   const uint32_t K1 = (uint32_t)d.K[1], K2 = (uint32_t)d.K[2];
   const int64_t rowpix = (int64_t)n1 * n2;
   bool nan = false;
@@ -226,8 +229,8 @@ __global__ __launch_bounds__(64 * RW) void k_stencil(
     S.recB[row][lane] = make_uint4(R0.v[2], R0.v[3], R0.v[6], R0.v[7]);
     __syncthreads();
     Rec ym, yp, xm, xp;
-    const uint4 b = row > 0 ? S.recB[row - 1][lane] : make_uint4(NONE, NONE, NONE, NONE);
-    const uint4 a = row < RW - 1 ? S.recA[row + 1][lane] : make_uint4(NONE, NONE, NONE, NONE);
+    const uint4 b = !ROW1 && row > 0 ? S.recB[row - 1][lane] : make_uint4(NONE, NONE, NONE, NONE);
+    const uint4 a = !ROW1 && row < RW - 1 ? S.recA[row + 1][lane] : make_uint4(NONE, NONE, NONE, NONE);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       ym.v[t] = NONE;
@@ -437,8 +440,8 @@ __global__ __launch_bounds__(64 * RW) void k_stencil(
     codes_of_plane(R0, Rn, Rn, &E, &F);
     S.cw[0][row][lane] = make_uint2(E, F);
     __syncthreads();
-    const uint32_t Fmy = row > 0 ? S.cw[0][row - 1][lane].y : NO_CODES;
-    const uint32_t Epy = row < RW - 1 ? S.cw[0][row + 1][lane].x : NO_CODES;
+    const uint32_t Fmy = !ROW1 && row > 0 ? S.cw[0][row - 1][lane].y : NO_CODES;
+    const uint32_t Epy = !ROW1 && row < RW - 1 ? S.cw[0][row + 1][lane].x : NO_CODES;
     const uint32_t Fmx = lane_up1(F), Epx = lane_down1(E);
     uint32_t mask = 0;
     if (inner) mask = classify(0, R0, E, F, NO_CODES, Fmy, Fmx, NO_CODES, Epy, Epx);
@@ -496,7 +499,7 @@ __global__ __launch_bounds__(64 * RW) void k_stencil(
   }
 }
 
-template <int NDIM, int RW, int ZC>
+template <int NDIM, int RW, int ZC, bool ROW1 = false>
 void launch_stencil_t(int ntiles, const float* img, const ImgDesc* imgs, const int4* tiles, Layout L,
                       uint64_t* surv, uint64_t surv_cap, unsigned long long* surv_count, int32_t* vlink,
                       int32_t* tlink, uint8_t* eapp, uint32_t* img_status, Status* st, hipStream_t stream) {
@@ -509,13 +512,15 @@ void launch_stencil_t(int ntiles, const float* img, const ImgDesc* imgs, const i
   const size_t dyn = NDIM == 3 ? 2 * stage_keys<RW>() * sizeof(uint64_t) : 0;
   static bool attr_set = false;
   if (dyn && !attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_stencil<NDIM, RW, ZC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_stencil<NDIM, RW, ZC, ROW1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)dyn);
     attr_set = true;
   }
-  k_stencil<NDIM, RW, ZC><<<ntiles, 64 * RW, dyn, stream>>>(img, imgs, tiles, L, surv, surv_cap, surv_count, vlink,
+  k_stencil<NDIM, RW, ZC, ROW1><<<ntiles, 64 * RW, dyn, stream>>>(img, imgs, tiles, L, surv, surv_cap, surv_count, vlink,
                                                             tlink, eapp, img_status, st, stage_cap);
 }
+
+constexpr int ROW1_VARIANT = 3;  // the one-row layout (not a tuning choice)
 
 // Tile shapes: RW wavefronts (RW-2 interior rows of 62 pixels) and ZC planes.
 struct TileVariant {
@@ -531,7 +536,10 @@ void launch_apparent(int ndim, int variant, int ntiles, const float* img, const 
   if (ntiles <= 0) return;
 #define CR_STENCIL(N, R, Z) \
   launch_stencil_t<N, R, Z>(ntiles, img, imgs, tiles, L, surv, surv_cap, surv_count, vlink, tlink, eapp, img_status, st, stream)
-  if (ndim == 2) {
+  if (ndim == 2 && variant == ROW1_VARIANT) {
+    launch_stencil_t<2, 16, 1, true>(ntiles, img, imgs, tiles, L, surv, surv_cap, surv_count, vlink, tlink, eapp,
+                                     img_status, st, stream);
+  } else if (ndim == 2) {
     if (variant == 1) CR_STENCIL(2, 8, 1);
     else if (variant == 2) CR_STENCIL(2, 4, 1);
     else CR_STENCIL(2, 16, 1);
@@ -541,6 +549,15 @@ void launch_apparent(int ndim, int variant, int ntiles, const float* img, const 
     else CR_STENCIL(3, 16, 32);
   }
 #undef CR_STENCIL
+}
+
+// Extents (z, y, x) of the interior of a tile of the one-row layout (variant
+// ROW1_VARIANT of ndim 2, chosen by the library for calls whose images all have
+// one row).
+void stencil_tile_row1(int ext[3]) {
+  ext[0] = 1;
+  ext[1] = 1;
+  ext[2] = 62 * 16;
 }
 
 // Extents (z, y, x) of the interior of stencil tile `variant` for ndim; false if there is no such variant.
