@@ -275,7 +275,9 @@ cr_status cr_get_stage_times(cr_context* ctx, float* ms, int capacity, int* n_st
 /* Launch parameters of one ndim.  They change speed only: every setting gives
  * the same diagrams. */
 typedef struct cr_tuning {
-  int32_t tile;         /* stencil tile shape, 0 .. cr_tile_variants(ndim)-1 (see cr_tile_shape) */
+  int32_t tile;         /* stencil tile shape, 0 .. cr_tile_variants(ndim)-1 (see cr_tile_shape);
+                           a call whose images all have one row (1D signals) uses a one-row
+                           layout of its own instead */
   int32_t grid;         /* workgroups of the grid-stride kernels (union-find, output), 64 .. 65536 */
   int32_t long_len;     /* degree-1 reduction of a volume: a stored column longer than this
                            continues one per wavefront instead of one per thread (values
