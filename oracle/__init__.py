@@ -13,6 +13,10 @@ standard reduction behind the paper's pivot pairing, Sec. 2 of Kaji-Sudo-Ahara,
 * ``mode="plain"``: all columns reduced left to right;
   ``mode="twist"``: dimension by dimension from the top, with clearing (Sec. 2,
   "reduced to zero without computation");
+  ``mode="cohomology"``: the paper's own formulation (Sec. 2), the coboundary
+  matrix in reverse order, each cell paired with the earliest cofacet its
+  reduced column ends on; a second reduction algorithm that must give the same
+  pairs (duality of persistent homology and cohomology);
 * output: pairs with death > birth and essential bars (death = +inf,
   death_pixel = -1), each with the flat index of the pixel whose value the birth
   (death) cell takes, in canonical order (dim, birth_pixel, death_pixel), an
@@ -144,7 +148,7 @@ def persistence(img, maxdim: int | None = None, mode: str = "twist",
     shape = (ctypes.c_int64 * a.ndim)(*a.shape)
     handle = ctypes.c_void_p()
     code = lib.oracle_run(a.ctypes.data, a.ndim, shape, int(maxdim),
-                          {"plain": 0, "twist": 1}[mode], ctypes.byref(handle))
+                          {"plain": 0, "twist": 1, "cohomology": 2}[mode], ctypes.byref(handle))
     if code != 0:
         raise OracleError(code)
     try:

@@ -35,6 +35,15 @@
  *    every pivot row before its dimension is reduced ("many columns are known
  *    to be reduced to zero without computation", Sec. 2).  Both give the same
  *    pairing because the pairing of a reduced matrix is unique.
+ *    Mode ORACLE_COHOMOLOGY is the paper's own formulation (Sec. 2): the
+ *    coboundary matrix, columns and rows in reverse key order.  The column of
+ *    a cell lists its cofacets; its pivot is the cofacet earliest in key order.
+ *    Columns of dimension 0..maxdim are reduced from the latest cell to the
+ *    earliest by additions of the columns already reduced.  A nonzero reduced
+ *    column pairs its cell (birth) with its pivot (death).  By the duality of
+ *    persistent homology and cohomology over a field (from the work the paper
+ *    cites for the algorithm), for the same total order the pairs are those of
+ *    the homology reduction.  The two share no reduction code.
  *  - Output: the pairs with death > birth (zero-length pairs are dropped) plus
  *    the essential bars, in dimensions 0..maxdim, each with the flat index of
  *    the pixel whose value the birth (death) cell takes: among the vertices of
@@ -51,7 +60,7 @@
 
 enum { ORACLE_OK = 0, ORACLE_ERR_ARG = 1, ORACLE_ERR_NAN = 2, ORACLE_ERR_TOO_LARGE = 3,
        ORACLE_ERR_NOMEM = 5 };
-enum { ORACLE_PLAIN = 0, ORACLE_TWIST = 1 };
+enum { ORACLE_PLAIN = 0, ORACLE_TWIST = 1, ORACLE_COHOMOLOGY = 2 };
 
 typedef struct {
     int64_t n[3];   /* pixel extents, z y x */
@@ -171,7 +180,7 @@ int oracle_run(const float* img_in, int ndim, const int64_t* shape, int maxdim, 
     if (!out) return ORACLE_ERR_ARG;
     *out = NULL;
     if (!img_in || !shape || ndim < 1 || ndim > 3 || maxdim < 0) return ORACLE_ERR_ARG;
-    if (mode != ORACLE_PLAIN && mode != ORACLE_TWIST) return ORACLE_ERR_ARG;
+    if (mode != ORACLE_PLAIN && mode != ORACLE_TWIST && mode != ORACLE_COHOMOLOGY) return ORACLE_ERR_ARG;
 
     grid_t g;
     for (int a = 0; a < 3; ++a) g.n[a] = 1;
@@ -279,7 +288,65 @@ int oracle_run(const float* img_in, int ndim, const int64_t* shape, int maxdim, 
             }                                                                        \
         } while (0)
 
-    if (mode == ORACLE_PLAIN) {
+    if (mode == ORACLE_COHOMOLOGY) {
+        /* column of the cell at reversed rank q = N-1-rank: the reversed ranks
+           of its cofacets, ascending, so that its last entry is the cofacet
+           earliest in key order; owner[q'] = the reduced column whose last
+           entry is q' */
+        int32_t* owner = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+        col_t* Q = (col_t*)calloc((size_t)N, sizeof(col_t));
+        if (!owner || !Q) status = ORACLE_ERR_NOMEM;
+        for (int64_t i = 0; status == ORACLE_OK && i < N; ++i) owner[i] = -1;
+        for (int64_t q = 0; q < N && status == ORACLE_OK; ++q) {
+            const int64_t j = N - 1 - q;
+            int64_t c[3], f[3];
+            coords_of(&g, cell_at[j], c);
+            const int d = dim_of(c);
+            if (d > maxdim || d + 1 > top) continue;
+            int32_t tmp[6];
+            int m = 0;
+            for (int a = 0; a < 3; ++a) {
+                if (c[a] & 1) continue;  /* the cell extends along a: no cofacet that way */
+                for (int sg = -1; sg <= 1; sg += 2) {
+                    f[0] = c[0]; f[1] = c[1]; f[2] = c[2];
+                    f[a] += sg;
+                    if (f[a] < 0 || f[a] >= g.K[a]) continue;
+                    tmp[m++] = (int32_t)(N - 1 - rank[kidx_of(&g, f)]);
+                }
+            }
+            for (int p2 = 1; p2 < m; ++p2) {  /* insertion sort, ascending */
+                int32_t t = tmp[p2]; int r2 = p2 - 1;
+                while (r2 >= 0 && tmp[r2] > t) { tmp[r2 + 1] = tmp[r2]; --r2; }
+                tmp[r2 + 1] = t;
+            }
+            col_t cur;
+            cur.n = m;
+            cur.v = (int32_t*)malloc(sizeof(int32_t) * 6);
+            if (!cur.v) { status = ORACLE_ERR_NOMEM; break; }
+            memcpy(cur.v, tmp, sizeof(int32_t) * (size_t)m);
+            while (cur.n > 0) {
+                const int32_t low = cur.v[cur.n - 1];
+                const int32_t k = owner[low];
+                if (k < 0) break;
+                col_t nxt;
+                if (col_xor(&cur, &Q[k], &nxt) != 0) { status = ORACLE_ERR_NOMEM; break; }
+                free(cur.v);
+                cur = nxt;
+            }
+            if (status != ORACLE_OK) { free(cur.v); break; }
+            if (cur.n > 0) {
+                const int32_t low = cur.v[cur.n - 1];
+                owner[low] = (int32_t)q;
+                Q[q] = cur;
+                pivot_col[j] = (int32_t)(N - 1 - low);  /* birth rank j, death rank of the pivot */
+            } else {
+                free(cur.v);
+            }
+        }
+        if (Q) for (int64_t i = 0; i < N; ++i) free(Q[i].v);
+        free(Q);
+        free(owner);
+    } else if (mode == ORACLE_PLAIN) {
         for (int64_t j = 0; j < N && status == ORACLE_OK; ++j) {
             int64_t c[3];
             coords_of(&g, cell_at[j], c);

@@ -207,6 +207,19 @@ def test_wave_mode_forced(setting):
             os.environ.pop(k, None)
 
 
+def test_against_cohomology_oracle():
+    """The GPU reduces boundary columns (homology); the oracle's cohomology mode
+    reduces the coboundary matrix as the paper does (Sec. 2).  Different
+    algorithms, the same diagram: volumes, a 2D image and a 1D signal."""
+    rng = np.random.default_rng(31)
+    cases = [(synth.blobs3d(20, 5), "blobs 20"), (synth.grf_seeded((14, 13, 12), 1.5, 2), "grf"),
+             (rng.integers(0, 3, size=(9, 8, 10)).astype(np.float32), "ties 3D"),
+             (synth.uniform2d((40, 37), 6), "uniform 2D"), (synth.random_walk(300, 3), "signal")]
+    for img, label in cases:
+        o = oracle.persistence(img, mode="cohomology")
+        assert_same(gpu_diag(img), [o.dim, o.birth, o.death, o.birth_pixel, o.death_pixel], f"{label} (cohomology)")
+
+
 def test_first_round_in_rank_order(monkeypatch):
     """The first round of the degree-1 reduction takes its columns in spatial
     order by default; with CR_SPATIAL=0 it takes them in rank order (the
